@@ -1,0 +1,258 @@
+"""Throughput of the rasterizer's fwd+bwd hot path on one MI355X.
+
+Workload (default): 1,000,000 Gaussians (unit-sphere shell, SH degree 3,
+volume and SH-band masks) rendered into 8 views of mixed progressive-training
+resolutions (3x316x208, 3x632x416, 2x1264x832; 3.09 Mpix per step) in one
+batched, HIP-graph-captured step.  A step = projection, binning/sort,
+forward compositing, L2 loss gradient, backward (composite + projection).
+
+Prints ONE JSON line: batched Mpix/s (the value), the per-view path's Mpix/s
+and the batched-over-per-view speedup (with the agreement of the two paths),
+per-stage times, the roofline of the dominant kernel and the FP64 oracle's
+throughput on a bounded sample on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+PEAK_FP32_TFLOPS = 157.3   # MI355X published fp32 vector peak
+PEAK_HBM_GBS = 8000.0      # MI355X HBM3E
+# Algorithmic work per composited (pixel, splat) pair, counted from the
+# operations the method needs (see the kernel notes in the design document):
+FWD_FLOP_PER_PAIR = 24.0
+BWD_FLOP_PER_PAIR = 60.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", type=int, default=4, help="workload 1..5")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-per-view", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--tile", type=str, default=None, help="WxH tile override, e.g. 16x16")
+    ap.add_argument("--batch-depth", type=int, default=None)
+    ap.add_argument("--ppt", type=int, default=None)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target CPU work of the oracle sample")
+    return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2501_14534_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(f.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str, workload: str, src_hash: str):
+    """HBM bytes per launch from committed rocprofv3 --pmc summaries, if taken on this kernel source."""
+    p = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+        e = d.get(f"{kernel}@{workload}")
+        if e and e.get("source_hash") == src_hash:
+            return float(e["hbm_bytes_per_launch"])
+    except (ValueError, KeyError, TypeError):
+        return None
+    return None
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+    import dataclasses
+
+    import torch
+
+    from paper_2501_14534_amd import autotune, gs, raster, scenes
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    gs.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    wl = scenes.config(args.config)
+    opts = autotune.best_opts(wl)
+    if args.tile:
+        tw, th = (int(x) for x in args.tile.lower().split("x"))
+        opts = dataclasses.replace(opts, tile_w=tw, tile_h=th)
+    if args.batch_depth:
+        opts = dataclasses.replace(opts, batch_depth=args.batch_depth)
+    if args.ppt:
+        opts = dataclasses.replace(opts, pixels_per_thread=args.ppt)
+    sc = wl.scene
+    V = len(wl.cams)
+    pixels = wl.pixels
+    params = raster.to_device(sc)
+    target = torch.from_numpy(np.concatenate([t.reshape(-1) for t in wl.targets])).to(dev)
+
+    def make(cams, tgt):
+        r = raster.Rasterizer(sc.n, sc.sh_degree, cams, opts, mask_eps=sc.mask_eps, sh_mask_eps=sc.sh_mask_eps)
+        return raster.Step(r, params, tgt, graph=not args.no_graph, loss_views=V)
+
+    # ---------------- batched path (all views in one call per stage) ----------------
+    step = make(wl.cams, target)
+    step.run()  # sizes the binning capacity (host check), captures the graph
+    for _ in range(args.warmup):
+        step.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step.launch()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    assert not step.rast.overflowed()
+    ms = (t1 - t0) * 1e3 / args.steps
+    value = pixels * args.steps / (t1 - t0) / 1e6
+
+    # ---------------- per-view path (one call per stage per view) ----------------
+    per_view = None
+    if not args.no_per_view and V > 1:
+        offs = np.cumsum([0] + [3 * c.pixels for c in wl.cams])
+        pv = [make([c], target[offs[i]:offs[i + 1]]) for i, c in enumerate(wl.cams)]
+        for s in pv:
+            s.run()
+        for _ in range(args.warmup):
+            for s in pv:
+                s.launch()
+        torch.cuda.synchronize()
+        p0 = time.perf_counter()
+        for _ in range(args.steps):
+            for s in pv:
+                s.launch()
+        torch.cuda.synchronize()
+        p1 = time.perf_counter()
+        # agreement: batched image == per-view images; gradients summed over views
+        step.launch()
+        torch.cuda.synchronize()
+        img_b = step.rast.image
+        img_p = torch.cat([s.rast.image for s in pv])
+        img_err = float((img_b - img_p).abs().max())
+        g_err = 0.0
+        for k, gb in step.grads.items():
+            gp = sum(s.grads[k] for s in pv)
+            rms = float(gp.pow(2).mean().sqrt())
+            tol = torch.clamp(gp.abs(), min=1e-2 * rms)
+            g_err = max(g_err, float(((gb - gp).abs() / tol).max()) if gb.numel() else 0.0)
+        per_view = dict(mpix_s=pixels * args.steps / (p1 - p0) / 1e6, ms_per_step=(p1 - p0) * 1e3 / args.steps,
+                        speedup=(p1 - p0) / (t1 - t0), image_max_abs_diff=img_err, grad_max_rel_diff=g_err,
+                        agree_1e5=bool(img_err <= 1e-5 and g_err <= 1e-5))
+        del pv
+        torch.cuda.empty_cache()
+
+    # ---------------- stage timing with HIP events on the launch stream ----------------
+    r = step.rast
+    stream = torch.cuda.current_stream()
+    names = ["project", "bin_sort", "render_fwd", "blend_bwd", "project_bwd"]
+    acc = {k: 0.0 for k in names}
+    grad_rec = torch.zeros(V * sc.n * gs.GRAD_FLOATS, dtype=torch.float32, device=dev)
+    nrep = max(3, min(args.steps, 10))
+    dL = step.dL
+    for _ in range(nrep):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
+        grad_rec.zero_()
+        for g in step.grads.values():
+            g.zero_()
+        ev[0].record(stream)
+        r.project(params)
+        ev[1].record(stream)
+        r.bin_sort()
+        ev[2].record(stream)
+        r.render_fwd()
+        ev[3].record(stream)
+        r.blend_bwd(dL, grad_rec)
+        ev[4].record(stream)
+        r.project_bwd(params, grad_rec, step.grads)
+        ev[5].record(stream)
+        torch.cuda.synchronize()
+        for i, k in enumerate(names):
+            acc[k] += ev[i].elapsed_time(ev[i + 1])
+    stage_ms = {k: v / nrep for k, v in acc.items()}
+    K = r.pairs()
+    useful_pairs = int(r.last.to(torch.int64).sum())
+
+    # dominant single-kernel stage
+    single = {"render_fwd": "render_fwd_kernel", "blend_bwd": "render_bwd_kernel", "project": "project_kernel",
+              "project_bwd": "project_bwd_kernel"}
+    dom = max(single, key=lambda k: stage_ms[k])
+    src_hash = kernel_source_hash()
+    workload = f"config{args.config}"
+    t_s = stage_ms[dom] * 1e-3
+    if dom in ("render_fwd", "blend_bwd"):
+        flop = useful_pairs * (FWD_FLOP_PER_PAIR if dom == "render_fwd" else BWD_FLOP_PER_PAIR)
+        achieved = flop / t_s / 1e12
+        roof = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
+                    frac=round(achieved / PEAK_FP32_TFLOPS, 5))
+    else:
+        nrec = V * sc.n
+        if dom == "project":
+            byts = 252.0 * sc.n + 52.0 * nrec
+        else:
+            byts = 36.0 * nrec + 504.0 * sc.n
+        achieved = byts / t_s / 1e9
+        roof = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
+                    frac=round(achieved / PEAK_HBM_GBS, 5))
+    roof["kernel"] = single[dom]
+    roof["ms_per_launch"] = round(stage_ms[dom], 4)
+    roof["traffic"] = load_traffic(single[dom], workload, src_hash)
+
+    # ---------------- FP64 oracle on the host cores (bounded sample) ----------------
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import baseline
+        cpu = baseline.measure(wl, opts, target_seconds=args.cpu_seconds)
+
+    out = {
+        "metric": "fwd+bwd rasterized Mpix/s at 1M Gaussians; batched-vs-per-view speedup at 1e-5",
+        "value": round(value, 2),
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded Gaussians and cameras shaped like the paper's scenes; no dataset)",
+        "config": {"workload": wl.name, "gaussians": sc.n, "views": V, "pixels_per_step": pixels,
+                   "resolutions": [f"{c.width}x{c.height}" for c in wl.cams], "sh_degree": sc.sh_degree,
+                   "tile": f"{opts.tile_w}x{opts.tile_h}", "batch_depth": opts.batch_depth,
+                   "pixels_per_thread": opts.pixels_per_thread, "graph": not args.no_graph},
+        "per_view": per_view,
+        "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+        "pairs": K,
+        "useful_pairs": useful_pairs,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "kernel_source": src_hash,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

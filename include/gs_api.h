@@ -1,0 +1,208 @@
+/*
+ * gs_api.h -- C ABI of libgs, an MI355X (gfx950) differentiable Gaussian-splatting
+ * tile rasterizer: the forward and backward hot path of the training step of
+ * Trick-GS (arXiv 2501.14534).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every array pointer is a DEVICE pointer owned by the caller (typically a
+ *    PyTorch tensor).  Host structs (gs_gaussians, gs_camera, gs_opts, ...)
+ *    are read during the call only.
+ *  - The library never allocates, frees or synchronises.  A call validates
+ *    its arguments on the host, enqueues kernels on `stream` and returns; no
+ *    call reads device memory on the host, so every call may be captured in a
+ *    HIP graph.  Scratch memory comes in through `ws` (size from
+ *    gs_workspace_size) and is clobbered by the call.
+ *  - Layouts are structure-of-arrays with the Gaussian index last: an array
+ *    documented [3][n] holds component k of Gaussian i at [k*n + i].
+ *  - A "record" is one (view, Gaussian) pair, r = view * n + gaussian.
+ *  - V views of one call are batched: their tiles form one key space (global
+ *    tile id = view's tile offset + ty * TX + tx, views in call order) and
+ *    their pixels are concatenated in call order.
+ *  - Return value: GS_OK, or a negative GS_E_* code.  On GS_E_INVALID nothing
+ *    was enqueued.  Capacity overflow of the binning is a DEVICE-side status
+ *    (see gs_binning); the call that overflows cannot know it.
+ */
+#ifndef GS_API_H
+#define GS_API_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+struct ihipStream_t;
+typedef struct ihipStream_t* gs_stream_t; /* a hipStream_t; NULL = the null stream */
+
+enum {
+  GS_OK = 0,
+  GS_E_INVALID = -1,     /* bad argument: null pointer, size, degree, tile shape ... */
+  GS_E_CAPACITY = -2,    /* reported through gs_binning.status, never returned by a call */
+  GS_E_HIP = -3,         /* a kernel launch failed; hipGetLastError() is left set */
+  GS_E_UNSUPPORTED = -4  /* the current device is not gfx950 */
+};
+
+#define GS_MAX_VIEWS 16       /* views per call */
+#define GS_SPLAT_FLOATS 12    /* floats per projected record */
+#define GS_GRAD_FLOATS 9      /* floats per record gradient */
+#define GS_MAX_BATCH 256      /* largest per-tile staging batch */
+
+/* Gaussian parameters, raw (before activations).  Sec. 3.1: mean, scale,
+ * rotation quaternion, opacity, diffuse colour and SH coefficients; Sec. 3.2.5:
+ * the diffuse colour (band 0) is passed separately from SH bands 1..3;
+ * Sec. 3.2.1 (Eq. 3): one volume-mask logit per Gaussian, applied to opacity
+ * and scales; Sec. 3.2.3 (Eq. 5): one mask logit per SH band 1..3.           */
+typedef struct gs_gaussians {
+  const float* means;           /* [3][n] world position                                 */
+  const float* log_scales;      /* [3][n] log of the three axis scales                   */
+  const float* quats;           /* [4][n] rotation (w, x, y, z); normalised internally   */
+  const float* opacity_logits;  /* [n]   opacity = sigmoid(logit)                        */
+  const float* sh_dc;           /* [3][n] diffuse colour c_dc (RGB)                      */
+  const float* sh_rest;         /* [(K-1)][3][n], K = (deg+1)^2, coefficient k >= 1 of
+                                   channel c at [((k-1)*3 + c)*n + i]; NULL iff deg == 0 */
+  const float* mask_logits;     /* [n] or NULL (no volume mask)                          */
+  const float* sh_mask_logits;  /* [3][n] bands 1..3, or NULL (no band masks)            */
+  int64_t n;                    /* number of Gaussians, >= 0                             */
+  int32_t sh_degree;            /* 0..3                                                  */
+  float mask_eps;               /* hard mask M = [sigmoid(m) > mask_eps]                 */
+  float sh_mask_eps;            /* hard band mask M^l = [sigmoid(m_l) > sh_mask_eps]     */
+} gs_gaussians;
+
+/* Pinhole camera: x_cam = R x_world + t, camera axes x right, y down, z
+ * forward; pixel (i, j) has its centre at (i + 0.5, j + 0.5).              */
+typedef struct gs_camera {
+  float R[9]; /* row-major world -> camera rotation */
+  float t[3];
+  float fx, fy, cx, cy;
+  int32_t width, height; /* > 0 */
+} gs_camera;
+
+/* Per-call rasterizer options. */
+typedef struct gs_opts {
+  float near_plane;  /* cull when camera z <= near_plane (e.g. 0.2)                        */
+  float tan_clamp;   /* lateral ratio guard of the EWA Jacobian, in half fields of view (1.3) */
+  float lowpass;     /* s of Sigma' + sI (Sec. 3.2.4; 0.3, or max(0.3, HW/(9 pi N)))       */
+  float bg[3];       /* background colour added with the final transmittance              */
+  int32_t tile_w;    /* tile width in pixels, power of two                                 */
+  int32_t tile_h;    /* tile height in pixels, power of two; tile_w*tile_h in [64, 1024]   */
+  int32_t batch_depth;       /* splats staged per tile batch, 1..GS_MAX_BATCH              */
+  int32_t pixels_per_thread; /* 1, 2 or 4; tile_w*tile_h/ppt a multiple of 64, <= 256      */
+} gs_opts;
+
+/* Projected (view, Gaussian) records, written by gs_project.
+ * splats: [V*n][12] floats, 16-byte aligned:
+ *   [0] u  [1] v            screen position of the mean (pixels)
+ *   [2] A  [3] B  [4] C     conic: inverse of Sigma' + sI, exponent -(A dx^2 + 2B dx dy + C dy^2)/2
+ *   [5] o'                  masked opacity
+ *   [6] radius              integral, 3 standard deviations of the major axis
+ *   [7] depth               camera-space z
+ *   [8..10] rgb             view-dependent colour
+ *   [11] valid              1 when projected, 0 when culled (then [0..10] are 0)
+ * tiles_touched: [V*n] number of tiles the record is binned to (0 = none). */
+typedef struct gs_projected {
+  float* splats;
+  uint32_t* tiles_touched;
+} gs_projected;
+
+/* Sorted (tile, depth) lists.  keys/ids hold `capacity` entries; after a
+ * successful gs_bin_sort the first K = *count are sorted by key, then by id:
+ *   key = (global tile << 32) | IEEE bits of the record's depth
+ *   id  = record index (view * n + gaussian)
+ * ranges: [total_tiles][2] = [start, end) into keys/ids, [0,0) when empty.
+ * count, status: device words written by gs_bin_sort.  status = 0 on success,
+ * 1 when K > capacity: then no list is written, every range is empty and
+ * *count still holds K, so the caller can grow the buffers and run again. */
+typedef struct gs_binning {
+  uint64_t* keys;
+  uint32_t* ids;
+  uint32_t* ranges;
+  uint64_t capacity; /* < 2^32 */
+  uint32_t* count;   /* device, 1 word */
+  int32_t* status;   /* device, 1 word */
+} gs_binning;
+
+/* Gradients, ACCUMULATED (+=) into caller-zeroed arrays shaped like the
+ * parameters.  Any member may be NULL to skip it.  mean2d, if given, is
+ * [V][2][n] and receives dL/d(u, v) (densification statistics).            */
+typedef struct gs_grads {
+  float* means;
+  float* log_scales;
+  float* quats;
+  float* opacity_logits;
+  float* sh_dc;
+  float* sh_rest;
+  float* mask_logits;
+  float* sh_mask_logits;
+  float* mean2d;
+} gs_grads;
+
+/* Number of tiles and pixels of V views under `opts` (host only). */
+int gs_view_sizes(const gs_camera* cams, int32_t V, const gs_opts* opts, int64_t* total_tiles,
+                  int64_t* total_pixels);
+
+/* Bytes of scratch memory that gs_bin_sort and gs_render_bwd need for n
+ * Gaussians, V views and a list capacity (host only; 0 on invalid input). */
+size_t gs_workspace_size(int64_t n, int32_t V, const gs_camera* cams, const gs_opts* opts, uint64_t capacity);
+
+/* Projection of every Gaussian into every view (Sec. 3.1 Eq. 1, Sec. 3.2.4,
+ * Eq. 3, Eq. 5, Sec. 3.2.5): activations, hard masks, world->camera, near
+ * cull, 3D covariance from scale and rotation, EWA projection with the
+ * low-pass s, conic, radius, SH colour (bands 1..deg scaled by their hard
+ * masks, clamped at 0) and the number of tiles each record touches.
+ * Reads each Gaussian once for all V views.  Writes out->splats and
+ * out->tiles_touched ([V*n] records). */
+int gs_project(const gs_gaussians* g, const gs_camera* cams, int32_t V, const gs_opts* opts,
+               gs_projected* out, gs_stream_t stream);
+
+/* Tile binning and ordering of the records of a gs_project call: device-wide
+ * scan of tiles_touched, emission of one (tile, depth) key per touched tile,
+ * LSD radix sort over the significant key bits (stable, so equal keys keep
+ * id order), per-tile ranges.  Needs ws_bytes >= gs_workspace_size(...). */
+int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int32_t V, int64_t n, const gs_opts* opts,
+                gs_binning* out, void* ws, size_t ws_bytes, gs_stream_t stream);
+
+/* Front-to-back compositing of Eq. 2 per pixel over its tile's list:
+ * square test |centre - (u,v)| <= radius per axis, alpha = min(0.99, o' exp(-q/2)),
+ * skip alpha < 1/255, stop before a Gaussian that would bring the
+ * transmittance under 1e-4, output C + T bg.
+ * image: [sum_v 3*H_v*W_v] planar per view ([3][H][W]), views concatenated.
+ * T_final, last_contrib: [sum_v H_v*W_v]; last_contrib counts the list
+ * entries of the pixel's tile up to and including the last composited one. */
+int gs_render_fwd(const gs_projected* proj, const gs_binning* bins, const gs_camera* cams, int32_t V,
+                  int64_t n, const gs_opts* opts, float* image, float* T_final, int32_t* last_contrib,
+                  gs_stream_t stream);
+
+/* Backward of gs_render_fwd and gs_project for dL/dimage (layout of image):
+ * each tile's list is walked back to front from its largest last_contrib,
+ * transmittance recovered by division, per-splat partials reduced across the
+ * wave and the workgroup before one atomic per attribute per (tile, splat),
+ * then the chain rule to the raw parameters including the straight-through
+ * mask gradients (Eq. 3, Eq. 5).  Gradients are accumulated into `grads`.
+ * Needs ws_bytes >= gs_workspace_size(...). */
+int gs_render_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t V, const gs_opts* opts,
+                  const gs_projected* proj, const gs_binning* bins, const float* T_final,
+                  const int32_t* last_contrib, const float* dL_dimage, gs_grads* grads, void* ws,
+                  size_t ws_bytes, gs_stream_t stream);
+
+/* The two halves of gs_render_bwd, for callers that schedule or time them
+ * separately.  gs_blend_bwd: the per-tile back-to-front walk only; ADDS the
+ * per-record splat gradients (u, v, A, B, C, o', r, g, b) into grad_rec
+ * ([V*n][9], caller-zeroed).  gs_project_bwd: the chain rule from grad_rec
+ * to the raw parameters (same math as the second half of gs_render_bwd),
+ * accumulated into `grads`.                                                 */
+int gs_blend_bwd(const gs_camera* cams, int32_t V, int64_t n, const gs_opts* opts, const gs_projected* proj,
+                 const gs_binning* bins, const float* T_final, const int32_t* last_contrib, const float* dL_dimage,
+                 float* grad_rec, gs_stream_t stream);
+int gs_project_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t V, const gs_opts* opts,
+                   const float* grad_rec, gs_grads* grads, gs_stream_t stream);
+
+/* Static description of a return code. */
+const char* gs_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GS_API_H */

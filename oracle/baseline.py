@@ -1,0 +1,90 @@
+"""Times the FP64 oracle on a bounded sample of a workload (benchmark CPU baseline).
+
+TEST INFRASTRUCTURE ONLY (the benchmark's cpu_baseline leg).  The oracle is
+run as it stands -- not tuned for speed -- on the host cores it was built for
+(OpenMP threads as the environment sets them):
+  * projection of every (view, Gaussian) record and binning/ordering of the
+    whole workload are run in full;
+  * forward and backward compositing run on a random subset of tiles, sized
+    to the time budget, and are scaled to all tiles by the tile fraction;
+  * the projection backward runs on a random subset of records and is scaled
+    by the record fraction.
+The reported rate is total pixels / (sum of the scaled stage times).
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from . import oracle as O
+
+
+def _t(fn):
+    t0 = time.perf_counter()
+    out = fn()
+    return out, time.perf_counter() - t0
+
+
+def measure(wl, opts, target_seconds: float = 20.0, seed: int = 0) -> dict:
+    sc = wl.scene
+    n, V = sc.n, len(wl.cams)
+    rng = np.random.default_rng(seed)
+    sp, t_proj = _t(lambda: O.project_views(sc, wl.cams, opts))
+    lists, t_bin = _t(lambda: O.bin(wl.cams, opts, n, sp["uv"][:, 0].astype(np.float32),
+                                     sp["uv"][:, 1].astype(np.float32), sp["depth"].astype(np.float32),
+                                     sp["radius"], sp["valid"]))
+    T = lists["ranges"].shape[0]
+    P = wl.pixels
+    dl = rng.standard_normal(3 * P) / np.sqrt(3 * P)
+
+    def composite(tiles):
+        mask = np.zeros(T, np.uint8)
+        mask[tiles] = 1
+        _, tf = _t(lambda: O.composite_fwd(wl.cams, opts, n, sp, lists["ids"], lists["ranges"], tile_mask=mask))
+        grec, tb = _t(lambda: O.composite_bwd(wl.cams, opts, n, sp, lists["ids"], lists["ranges"], dl,
+                                              tile_mask=mask))
+        return tf, tb
+
+    order = rng.permutation(T)
+    probe = order[: max(1, T // 200)]
+    tf, tb = composite(probe)
+    per_tile = (tf + tb) / len(probe)
+    budget = max(0.4 * target_seconds - (tf + tb), 0.0)
+    extra = int(min(T - len(probe), budget / max(per_tile, 1e-9)))
+    sample = order[: len(probe) + extra]
+    tf, tb = composite(sample)
+    ft = len(sample) / T
+
+    # projection backward: a random subset of records with unit splat gradients
+    rec_cost_probe = max(1, min(n, 2000))
+    idx = rng.choice(n, size=rec_cost_probe, replace=False)
+    sub = sc.subset(np.sort(idx))
+    grads = O.zero_grads(sub)
+    gr = np.ones((sub.n, 9))
+    _, tp = _t(lambda: O.project_bwd(sub, wl.cams[0], opts, gr, grads))
+    per_rec = tp / sub.n
+    m = int(min(n, max(rec_cost_probe, 0.25 * target_seconds / max(per_rec, 1e-12))))
+    idx = rng.choice(n, size=m, replace=False)
+    sub = sc.subset(np.sort(idx))
+    grads = O.zero_grads(sub)
+    gr = np.ones((sub.n, 9))
+    _, tp = _t(lambda: O.project_bwd(sub, wl.cams[0], opts, gr, grads))
+    fr = sub.n / n
+    t_pbwd_full = tp / fr * V
+
+    total = t_proj + t_bin + tf / ft + tb / ft + t_pbwd_full
+    return {
+        "value": round(P / total / 1e6, 5),
+        "unit": "Mpix/s",
+        "cores": O.num_threads(),
+        "kind": "oracle",
+        "sample": (f"FP64 oracle: projection of all {V * n} records and binning of all {lists['K']} pairs in full; "
+                   f"forward+backward compositing on {len(sample)} of {T} tiles (random) scaled by the tile "
+                   f"fraction; projection backward on {sub.n} of {n} Gaussians scaled by the record fraction "
+                   f"and view count"),
+        "stage_s": {"project": round(t_proj, 3), "bin": round(t_bin, 3),
+                    "composite_fwd_scaled": round(tf / ft, 3), "composite_bwd_scaled": round(tb / ft, 3),
+                    "project_bwd_scaled": round(t_pbwd_full, 3)},
+        "measured_s": round(t_proj + t_bin + tf + tb + tp, 3),
+    }

@@ -330,6 +330,7 @@ inline void campos_of(const OrcCamera& cam, double p[3]) {
   for (int j = 0; j < 3; ++j) p[j] = -(cam.R[j] * cam.t[0] + cam.R[3 + j] * cam.t[1] + cam.R[6 + j] * cam.t[2]);
 }
 
+// A Gaussian is culled when any input that its forward value reads is not finite.
 bool finite_inputs(const OrcGaussians& g, int64_t i) {
   const int64_t n = g.n;
   for (int k = 0; k < 3; ++k)
@@ -340,12 +341,20 @@ bool finite_inputs(const OrcGaussians& g, int64_t i) {
     if (!std::isfinite(g.quats[k * n + i])) return false;
   if (!std::isfinite(g.opacity_logits[i])) return false;
   if (g.mask_logits && !std::isfinite(g.mask_logits[i])) return false;
-  const int K = (g.sh_degree + 1) * (g.sh_degree + 1);
-  for (int k = 0; k < (K - 1) * 3; ++k)
-    if (!std::isfinite(g.sh_rest[k * n + i])) return false;
-  if (g.sh_mask_logits)
-    for (int k = 0; k < 3; ++k)
-      if (!std::isfinite(g.sh_mask_logits[k * n + i])) return false;
+  // SH band l's coefficients enter the forward only when its hard mask is on
+  bool on[4] = {true, true, true, true};
+  if (g.sh_mask_logits && g.sh_degree > 0)
+    for (int l = 1; l <= 3; ++l) {
+      const double m = g.sh_mask_logits[(l - 1) * n + i];
+      if (!std::isfinite(m)) return false;
+      on[l] = 1.0 / (1.0 + std::exp(-m)) > g.sh_mask_eps;
+    }
+  for (int l = 1; l <= g.sh_degree; ++l) {
+    if (!on[l]) continue;
+    for (int k = l * l; k < (l + 1) * (l + 1); ++k)
+      for (int c = 0; c < 3; ++c)
+        if (!std::isfinite(g.sh_rest[((k - 1) * 3 + c) * n + i])) return false;
+  }
   return true;
 }
 
@@ -619,11 +628,13 @@ int64_t orc_bin(int32_t V, int64_t n, const OrcCamera* cams, const OrcOpts* o, c
 // Optional: eps[3] = relative alpha window, relative T window, pixel window
 // for flagging near-threshold decisions (flags per pixel: 1 square edge,
 // 2 alpha skip, 4 termination, 8 alpha cap), and a per-pixel hash of all
-// decisions taken.
+// decisions taken.  tile_mask (per global tile, may be NULL) restricts the
+// work to the tiles marked 1; pixels of other tiles are left untouched.
 void orc_composite_fwd(int32_t V, int64_t n, const OrcCamera* cams, const OrcOpts* o, const double* uv,
                        const double* conic, const double* opacity, const double* rgb, const int32_t* radius,
                        const uint32_t* ids, const uint32_t* ranges, double* image, double* T_final,
-                       int32_t* last_contrib, const double* eps, uint8_t* flags, uint64_t* hash) {
+                       int32_t* last_contrib, const double* eps, uint8_t* flags, uint64_t* hash,
+                       const uint8_t* tile_mask) {
   (void)n;
   int64_t total_tiles = 0;
   std::vector<ViewGeom> vt = view_table(V, cams, *o, &total_tiles, nullptr);
@@ -632,6 +643,7 @@ void orc_composite_fwd(int32_t V, int64_t n, const OrcCamera* cams, const OrcOpt
     for (int64_t t = 0; t < (int64_t)vt[v].TX * vt[v].TY; ++t) tile_view[vt[v].tile_off + t] = v;
 #pragma omp parallel for schedule(dynamic, 1)
   for (int64_t gt = 0; gt < total_tiles; ++gt) {
+    if (tile_mask && !tile_mask[gt]) continue;
     const int vi = tile_view[gt];
     const ViewGeom& g = vt[vi];
     const int64_t lt = gt - g.tile_off;
@@ -657,9 +669,11 @@ void orc_composite_fwd(int32_t V, int64_t n, const OrcCamera* cams, const OrcOpt
 // R_i = sum_{j>i} c_j a_j T_j + T_final bg (the colour behind it):
 //   dC/dc_i = a_i T_i,   dC/da_i = T_i c_i - R_i / (1 - a_i);
 // a = min(0.99, o' G), G = exp(-q/2): capped alphas pass no gradient.
+// tile_mask as in orc_composite_fwd (pixels of other tiles contribute nothing).
 void orc_composite_bwd(int32_t V, int64_t n, const OrcCamera* cams, const OrcOpts* o, const double* uv,
                        const double* conic, const double* opacity, const double* rgb, const int32_t* radius,
-                       const uint32_t* ids, const uint32_t* ranges, const double* dL_dimage, double* grad_rec) {
+                       const uint32_t* ids, const uint32_t* ranges, const double* dL_dimage, double* grad_rec,
+                       const uint8_t* tile_mask) {
   int64_t total_tiles = 0;
   std::vector<ViewGeom> vt = view_table(V, cams, *o, &total_tiles, nullptr);
   std::vector<int32_t> tile_view(total_tiles);
@@ -672,6 +686,7 @@ void orc_composite_bwd(int32_t V, int64_t n, const OrcCamera* cams, const OrcOpt
   std::vector<double> eg((size_t)Kmax * 9, 0.0);  // per list entry; each entry belongs to one tile
 #pragma omp parallel for schedule(dynamic, 1)
   for (int64_t gt = 0; gt < total_tiles; ++gt) {
+    if (tile_mask && !tile_mask[gt]) continue;
     const int vi = tile_view[gt];
     const ViewGeom& g = vt[vi];
     const int64_t lt = gt - g.tile_off;

@@ -81,9 +81,9 @@ def lib():
         L.orc_bin.argtypes = [C.c_int32, C.c_int64, C.POINTER(OrcCamera), C.POINTER(OrcOpts), F, F, F, I32, I32,
                               U32, U64, U32, C.c_int64, U32]
         L.orc_composite_fwd.argtypes = [C.c_int32, C.c_int64, C.POINTER(OrcCamera), C.POINTER(OrcOpts), D, D, D, D,
-                                        I32, U32, U32, D, D, I32, D, U8, U64]
+                                        I32, U32, U32, D, D, I32, D, U8, U64, U8]
         L.orc_composite_bwd.argtypes = [C.c_int32, C.c_int64, C.POINTER(OrcCamera), C.POINTER(OrcOpts), D, D, D, D,
-                                        I32, U32, U32, D, D]
+                                        I32, U32, U32, D, D, U8]
         L.orc_project_bwd.argtypes = [C.POINTER(OrcGaussians), C.POINTER(OrcCamera), C.POINTER(OrcOpts), D,
                                       C.POINTER(OrcGrads)]
         _lib = L
@@ -228,9 +228,14 @@ def _splat_args(sp):
     return uv, conic, op, rgb, rad
 
 
-def composite_fwd(cams, opts, n, splats, ids, ranges, eps=None) -> dict:
+def _mask(tile_mask):
+    return None if tile_mask is None else np.ascontiguousarray(tile_mask, np.uint8)
+
+
+def composite_fwd(cams, opts, n, splats, ids, ranges, eps=None, tile_mask=None) -> dict:
     """Eq. 2 per pixel.  Returns flat image (views concatenated, each [3,H,W]),
-    T_final, last_contrib, and (if eps given) near-threshold flags + decision hashes."""
+    T_final, last_contrib, and (if eps given) near-threshold flags + decision hashes.
+    tile_mask (uint8 per global tile) restricts the work to the marked tiles."""
     V = len(cams)
     P = sum(c.width * c.height for c in cams)
     uv, conic, op, rgb, rad = _splat_args(splats)
@@ -244,15 +249,16 @@ def composite_fwd(cams, opts, n, splats, ids, ranges, eps=None) -> dict:
     flags = np.zeros(P, np.uint8)
     hsh = np.zeros(P, np.uint64)
     e = None if eps is None else np.asarray(eps, np.float64)
+    tm = _mask(tile_mask)
     cs, o = _cams(cams), opts_struct(opts)
     lib().orc_composite_fwd(V, n, cs, C.byref(o), _p(uv, D), _p(conic, D), _p(op, D), _p(rgb, D), _p(rad, I32),
                             _p(ids, U32), _p(ranges, U32), _p(img, D), _p(T, D), _p(last, I32), _p(e, D),
                             _p(flags, U8) if e is not None else None,
-                            _p(hsh, U64) if e is not None else None)
+                            _p(hsh, U64) if e is not None else None, _p(tm, U8))
     return dict(image=img, T_final=T, last_contrib=last, flags=flags, hash=hsh)
 
 
-def composite_bwd(cams, opts, n, splats, ids, ranges, dL_dimage) -> np.ndarray:
+def composite_bwd(cams, opts, n, splats, ids, ranges, dL_dimage, tile_mask=None) -> np.ndarray:
     """Gradient of sum(dL_dimage * image) w.r.t. per-record (u, v, A, B, C, o', r, g, b) -> [V*n, 9]."""
     V = len(cams)
     uv, conic, op, rgb, rad = _splat_args(splats)
@@ -262,9 +268,10 @@ def composite_bwd(cams, opts, n, splats, ids, ranges, dL_dimage) -> np.ndarray:
     ranges = np.ascontiguousarray(ranges, np.uint32)
     dl = _f64(dL_dimage).reshape(-1)
     out = np.zeros((V * n, 9))
+    tm = _mask(tile_mask)
     cs, o = _cams(cams), opts_struct(opts)
     lib().orc_composite_bwd(V, n, cs, C.byref(o), _p(uv, D), _p(conic, D), _p(op, D), _p(rgb, D), _p(rad, I32),
-                            _p(ids, U32), _p(ranges, U32), _p(dl, D), _p(out, D))
+                            _p(ids, U32), _p(ranges, U32), _p(dl, D), _p(out, D), _p(tm, U8))
     return out
 
 

@@ -1,0 +1,106 @@
+"""Tile-shape / batch-depth / pixels-per-thread autotuner with a JSON cache.
+
+The image does not depend on these choices (every pixel walks the same splats
+in the same order whatever the tiling: each pixel applies the square test), so
+the tuner may pick freely by time.  Candidates are timed as whole fwd+bwd
+steps of the workload; the winner is stored per (device arch, workload key).
+"""
+from __future__ import annotations
+
+import dataclasses
+import json
+import os
+from typing import Dict, Iterable, List, Optional, Tuple
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CACHE = os.path.join(HERE, "autotune_cache.json")
+
+# (tile_w, tile_h, batch_depth, pixels_per_thread)
+CANDIDATES: List[Tuple[int, int, int, int]] = [
+    (16, 16, 256, 1), (16, 16, 128, 1), (16, 16, 64, 1),
+    (16, 16, 256, 2), (16, 16, 128, 2),
+    (16, 16, 256, 4), (16, 16, 128, 4), (16, 16, 64, 4),
+    (8, 8, 64, 1), (16, 8, 128, 1), (16, 8, 128, 2), (32, 8, 256, 1), (32, 8, 128, 2),
+    (32, 16, 256, 2), (32, 16, 256, 4),
+]
+
+
+def workload_key(wl) -> str:
+    res = ",".join(f"{c.width}x{c.height}" for c in wl.cams)
+    sc = wl.scene
+    nb = 1 << max(0, int(sc.n - 1).bit_length())  # power-of-two bucket of the Gaussian count
+    return f"n<={nb}|deg{sc.sh_degree}|{res}"
+
+
+def _arch() -> str:
+    try:
+        import torch
+        return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    except Exception:  # noqa: BLE001 - no device: no cached entry applies
+        return "none"
+
+
+def load_cache() -> Dict[str, dict]:
+    if not os.path.exists(CACHE):
+        return {}
+    try:
+        return json.load(open(CACHE))
+    except ValueError:
+        return {}
+
+
+def best_opts(wl, arch: Optional[str] = None):
+    """Cached winner for this workload on this device, else the workload's default options."""
+    arch = arch or _arch()
+    e = load_cache().get(f"{arch}|{workload_key(wl)}")
+    if not e:
+        return wl.opts
+    return dataclasses.replace(wl.opts, tile_w=e["tile_w"], tile_h=e["tile_h"], batch_depth=e["batch_depth"],
+                               pixels_per_thread=e["pixels_per_thread"])
+
+
+def tune(wl, candidates: Iterable[Tuple[int, int, int, int]] = CANDIDATES, steps: int = 5, warmup: int = 2,
+         write: bool = True, verbose: bool = True) -> dict:
+    """Time each candidate's fwd+bwd step and store the fastest in the cache."""
+    import time
+
+    import numpy as np
+    import torch
+
+    from . import raster
+
+    sc = wl.scene
+    params = raster.to_device(sc)
+    target = torch.from_numpy(np.concatenate([t.reshape(-1) for t in wl.targets])).cuda()
+    results = []
+    ref_img = None
+    for tw, th, bd, ppt in candidates:
+        o = dataclasses.replace(wl.opts, tile_w=tw, tile_h=th, batch_depth=bd, pixels_per_thread=ppt)
+        r = raster.Rasterizer(sc.n, sc.sh_degree, wl.cams, o, mask_eps=sc.mask_eps, sh_mask_eps=sc.sh_mask_eps)
+        st = raster.Step(r, params, target, graph=True)
+        st.run()
+        for _ in range(warmup):
+            st.launch()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            st.launch()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        img = r.image.clone()
+        if ref_img is None:
+            ref_img = img
+        same = bool(torch.equal(img, ref_img))
+        results.append(dict(tile_w=tw, tile_h=th, batch_depth=bd, pixels_per_thread=ppt, ms=ms, image_equal=same))
+        if verbose:
+            print(f"  tile {tw}x{th} batch {bd} ppt {ppt}: {ms:.3f} ms/step, image identical: {same}", flush=True)
+        del st, r
+        torch.cuda.empty_cache()
+    ok = [x for x in results if x["image_equal"]]
+    best = min(ok, key=lambda x: x["ms"])
+    if write:
+        cache = load_cache()
+        cache[f"{_arch()}|{workload_key(wl)}"] = best
+        with open(CACHE, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+    return dict(best=best, results=results)

@@ -1,0 +1,293 @@
+// Host side of the libgs C ABI: argument validation, per-view constant
+// tables, workspace carve-up and kernel launches on the caller's stream.
+// Nothing here allocates, frees, synchronises or reads device memory.
+#include <cmath>
+#include <cstring>
+
+#include "gs_api.h"
+#include "kernels.h"
+
+using namespace gs;
+
+namespace {
+
+bool pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+int ilog2(int x) {
+  int r = 0;
+  while ((1 << r) < x) ++r;
+  return r;
+}
+
+int device_ok() {
+  static int cached[64] = {0};  // 0 unknown, 1 gfx950, -1 other
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return GS_E_HIP;
+  if (cached[dev] == 0) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return GS_E_HIP;
+    cached[dev] = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : -1;
+  }
+  return cached[dev] == 1 ? GS_OK : GS_E_UNSUPPORTED;
+}
+
+// logit(eps) rounded down to a float, so that for every float m:
+// (m > thr)  <=>  (m > logit(eps))  <=>  (sigmoid(m) > eps) in exact arithmetic.
+bool mask_threshold(float eps, float* thr) {
+  if (!(eps > 0.0f && eps < 1.0f)) return false;
+  const double L = std::log((double)eps / (1.0 - (double)eps));
+  float f = (float)L;
+  if ((double)f > L) f = std::nextafter(f, -INFINITY);
+  *thr = f;
+  return true;
+}
+
+bool opts_ok(const gs_opts* o) {
+  if (!o) return false;
+  if (!pow2(o->tile_w) || !pow2(o->tile_h)) return false;
+  const int px = o->tile_w * o->tile_h;
+  if (px < 64 || px > 1024) return false;
+  if (o->pixels_per_thread != 1 && o->pixels_per_thread != 2 && o->pixels_per_thread != 4) return false;
+  if (px % (64 * o->pixels_per_thread) != 0) return false;
+  if (px / o->pixels_per_thread > 256) return false;  // render kernels run <= 256 threads per tile
+  if (o->batch_depth < 1 || o->batch_depth > GS_MAX_BATCH) return false;
+  if (!std::isfinite(o->lowpass) || o->lowpass < 0.0f) return false;
+  if (!std::isfinite(o->near_plane)) return false;
+  if (!(o->tan_clamp > 0.0f)) return false;
+  for (int c = 0; c < 3; ++c)
+    if (!std::isfinite(o->bg[c])) return false;
+  return true;
+}
+
+bool view_table(const gs_camera* cams, int32_t V, const gs_opts* o, ViewTable* vt, int64_t* total_pixels) {
+  if (!cams || V < 1 || V > GS_MAX_VIEWS || !opts_ok(o)) return false;
+  std::memset(vt, 0, sizeof(*vt));
+  int64_t to = 0, po = 0;
+  for (int v = 0; v < V; ++v) {
+    const gs_camera& c = cams[v];
+    if (c.width <= 0 || c.height <= 0 || !(c.fx > 0.0f) || !(c.fy > 0.0f)) return false;
+    for (int k = 0; k < 9; ++k)
+      if (!std::isfinite(c.R[k])) return false;
+    for (int k = 0; k < 3; ++k)
+      if (!std::isfinite(c.t[k])) return false;
+    ViewArgs& a = vt->v[v];
+    std::memcpy(a.R, c.R, sizeof(a.R));
+    std::memcpy(a.t, c.t, sizeof(a.t));
+    a.fx = c.fx, a.fy = c.fy, a.cx = c.cx, a.cy = c.cy;
+    for (int j = 0; j < 3; ++j)
+      a.campos[j] = (float)-((double)c.R[j] * c.t[0] + (double)c.R[3 + j] * c.t[1] + (double)c.R[6 + j] * c.t[2]);
+    a.limx = (float)((double)o->tan_clamp * 0.5 * c.width / c.fx);
+    a.limy = (float)((double)o->tan_clamp * 0.5 * c.height / c.fy);
+    a.W = c.width, a.H = c.height;
+    a.TX = (c.width + o->tile_w - 1) / o->tile_w;
+    a.TY = (c.height + o->tile_h - 1) / o->tile_h;
+    a.tile_off = (int32_t)to;
+    a.pix_off = (int32_t)po;
+    to += (int64_t)a.TX * a.TY;
+    po += (int64_t)c.width * c.height;
+    if (to >= (1ll << 31) || 3 * po >= (1ll << 31)) return false;
+  }
+  vt->nviews = V;
+  vt->total_tiles = (int32_t)to;
+  if (total_pixels) *total_pixels = po;
+  return true;
+}
+
+bool gaussians_ok(const gs_gaussians* g, ProjectArgs* a) {
+  if (!g || g->n < 0 || g->n >= (1ll << 31) || g->sh_degree < 0 || g->sh_degree > 3) return false;
+  if (g->n > 0 && (!g->means || !g->log_scales || !g->quats || !g->opacity_logits || !g->sh_dc)) return false;
+  if (g->n > 0 && g->sh_degree > 0 && !g->sh_rest) return false;
+  std::memset(a, 0, sizeof(*a));
+  a->means = g->means, a->log_scales = g->log_scales, a->quats = g->quats;
+  a->opacity_logits = g->opacity_logits, a->sh_dc = g->sh_dc;
+  a->sh_rest = g->sh_degree > 0 ? g->sh_rest : nullptr;
+  a->mask_logits = g->mask_logits;
+  a->sh_mask_logits = g->sh_degree > 0 ? g->sh_mask_logits : nullptr;
+  a->n = g->n;
+  a->mask_thr = 0.f;
+  a->sh_mask_thr = 0.f;
+  if (g->mask_logits && !mask_threshold(g->mask_eps, &a->mask_thr)) return false;
+  if (g->sh_mask_logits && g->sh_degree > 0 && !mask_threshold(g->sh_mask_eps, &a->sh_mask_thr)) return false;
+  return true;
+}
+
+SortPlan sort_plan(int64_t n, int32_t V, int32_t total_tiles, uint64_t capacity) {
+  SortPlan p;
+  p.nrec = (int64_t)V * n;
+  p.scan_blocks = (p.nrec + 1023) / 1024;
+  p.sort_blocks = (int64_t)((capacity + 4095) / 4096);
+  p.bits = 32 + (total_tiles > 1 ? ilog2(total_tiles) : 0);
+  p.passes = (p.bits + 7) / 8;
+  return p;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+RenderArgs render_args(const gs_projected* p, const gs_binning* b, const gs_opts* o) {
+  RenderArgs a;
+  a.splats = (const float4*)p->splats;
+  a.ids = b->ids;
+  a.ranges = b->ranges;
+  a.status = b->status;
+  a.log2_tw = ilog2(o->tile_w);
+  a.log2_th = ilog2(o->tile_h);
+  a.batch = o->batch_depth;
+  a.ppt = o->pixels_per_thread;
+  for (int c = 0; c < 3; ++c) a.bg[c] = o->bg[c];
+  return a;
+}
+
+int launched(hipError_t e) { return e == hipSuccess ? GS_OK : GS_E_HIP; }
+
+ProjectBwdArgs project_bwd_args(ProjectArgs pa, const gs_opts* opts, const float* grad_rec, const gs_grads* grads,
+                                int deg) {
+  pa.near_plane = opts->near_plane;
+  pa.lowpass = opts->lowpass;
+  pa.inv_tw = 1.0f / (float)opts->tile_w;
+  pa.inv_th = 1.0f / (float)opts->tile_h;
+  ProjectBwdArgs b;
+  b.p = pa;
+  b.grad_rec = grad_rec;
+  b.g_means = grads->means;
+  b.g_log_scales = grads->log_scales;
+  b.g_quats = grads->quats;
+  b.g_opacity_logits = grads->opacity_logits;
+  b.g_sh_dc = grads->sh_dc;
+  b.g_sh_rest = deg > 0 ? grads->sh_rest : nullptr;
+  b.g_mask_logits = grads->mask_logits;
+  b.g_sh_mask_logits = deg > 0 ? grads->sh_mask_logits : nullptr;
+  b.g_mean2d = grads->mean2d;
+  return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gs_strerror(int code) {
+  switch (code) {
+    case GS_OK: return "ok";
+    case GS_E_INVALID: return "invalid argument";
+    case GS_E_CAPACITY: return "binning capacity exceeded";
+    case GS_E_HIP: return "HIP launch failure";
+    case GS_E_UNSUPPORTED: return "device is not gfx950";
+    default: return "unknown error";
+  }
+}
+
+int gs_view_sizes(const gs_camera* cams, int32_t V, const gs_opts* opts, int64_t* total_tiles,
+                  int64_t* total_pixels) {
+  ViewTable vt;
+  int64_t px = 0;
+  if (!view_table(cams, V, opts, &vt, &px)) return GS_E_INVALID;
+  if (total_tiles) *total_tiles = vt.total_tiles;
+  if (total_pixels) *total_pixels = px;
+  return GS_OK;
+}
+
+size_t gs_workspace_size(int64_t n, int32_t V, const gs_camera* cams, const gs_opts* opts, uint64_t capacity) {
+  ViewTable vt;
+  if (n < 0 || capacity >= (1ull << 32) || !view_table(cams, V, opts, &vt, nullptr)) return 0;
+  const SortPlan p = sort_plan(n, V, vt.total_tiles, capacity);
+  const size_t sort_bytes = bin_sort_ws_bytes(p);
+  const size_t bwd_bytes = align256(sizeof(float) * GS_GRAD_FLOATS * (size_t)V * (size_t)n);
+  return sort_bytes > bwd_bytes ? sort_bytes : bwd_bytes;
+}
+
+int gs_project(const gs_gaussians* g, const gs_camera* cams, int32_t V, const gs_opts* opts, gs_projected* out,
+               gs_stream_t stream) {
+  ProjectArgs a;
+  ViewTable vt;
+  if (!gaussians_ok(g, &a) || !view_table(cams, V, opts, &vt, nullptr)) return GS_E_INVALID;
+  if (!out || (g->n > 0 && (!out->splats || !out->tiles_touched))) return GS_E_INVALID;
+  if (((uintptr_t)out->splats & 15) != 0) return GS_E_INVALID;
+  const int d = device_ok();
+  if (d != GS_OK) return d;
+  a.near_plane = opts->near_plane;
+  a.lowpass = opts->lowpass;
+  a.inv_tw = 1.0f / (float)opts->tile_w;
+  a.inv_th = 1.0f / (float)opts->tile_h;
+  a.splats = (float4*)out->splats;
+  a.tiles_touched = out->tiles_touched;
+  return launched(launch_project(a, vt, g->sh_degree, (hipStream_t)stream));
+}
+
+int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int32_t V, int64_t n, const gs_opts* opts,
+                gs_binning* out, void* ws, size_t ws_bytes, gs_stream_t stream) {
+  ViewTable vt;
+  if (!proj || !out || n < 0 || n >= (1ll << 31) || !view_table(cams, V, opts, &vt, nullptr)) return GS_E_INVALID;
+  if ((int64_t)V * n >= (1ll << 32)) return GS_E_INVALID;
+  if (n > 0 && (!proj->splats || !proj->tiles_touched)) return GS_E_INVALID;
+  if (!out->ranges || !out->count || !out->status || out->capacity >= (1ull << 32)) return GS_E_INVALID;
+  if (out->capacity > 0 && (!out->keys || !out->ids)) return GS_E_INVALID;
+  if (ws_bytes < gs_workspace_size(n, V, cams, opts, out->capacity) || (!ws && ws_bytes > 0)) return GS_E_INVALID;
+  const int d = device_ok();
+  if (d != GS_OK) return d;
+  const SortPlan p = sort_plan(n, V, vt.total_tiles, out->capacity);
+  return launched(launch_bin_sort(p, (const float4*)proj->splats, proj->tiles_touched, n, vt,
+                                  1.0f / (float)opts->tile_w, 1.0f / (float)opts->tile_h, out->keys, out->ids,
+                                  out->ranges, out->capacity, out->count, out->status, ws, (hipStream_t)stream));
+}
+
+int gs_render_fwd(const gs_projected* proj, const gs_binning* bins, const gs_camera* cams, int32_t V, int64_t n,
+                  const gs_opts* opts, float* image, float* T_final, int32_t* last_contrib, gs_stream_t stream) {
+  ViewTable vt;
+  if (!proj || !bins || n < 0 || !view_table(cams, V, opts, &vt, nullptr)) return GS_E_INVALID;
+  if (!image || !T_final || !last_contrib || !bins->ranges || !bins->status) return GS_E_INVALID;
+  if (n > 0 && (!proj->splats || (bins->capacity > 0 && !bins->ids))) return GS_E_INVALID;
+  const int d = device_ok();
+  if (d != GS_OK) return d;
+  const RenderArgs a = render_args(proj, bins, opts);
+  return launched(launch_render_fwd(a, vt, image, T_final, last_contrib, (hipStream_t)stream));
+}
+
+int gs_render_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t V, const gs_opts* opts,
+                  const gs_projected* proj, const gs_binning* bins, const float* T_final,
+                  const int32_t* last_contrib, const float* dL_dimage, gs_grads* grads, void* ws, size_t ws_bytes,
+                  gs_stream_t stream) {
+  ProjectArgs pa;
+  ViewTable vt;
+  if (!gaussians_ok(g, &pa) || !view_table(cams, V, opts, &vt, nullptr)) return GS_E_INVALID;
+  if (!proj || !bins || !T_final || !last_contrib || !dL_dimage || !grads) return GS_E_INVALID;
+  if (!bins->ranges || !bins->status) return GS_E_INVALID;
+  if (g->n > 0 && (!proj->splats || (bins->capacity > 0 && !bins->ids))) return GS_E_INVALID;
+  const size_t need = align256(sizeof(float) * GS_GRAD_FLOATS * (size_t)V * (size_t)g->n);
+  if (ws_bytes < need || (!ws && need > 0)) return GS_E_INVALID;
+  const int d = device_ok();
+  if (d != GS_OK) return d;
+  hipStream_t s = (hipStream_t)stream;
+  float* grad_rec = (float*)ws;
+  hipError_t e = launch_fill_u32((uint32_t*)grad_rec, (int64_t)GS_GRAD_FLOATS * V * g->n, 0u, s);
+  if (e != hipSuccess) return GS_E_HIP;
+  const RenderArgs ra = render_args(proj, bins, opts);
+  e = launch_render_bwd(ra, vt, T_final, last_contrib, dL_dimage, grad_rec, s);
+  if (e != hipSuccess) return GS_E_HIP;
+  return launched(launch_project_bwd(project_bwd_args(pa, opts, grad_rec, grads, g->sh_degree), vt, g->sh_degree, s));
+}
+
+int gs_blend_bwd(const gs_camera* cams, int32_t V, int64_t n, const gs_opts* opts, const gs_projected* proj,
+                 const gs_binning* bins, const float* T_final, const int32_t* last_contrib, const float* dL_dimage,
+                 float* grad_rec, gs_stream_t stream) {
+  ViewTable vt;
+  if (n < 0 || !view_table(cams, V, opts, &vt, nullptr)) return GS_E_INVALID;
+  if (!proj || !bins || !T_final || !last_contrib || !dL_dimage || !bins->ranges || !bins->status) return GS_E_INVALID;
+  if (n > 0 && (!proj->splats || !grad_rec || (bins->capacity > 0 && !bins->ids))) return GS_E_INVALID;
+  const int d = device_ok();
+  if (d != GS_OK) return d;
+  const RenderArgs ra = render_args(proj, bins, opts);
+  return launched(launch_render_bwd(ra, vt, T_final, last_contrib, dL_dimage, grad_rec, (hipStream_t)stream));
+}
+
+int gs_project_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t V, const gs_opts* opts,
+                   const float* grad_rec, gs_grads* grads, gs_stream_t stream) {
+  ProjectArgs pa;
+  ViewTable vt;
+  if (!gaussians_ok(g, &pa) || !view_table(cams, V, opts, &vt, nullptr)) return GS_E_INVALID;
+  if (!grads || (g->n > 0 && !grad_rec)) return GS_E_INVALID;
+  const int d = device_ok();
+  if (d != GS_OK) return d;
+  return launched(launch_project_bwd(project_bwd_args(pa, opts, grad_rec, grads, g->sh_degree), vt, g->sh_degree,
+                                     (hipStream_t)stream));
+}
+
+}  // extern "C"

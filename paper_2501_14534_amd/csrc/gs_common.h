@@ -1,0 +1,143 @@
+// Device-side definitions shared by the libgs kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gs_api.h"
+
+namespace gs {
+
+// Compositing constants of the rasterizer the paper builds on: alpha cap,
+// skip threshold and the transmittance floor that stops a pixel.
+constexpr float kAlphaMax = 0.99f;
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kTMin = 1e-4f;
+constexpr float kLog2e = 1.44269504088896341f;
+
+constexpr int kWave = 64;
+
+// Per-view constants, passed by value in kernel arguments (graph-capture safe).
+struct ViewArgs {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  float campos[3];     // -R^T t
+  float limx, limy;    // lateral ratio guard of the Jacobian
+  int32_t W, H, TX, TY;
+  int32_t tile_off;    // first global tile of the view
+  int32_t pix_off;     // first pixel of the view in the concatenated planes
+};
+
+struct ViewTable {
+  ViewArgs v[GS_MAX_VIEWS];
+  int32_t nviews;
+  int32_t total_tiles;
+};
+
+__device__ __forceinline__ int view_of_tile(const ViewTable& vt, int gtile) {
+  int v = 0;
+#pragma unroll 1
+  for (int i = 1; i < vt.nviews; ++i) v = (gtile >= vt.v[i].tile_off) ? i : v;
+  return v;
+}
+
+// Tile rectangle of a record in single precision: x in
+// [floor((u - r)/TW), floor((u + r)/TW)] clipped to [0, TX-1], likewise y.
+// u - r and u + r are single IEEE operations; TW, TH are powers of two so the
+// scaling by 1/TW is exact.  Returns false when the rectangle is empty.
+__device__ __forceinline__ bool tile_rect(float u, float v, float r, float inv_tw, float inv_th, int TX, int TY,
+                                          int* x0, int* y0, int* x1, int* y1) {
+#pragma clang fp contract(off)
+  float fx0 = floorf((u - r) * inv_tw);
+  float fx1 = floorf((u + r) * inv_tw);
+  float fy0 = floorf((v - r) * inv_th);
+  float fy1 = floorf((v + r) * inv_th);
+  fx0 = fmaxf(fx0, 0.0f);
+  fy0 = fmaxf(fy0, 0.0f);
+  fx1 = fminf(fx1, (float)(TX - 1));
+  fy1 = fminf(fy1, (float)(TY - 1));
+  if (!(fx1 >= fx0) || !(fy1 >= fy0)) return false;
+  *x0 = (int)fx0;
+  *x1 = (int)fx1;
+  *y0 = (int)fy0;
+  *y1 = (int)fy1;
+  return true;
+}
+
+// One (pixel, splat) evaluation shared bit-for-bit by the forward and the
+// backward walks: square test, Gaussian falloff G and alpha = min(0.99, o' G).
+// Every operation is explicit (no contraction), so both kernels take identical
+// skip/stop decisions.  Returns false when the pixel is outside the square.
+struct Eval {
+  float dx, dy, G, raw, alpha;
+};
+
+__device__ __forceinline__ bool eval_splat(float px, float py, float u, float v, float A, float B, float C, float o,
+                                           float rad, Eval* e) {
+#pragma clang fp contract(off)
+  const float dx = px - u;
+  const float dy = py - v;
+  if (!(fabsf(dx) <= rad && fabsf(dy) <= rad)) return false;
+  const float q = A * dx * dx + 2.0f * B * dx * dy + C * dy * dy;
+  const float G = __builtin_amdgcn_exp2f(q * (-0.5f * kLog2e));
+  const float raw = o * G;
+  e->dx = dx;
+  e->dy = dy;
+  e->G = G;
+  e->raw = raw;
+  e->alpha = fminf(kAlphaMax, raw);
+  return true;
+}
+
+// Sum over the 64 lanes of a wave, result valid in lane 63.  Row-local
+// shifted adds (row_shr 1, 2, 4, 8) give each row's total in its lane 15;
+// row_bcast:15 and row_bcast:31 then fold rows 0..3 into lane 63.
+__device__ __forceinline__ float wave_sum_lane63(float v) {
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x111, 0xf, 0xf, false));
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x112, 0xf, 0xf, false));
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x114, 0xf, 0xf, false));
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x118, 0xf, 0xf, false));
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x142, 0xa, 0xf, false));
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x143, 0xc, 0xf, false));
+  return v;
+}
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Real SH basis constants (closed forms: 1/2 sqrt(15/pi) etc.), single precision.
+constexpr float kC1 = 0.48860251190291992f;   // sqrt(3/(4 pi))
+constexpr float kC2a = 1.09254843059207907f;  // 1/2 sqrt(15/pi)
+constexpr float kC2b = 0.31539156525252005f;  // 1/4 sqrt(5/pi)
+constexpr float kC2c = 0.54627421529603959f;  // 1/4 sqrt(15/pi)
+constexpr float kC3a = 0.59004358992664352f;  // 1/4 sqrt(35/(2 pi))
+constexpr float kC3b = 2.89061144264055405f;  // 1/2 sqrt(105/pi)
+constexpr float kC3c = 0.45704579946446572f;  // 1/4 sqrt(21/(2 pi))
+constexpr float kC3d = 0.37317633259011540f;  // 1/4 sqrt(7/pi)
+constexpr float kC3e = 1.44530572132027737f;  // 1/4 sqrt(105/pi)
+
+// Basis functions k = 1..15 (band 0 is the diffuse colour) at unit (x, y, z).
+__device__ __forceinline__ void sh_basis15(float x, float y, float z, float Y[15]) {
+  const float xx = x * x, yy = y * y, zz = z * z;
+  Y[0] = -kC1 * y;
+  Y[1] = kC1 * z;
+  Y[2] = -kC1 * x;
+  Y[3] = kC2a * x * y;
+  Y[4] = -kC2a * y * z;
+  Y[5] = kC2b * (2.0f * zz - xx - yy);
+  Y[6] = -kC2a * x * z;
+  Y[7] = kC2c * (xx - yy);
+  Y[8] = -kC3a * y * (3.0f * xx - yy);
+  Y[9] = kC3b * x * y * z;
+  Y[10] = -kC3c * y * (4.0f * zz - xx - yy);
+  Y[11] = kC3d * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+  Y[12] = -kC3c * x * (4.0f * zz - xx - yy);
+  Y[13] = kC3e * z * (xx - yy);
+  Y[14] = -kC3a * x * (xx - 3.0f * yy);
+}
+
+__device__ __forceinline__ float sigmoidf(float x) { return 1.0f / (1.0f + __expf(-x)); }
+
+__device__ __forceinline__ bool finitef(float x) { return __builtin_isfinite(x); }
+
+}  // namespace gs

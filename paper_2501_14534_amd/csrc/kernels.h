@@ -1,0 +1,83 @@
+// Kernel argument structs and launch wrappers of libgs (host + device).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gs_common.h"
+
+namespace gs {
+
+struct ProjectArgs {
+  const float* means;
+  const float* log_scales;
+  const float* quats;
+  const float* opacity_logits;
+  const float* sh_dc;
+  const float* sh_rest;
+  const float* mask_logits;
+  const float* sh_mask_logits;
+  int64_t n;
+  float mask_thr;     // logit(mask_eps), rounded down to float
+  float sh_mask_thr;  // logit(sh_mask_eps), rounded down to float
+  float near_plane;
+  float lowpass;
+  float inv_tw, inv_th;
+  float4* splats;
+  uint32_t* tiles_touched;
+};
+
+struct RenderArgs {
+  const float4* splats;
+  const uint32_t* ids;
+  const uint32_t* ranges;
+  const int32_t* status;
+  int32_t log2_tw, log2_th;
+  int32_t batch;
+  int32_t ppt;
+  float bg[3];
+};
+
+struct ProjectBwdArgs {
+  ProjectArgs p;           // forward inputs (outputs unused)
+  const float* grad_rec;   // [V*n][9]
+  float* g_means;
+  float* g_log_scales;
+  float* g_quats;
+  float* g_opacity_logits;
+  float* g_sh_dc;
+  float* g_sh_rest;
+  float* g_mask_logits;
+  float* g_sh_mask_logits;
+  float* g_mean2d;
+};
+
+// Workspace carve-up of gs_bin_sort / gs_render_bwd.
+struct SortPlan {
+  int64_t nrec;         // V * n
+  int64_t scan_blocks;  // records / 1024
+  int64_t sort_blocks;  // capacity / 4096
+  int passes;
+  int bits;
+};
+
+hipError_t launch_project(const ProjectArgs& a, const ViewTable& vt, int deg, hipStream_t s);
+
+hipError_t launch_bin_sort(const SortPlan& plan, const float4* splats, const uint32_t* tiles_touched, int64_t n,
+                           const ViewTable& vt, float inv_tw, float inv_th, uint64_t* keys, uint32_t* ids,
+                           uint32_t* ranges, uint64_t capacity, uint32_t* count, int32_t* status, void* ws,
+                           hipStream_t s);
+
+hipError_t launch_render_fwd(const RenderArgs& a, const ViewTable& vt, float* image, float* T_final,
+                             int32_t* last_contrib, hipStream_t s);
+
+hipError_t launch_render_bwd(const RenderArgs& a, const ViewTable& vt, const float* T_final,
+                             const int32_t* last_contrib, const float* dL_dimage, float* grad_rec, hipStream_t s);
+
+hipError_t launch_project_bwd(const ProjectBwdArgs& a, const ViewTable& vt, int deg, hipStream_t s);
+
+hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t value, hipStream_t s);
+
+size_t bin_sort_ws_bytes(const SortPlan& plan);
+
+}  // namespace gs

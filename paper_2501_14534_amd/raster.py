@@ -1,0 +1,270 @@
+"""Device buffers and call sequences around libgs; torch.autograd wrapper; graph-captured step.
+
+`Rasterizer` owns the buffers of one (Gaussian count, view set, options)
+configuration and issues the four C-ABI calls on the current torch stream.
+PyTorch provides device memory and streams only; every step of the path runs
+in libgs kernels.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import gs
+
+PARAM_NAMES = ("means", "log_scales", "quats", "opacity_logits", "sh_dc", "sh_rest", "mask_logits", "sh_mask_logits")
+
+
+def to_device(scene, device="cuda") -> Dict[str, torch.Tensor]:
+    """Parameter arrays of a scenes.Scene as contiguous float32 device tensors."""
+    return {k: torch.from_numpy(np.ascontiguousarray(v, np.float32)).to(device) for k, v in scene.arrays().items()}
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+class Rasterizer:
+    """Forward/backward rasterization of n Gaussians into a fixed set of views.
+
+    capacity: number of (record, tile) pairs the sort buffers hold.  When a
+    forward finds more pairs (device status word), `forward(check=True)`
+    grows the buffers and re-runs the binning; graph-captured callers pass
+    check=False and call `overflowed()` after the step.
+    """
+
+    def __init__(self, n: int, sh_degree: int, cams: Sequence, opts, *, mask_eps: float = 0.5,
+                 sh_mask_eps: float = 0.5, capacity: Optional[int] = None, device: str = "cuda"):
+        gs.load()
+        if len(cams) < 1 or len(cams) > gs.MAX_VIEWS:
+            raise ValueError(f"1..{gs.MAX_VIEWS} views per call")
+        self.n, self.deg, self.V = int(n), int(sh_degree), len(cams)
+        self.cams = list(cams)
+        self.opts = opts
+        self.mask_eps, self.sh_mask_eps = mask_eps, sh_mask_eps
+        dev = torch.device(device)
+        if dev.type == "cuda" and dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        self.cams_arr = gs.cameras(self.cams)
+        self.opts_s = gs.options(opts)
+        self.total_tiles, self.total_pixels = gs.view_sizes(self.cams_arr, self.V, self.opts_s)
+        dev = self.device
+        nrec = self.V * self.n
+        self.splats = torch.zeros(max(nrec, 1) * gs.SPLAT_FLOATS, dtype=torch.float32, device=dev)
+        self.tiles_touched = torch.zeros(max(nrec, 1), dtype=torch.int32, device=dev)
+        self.ranges = torch.zeros(max(self.total_tiles, 1) * 2, dtype=torch.int32, device=dev)
+        self.count = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.status = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.image = torch.zeros(3 * self.total_pixels, dtype=torch.float32, device=dev)
+        self.T_final = torch.zeros(self.total_pixels, dtype=torch.float32, device=dev)
+        self.last = torch.zeros(self.total_pixels, dtype=torch.int32, device=dev)
+        self.proj = gs.GsProjected(gs.ptr(self.splats), gs.ptr(self.tiles_touched))
+        self.capacity = 0
+        self.set_capacity(capacity if capacity is not None else max(1 << 16, 8 * nrec))
+
+    # -- buffers ---------------------------------------------------------------------------------
+    def set_capacity(self, capacity: int) -> None:
+        capacity = int(min(max(capacity, 1), (1 << 32) - 1))
+        self.capacity = capacity
+        self.keys = torch.zeros(capacity, dtype=torch.int64, device=self.device)
+        self.ids = torch.zeros(capacity, dtype=torch.int32, device=self.device)
+        self.ws_bytes = gs.workspace_size(self.n, self.cams_arr, self.V, self.opts_s, capacity)
+        if self.ws_bytes == 0:
+            raise gs.GsError("invalid configuration for gs_workspace_size")
+        self.ws = torch.zeros(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.bins = gs.GsBinning(gs.ptr(self.keys), gs.ptr(self.ids), gs.ptr(self.ranges), capacity,
+                                 gs.ptr(self.count), gs.ptr(self.status))
+
+    def gaussians(self, params: Dict[str, torch.Tensor]) -> gs.GsGaussians:
+        for k, t in params.items():
+            if t is None:
+                continue
+            if t.device != self.device or t.dtype != torch.float32 or not t.is_contiguous():
+                raise ValueError(f"{k}: expected a contiguous float32 tensor on {self.device}")
+        return gs.gaussians(params, self.n, self.deg, self.mask_eps, self.sh_mask_eps)
+
+    # -- calls -----------------------------------------------------------------------------------
+    def project(self, params) -> None:
+        g = self.gaussians(params)
+        gs.check(gs.project(g, self.cams_arr, self.V, self.opts_s, self.proj, _stream()), "gs_project")
+
+    def bin_sort(self) -> None:
+        gs.check(gs.bin_sort(self.proj, self.cams_arr, self.V, self.n, self.opts_s, self.bins, gs.ptr(self.ws),
+                             self.ws_bytes, _stream()), "gs_bin_sort")
+
+    def render_fwd(self) -> None:
+        gs.check(gs.render_fwd(self.proj, self.bins, self.cams_arr, self.V, self.n, self.opts_s, gs.ptr(self.image),
+                               gs.ptr(self.T_final), gs.ptr(self.last), _stream()), "gs_render_fwd")
+
+    def render_bwd(self, params, dL_dimage: torch.Tensor, grads: Dict[str, torch.Tensor],
+                   mean2d: Optional[torch.Tensor] = None) -> None:
+        g = self.gaussians(params)
+        if dL_dimage.numel() != self.image.numel() or not dL_dimage.is_contiguous():
+            raise ValueError("dL_dimage must be contiguous and shaped like the image")
+        gr = gs.GsGrads(*[gs.ptr(grads.get(k)) for k in PARAM_NAMES], gs.ptr(mean2d))
+        gs.check(gs.render_bwd(g, self.cams_arr, self.V, self.opts_s, self.proj, self.bins, gs.ptr(self.T_final),
+                               gs.ptr(self.last), gs.ptr(dL_dimage), gr, gs.ptr(self.ws), self.ws_bytes, _stream()),
+                 "gs_render_bwd")
+
+    def blend_bwd(self, dL_dimage: torch.Tensor, grad_rec: torch.Tensor) -> None:
+        """Back-to-front walk only: adds per-record splat gradients into grad_rec [V*n, 9] (zeroed by the caller)."""
+        gs.check(gs.blend_bwd(self.cams_arr, self.V, self.n, self.opts_s, self.proj, self.bins, gs.ptr(self.T_final),
+                              gs.ptr(self.last), gs.ptr(dL_dimage), gs.ptr(grad_rec), _stream()), "gs_blend_bwd")
+
+    def project_bwd(self, params, grad_rec: torch.Tensor, grads: Dict[str, torch.Tensor], mean2d=None) -> None:
+        g = self.gaussians(params)
+        gr = gs.GsGrads(*[gs.ptr(grads.get(k)) for k in PARAM_NAMES], gs.ptr(mean2d))
+        gs.check(gs.project_bwd(g, self.cams_arr, self.V, self.opts_s, gs.ptr(grad_rec), gr, _stream()),
+                 "gs_project_bwd")
+
+    def overflowed(self) -> bool:
+        return bool(self.status.item())
+
+    def pairs(self) -> int:
+        return int(self.count.item()) & 0xFFFFFFFF
+
+    def forward(self, params, check: bool = True) -> torch.Tensor:
+        """project -> bin/sort -> composite; returns the flat image buffer (views concatenated)."""
+        self.project(params)
+        self.bin_sort()
+        if check and self.overflowed():
+            self.set_capacity(int(self.pairs() * 1.25) + 1024)
+            self.bin_sort()
+            assert not self.overflowed()
+        self.render_fwd()
+        return self.image
+
+    def backward(self, params, dL_dimage, grads, mean2d=None) -> None:
+        self.render_bwd(params, dL_dimage, grads, mean2d)
+
+    # -- views of the outputs --------------------------------------------------------------------
+    def split(self, flat: torch.Tensor, channels: int) -> List[torch.Tensor]:
+        out, off = [], 0
+        for c in self.cams:
+            k = channels * c.width * c.height
+            shape = (channels, c.height, c.width) if channels > 1 else (c.height, c.width)
+            out.append(flat[off:off + k].view(shape))
+            off += k
+        return out
+
+    def images(self) -> List[torch.Tensor]:
+        return self.split(self.image, 3)
+
+    def splat_records(self) -> torch.Tensor:
+        return self.splats[: self.V * self.n * gs.SPLAT_FLOATS].view(self.V * self.n, gs.SPLAT_FLOATS)
+
+    def grad_records(self) -> torch.Tensor:
+        """Per-record splat gradients left in the workspace by the last backward."""
+        k = self.V * self.n * gs.GRAD_FLOATS
+        return self.ws[: 4 * k].view(torch.float32).view(self.V * self.n, gs.GRAD_FLOATS)
+
+    def zero_grads(self, params) -> Dict[str, torch.Tensor]:
+        return {k: torch.zeros_like(v) for k, v in params.items() if v is not None}
+
+
+class RasterizeFn(torch.autograd.Function):
+    """image = rasterize(params); backward through gs_render_bwd.
+
+    The Rasterizer keeps the forward state (records, lists, T_final,
+    last_contrib) until its next forward, so one forward may be in flight
+    per Rasterizer."""
+
+    @staticmethod
+    def forward(ctx, rast: Rasterizer, names, *tensors):
+        params = dict(zip(names, tensors))
+        img = rast.forward(params).clone()
+        ctx.rast = rast
+        ctx.names = names
+        ctx.save_for_backward(*tensors)
+        return img
+
+    @staticmethod
+    def backward(ctx, dL):
+        tensors = ctx.saved_tensors
+        params = dict(zip(ctx.names, tensors))
+        grads = {k: torch.zeros_like(v) for k, v in params.items()}
+        ctx.rast.backward(params, dL.contiguous(), grads)
+        return (None, None, *[grads[k] for k in ctx.names])
+
+
+def rasterize(rast: Rasterizer, params: Dict[str, torch.Tensor]) -> torch.Tensor:
+    names = tuple(k for k in PARAM_NAMES if params.get(k) is not None)
+    return RasterizeFn.apply(rast, names, *[params[k] for k in names])
+
+
+def l2_loss_grad(image: torch.Tensor, target: torch.Tensor, views: int, out: torch.Tensor,
+                 pixels_per_view: Sequence[int]) -> None:
+    """dL/dimage of L = mean over views of mean over 3HW of (image - target)^2, written into `out`."""
+    off = 0
+    for p in pixels_per_view:
+        k = 3 * p
+        torch.sub(image[off:off + k], target[off:off + k], out=out[off:off + k])
+        out[off:off + k].mul_(2.0 / (k * views))
+        off += k
+
+
+class Step:
+    """One fwd+bwd step of a Rasterizer (project, bin/sort, composite, L2 gradient,
+    backward), run eagerly or replayed from a captured HIP graph.
+
+    The binning capacity is fixed while a graph exists; `run()` reads the
+    device status after the step and, on overflow, grows the buffers,
+    re-captures and runs again."""
+
+    def __init__(self, rast: Rasterizer, params, target_flat: torch.Tensor, graph: bool = True,
+                 loss_views: Optional[int] = None):
+        self.rast = rast
+        self.params = params
+        self.target = target_flat
+        self.dL = torch.zeros_like(rast.image)
+        self.grads = rast.zero_grads(params)
+        self.graph_enabled = graph
+        self.graph = None
+        self.pix = [c.width * c.height for c in rast.cams]
+        # number of views the loss averages over (a per-view step of a batch uses the batch's count)
+        self.loss_views = rast.V if loss_views is None else int(loss_views)
+
+    def _body(self):
+        r = self.rast
+        r.project(self.params)
+        r.bin_sort()
+        r.render_fwd()
+        l2_loss_grad(r.image, self.target, self.loss_views, self.dL, self.pix)
+        for g in self.grads.values():
+            g.zero_()
+        r.render_bwd(self.params, self.dL, self.grads)
+
+    def capture(self):
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            self._body()  # warm-up on the side stream before capture
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self._body()
+        self.graph = g
+
+    def launch(self):
+        """Enqueue one step (no host synchronisation)."""
+        if self.graph_enabled:
+            if self.graph is None:
+                self.capture()
+            self.graph.replay()
+        else:
+            self._body()
+
+    def run(self):
+        """One step with the capacity check (synchronises)."""
+        self.launch()
+        if self.rast.overflowed():
+            self.rast.set_capacity(int(self.rast.pairs() * 1.25) + 1024)
+            self.graph = None
+            self.launch()
+            assert not self.rast.overflowed()

@@ -1,0 +1,130 @@
+"""The C-ABI library loads, exports every symbol include/gs_api.h declares, and
+rejects invalid arguments on the host (CPU only: no compute call is made)."""
+import ctypes as C
+import dataclasses
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2501_14534_amd import gs, scenes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gs_api.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(gs.LIB):
+        pytest.skip("libgs.so not built")
+    return gs.load()
+
+
+def declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gs_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared()
+    assert {"gs_project", "gs_bin_sort", "gs_render_fwd", "gs_render_bwd"} <= set(names)
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(gs.EXPORTS)
+
+
+def test_strerror(lib):
+    assert gs.strerror(gs.GS_OK) == "ok"
+    assert "invalid" in gs.strerror(gs.GS_E_INVALID)
+    assert "capacity" in gs.strerror(gs.GS_E_CAPACITY)
+
+
+def test_view_sizes_match_tile_grid(lib):
+    wl = scenes.config(4, n=10)
+    cams = gs.cameras(wl.cams)
+    tiles, px = gs.view_sizes(cams, len(wl.cams), gs.options(wl.opts))
+    exp_t = sum(-(-c.width // 16) * -(-c.height // 16) for c in wl.cams)
+    assert tiles == exp_t == 12116
+    assert px == wl.pixels == 3089216
+
+
+def test_workspace_size(lib):
+    wl = scenes.config(1, n=100)
+    cams = gs.cameras(wl.cams)
+    o = gs.options(wl.opts)
+    a = gs.workspace_size(100, cams, 1, o, 1000)
+    b = gs.workspace_size(100, cams, 1, o, 100000)
+    assert 0 < a < b
+    bad = gs.options(dataclasses.replace(wl.opts, tile_w=12))
+    assert gs.workspace_size(100, cams, 1, bad, 1000) == 0
+    assert gs.workspace_size(100, cams, 1, o, 1 << 33) == 0
+
+
+def _bad_opts(wl):
+    yield dataclasses.replace(wl.opts, tile_w=12)
+    yield dataclasses.replace(wl.opts, tile_w=4, tile_h=4)           # 16 px: below one wave
+    yield dataclasses.replace(wl.opts, pixels_per_thread=3)
+    yield dataclasses.replace(wl.opts, tile_w=32, tile_h=32, pixels_per_thread=1)  # 1024 threads
+    yield dataclasses.replace(wl.opts, batch_depth=0)
+    yield dataclasses.replace(wl.opts, batch_depth=257)
+    yield dataclasses.replace(wl.opts, lowpass=-1.0)
+    yield dataclasses.replace(wl.opts, tan_clamp=0.0)
+
+
+def test_project_rejects_invalid_arguments(lib):
+    wl = scenes.config(1, n=64)
+    n = 64
+    fake = {k: 4096 for k in ("means", "log_scales", "quats", "opacity_logits", "sh_dc")}
+
+    class P:  # stand-in tensors: only their address is used, and invalid calls never reach the device
+        def __init__(self, a):
+            self.a = a
+
+        def data_ptr(self):
+            return self.a
+
+    params = {k: P(v) for k, v in fake.items()}
+    proj = gs.GsProjected(4096, 4096)
+    cams = gs.cameras(wl.cams)
+
+    def call(g=None, cams_=cams, V=1, opts=wl.opts, pr=proj):
+        g = g or gs.gaussians(params, n, 0, 0.5, 0.5)
+        return lib.gs_project(C.byref(g), cams_, V, C.byref(gs.options(opts)), C.byref(pr), None)
+
+    for o in _bad_opts(wl):
+        assert call(opts=o) == gs.GS_E_INVALID, o
+    assert call(V=0) == gs.GS_E_INVALID
+    assert call(V=gs.MAX_VIEWS + 1) == gs.GS_E_INVALID
+    assert call(g=gs.gaussians(params, n, 4, 0.5, 0.5)) == gs.GS_E_INVALID       # degree 4
+    assert call(g=gs.gaussians(params, n, 2, 0.5, 0.5)) == gs.GS_E_INVALID       # deg > 0 without sh_rest
+    assert call(g=gs.gaussians(params, -1, 0, 0.5, 0.5)) == gs.GS_E_INVALID
+    nomean = dict(params)
+    nomean["means"] = None
+    assert call(g=gs.gaussians(nomean, n, 0, 0.5, 0.5)) == gs.GS_E_INVALID
+    masked = dict(params, mask_logits=P(4096))
+    assert call(g=gs.gaussians(masked, n, 0, 1.5, 0.5)) == gs.GS_E_INVALID    # eps outside (0, 1)
+    assert call(pr=gs.GsProjected(4100, 4096)) == gs.GS_E_INVALID                # misaligned records
+    c0 = wl.cams[0]
+    bad_cam = scenes.Camera(c0.R, c0.t, -1.0, c0.fy, c0.cx, c0.cy, c0.width, c0.height)
+    assert call(cams_=gs.cameras([bad_cam])) == gs.GS_E_INVALID
+    zero_cam = scenes.Camera(c0.R, c0.t, c0.fx, c0.fy, c0.cx, c0.cy, 0, c0.height)
+    assert call(cams_=gs.cameras([zero_cam])) == gs.GS_E_INVALID
+
+
+def test_other_entry_points_reject_null_buffers(lib):
+    wl = scenes.config(1, n=64)
+    cams = gs.cameras(wl.cams)
+    o = gs.options(wl.opts)
+    proj = gs.GsProjected(4096, 4096)
+    bins = gs.GsBinning(4096, 4096, None, 100, 4096, 4096)  # ranges missing
+    assert lib.gs_bin_sort(C.byref(proj), cams, 1, 64, C.byref(o), C.byref(bins), 4096, 1 << 30, None) == \
+        gs.GS_E_INVALID
+    bins = gs.GsBinning(4096, 4096, 4096, 100, 4096, 4096)
+    assert lib.gs_bin_sort(C.byref(proj), cams, 1, 64, C.byref(o), C.byref(bins), 4096, 16, None) == \
+        gs.GS_E_INVALID  # workspace too small
+    assert lib.gs_render_fwd(C.byref(proj), C.byref(bins), cams, 1, 64, C.byref(o), None, 4096, 4096, None) == \
+        gs.GS_E_INVALID
+    assert lib.gs_blend_bwd(cams, 1, 64, C.byref(o), C.byref(proj), C.byref(bins), 4096, 4096, 4096, None,
+                            None) == gs.GS_E_INVALID

@@ -1,0 +1,273 @@
+"""Edge cases, metamorphic properties and full-size sampled parity of the HIP path (GPU only)."""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2501_14534_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2501_14534_amd import gs
+    gs.load()
+
+
+@pytest.fixture(scope="module")
+def P():
+    from tests import parity
+    return parity
+
+
+def _run(P, wl, opts=None, capacity=None, seed=5):
+    r, params = P.gpu_forward(wl, opts, capacity)
+    rng = np.random.default_rng(seed)
+    dL = torch.from_numpy(rng.standard_normal(3 * r.total_pixels).astype(np.float32) * 1e-3).cuda()
+    grads = r.zero_grads(params)
+    r.backward(params, dL, grads)
+    torch.cuda.synchronize()
+    return r, params, grads
+
+
+def _rel_close(a, b, tol):
+    a = a.double().cpu()
+    b = b.double().cpu()
+    if a.numel() == 0:
+        return True
+    rms = float(b.pow(2).mean().sqrt())
+    return bool(((a - b).abs() <= tol * torch.clamp(b.abs(), min=1e-2 * rms) + 1e-30).all())
+
+
+def test_empty_scene_gives_background(P):
+    wl = scenes.tiny(n=50, seed=1, deg=1)
+    sc = wl.scene.subset(np.zeros(wl.scene.n, bool))
+    wl0 = dataclasses.replace(wl, scene=sc, opts=dataclasses.replace(wl.opts, bg=(0.1, 0.2, 0.3)))
+    print("[edge] empty scene", flush=True)
+    r, params = P.gpu_forward(wl0)
+    img = r.images()[0].cpu().numpy()
+    for c, b in enumerate((0.1, 0.2, 0.3)):
+        assert np.all(img[c] == np.float32(b))
+    assert r.pairs() == 0
+    assert torch.all(r.T_final == 1.0)
+
+
+def test_all_culled_gives_background_and_zero_grads(P):
+    wl = scenes.tiny(n=80, seed=2, deg=2, masks=True)
+    sc = wl.scene.copy()
+    sc.means[1] = -np.abs(sc.means[1]) - 1.0  # everything behind the camera
+    wl1 = dataclasses.replace(wl, scene=sc)
+    print("[edge] all culled", flush=True)
+    r, params, grads = _run(P, wl1)
+    assert r.pairs() == 0
+    assert torch.all(r.image == 0.0)
+    for k, g in grads.items():
+        assert torch.all(g == 0.0), k
+
+
+def test_tile_batch_and_ppt_do_not_change_the_image(P):
+    wl = scenes.scaled(2, n=20000, shrink=4)
+    print("[edge] tile/batch/ppt invariance", flush=True)
+    ref, _, gref = _run(P, wl)
+    img = ref.image.clone()
+    T = ref.T_final.clone()
+    for tw, th, bd, ppt in [(8, 8, 64, 1), (32, 8, 256, 1), (16, 16, 17, 1), (16, 16, 1, 1), (16, 16, 256, 2),
+                            (16, 16, 100, 4), (32, 16, 256, 2), (16, 32, 128, 4), (64, 4, 256, 1)]:
+        o = dataclasses.replace(wl.opts, tile_w=tw, tile_h=th, batch_depth=bd, pixels_per_thread=ppt)
+        r, _, g = _run(P, wl, o)
+        assert torch.equal(r.image, img), (tw, th, bd, ppt)
+        assert torch.equal(r.T_final, T), (tw, th, bd, ppt)
+        for k in g:
+            assert _rel_close(g[k], gref[k], 1e-4), (k, tw, th, bd, ppt)
+
+
+def test_capacity_overflow_then_retry(P):
+    wl = scenes.scaled(3, n=30000, shrink=8)
+    print("[edge] capacity overflow", flush=True)
+    big, params = P.gpu_forward(wl)
+    K = big.pairs()
+    small = P.make_rasterizer(wl, capacity=max(1, K // 3))
+    small.project(params)
+    small.bin_sort()
+    small.render_fwd()
+    torch.cuda.synchronize()
+    assert small.overflowed() and small.pairs() == K
+    assert torch.all(small.ranges == 0)
+    assert torch.all(small.image == 0.0)  # bg = 0: every list empty
+    small.forward(params, check=True)  # grows and re-bins
+    torch.cuda.synchronize()
+    assert not small.overflowed() and small.capacity >= K
+    assert torch.equal(small.image, big.image)
+    assert torch.equal(small.keys[:K], big.keys[:K]) and torch.equal(small.ids[:K], big.ids[:K])
+
+
+def test_forward_is_deterministic(P):
+    wl = scenes.scaled(4, n=20000, shrink=4)
+    print("[edge] determinism", flush=True)
+    a, params = P.gpu_forward(wl)
+    img, keys, ids, ranges = a.image.clone(), a.keys.clone(), a.ids.clone(), a.ranges.clone()
+    a.forward(params)
+    torch.cuda.synchronize()
+    assert torch.equal(a.image, img)
+    assert torch.equal(a.keys, keys) and torch.equal(a.ids, ids) and torch.equal(a.ranges, ranges)
+
+
+def test_batched_equals_per_view(P):
+    wl = scenes.scaled(4, n=20000, shrink=2)
+    print("[edge] batched == per-view", flush=True)
+    rb, params = P.gpu_forward(wl)
+    rng = np.random.default_rng(9)
+    dLb = rng.standard_normal(3 * rb.total_pixels).astype(np.float32) * 1e-3
+    gb = rb.zero_grads(params)
+    rb.backward(params, torch.from_numpy(dLb).cuda(), gb)
+    gsum = rb.zero_grads(params)
+    off = 0
+    imgs = []
+    for c in wl.cams:
+        wv = dataclasses.replace(wl, cams=[c], targets=[None])
+        rv, _ = P.gpu_forward(wv, params=params)
+        k = 3 * c.pixels
+        rv.backward(params, torch.from_numpy(dLb[off:off + k]).cuda(), gsum)
+        imgs.append(rv.image.clone())
+        off += k
+    torch.cuda.synchronize()
+    assert torch.equal(torch.cat(imgs), rb.image)
+    for k in gb:
+        assert _rel_close(gb[k], gsum[k], 1e-5), k
+
+
+def test_graph_replay_matches_eager(P):
+    from paper_2501_14534_amd import raster
+    wl = scenes.scaled(4, n=20000, shrink=4)
+    print("[edge] graph replay == eager", flush=True)
+    target = torch.from_numpy(np.concatenate([t.reshape(-1) for t in wl.targets])).cuda()
+    params = raster.to_device(wl.scene)
+    eager = raster.Step(P.make_rasterizer(wl), params, target, graph=False)
+    eager.run()
+    torch.cuda.synchronize()
+    img0 = eager.rast.image.clone()
+    g0 = {k: v.clone() for k, v in eager.grads.items()}
+    st = raster.Step(P.make_rasterizer(wl), params, target, graph=True)
+    st.run()
+    for rep in range(3):
+        torch.cuda.synchronize()
+        junk = torch.randn(1 << 20, device="cuda").sum()  # unrelated eager work between replays
+        st.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(st.rast.image, img0), rep
+        for k in g0:
+            assert _rel_close(st.grads[k], g0[k], 1e-5), (rep, k)
+        del junk
+
+
+def test_autograd_function_matches_direct_backward(P):
+    from paper_2501_14534_amd import raster
+    wl = scenes.tiny(n=150, seed=4, deg=3, masks=True, band_masks=True, width=48, height=40)
+    print("[edge] autograd", flush=True)
+    r = P.make_rasterizer(wl)
+    params = raster.to_device(wl.scene)
+    leaves = {k: v.clone().requires_grad_(True) for k, v in params.items()}
+    img = raster.rasterize(r, leaves)
+    w = torch.randn_like(img)
+    (img * w).sum().backward()
+    r2, _ = P.gpu_forward(wl, params=params)
+    g = r2.zero_grads(params)
+    r2.backward(params, w.contiguous(), g)
+    torch.cuda.synchronize()
+    for k in g:
+        assert _rel_close(leaves[k].grad, g[k], 1e-5), k
+
+
+def test_mask_metamorphic_identities(P):
+    wl = scenes.tiny(n=200, seed=6, deg=3, masks=True, band_masks=True, width=64, height=48)
+    print("[edge] mask identities", flush=True)
+    sc = wl.scene.copy()
+    sc.mask_logits[:] = 3.0
+    sc.sh_mask_logits[:] = 3.0
+    on, _ = P.gpu_forward(dataclasses.replace(wl, scene=sc))
+    plain = sc.copy()
+    plain.mask_logits, plain.sh_mask_logits = None, None
+    pl, _ = P.gpu_forward(dataclasses.replace(wl, scene=plain))
+    assert torch.equal(on.image, pl.image)  # all masks on == unmasked
+    off = sc.copy()
+    off.sh_mask_logits[:] = -3.0
+    ro, _ = P.gpu_forward(dataclasses.replace(wl, scene=off))
+    d0 = plain.copy()
+    d0.sh_degree, d0.sh_rest = 0, None
+    r0, _ = P.gpu_forward(dataclasses.replace(wl, scene=d0))
+    assert torch.equal(ro.image, r0.image)  # all band masks off == degree 0
+    dele = sc.copy()
+    dele.mask_logits[::4] = -3.0
+    rd, _ = P.gpu_forward(dataclasses.replace(wl, scene=dele))
+    keep = np.ones(sc.n, bool)
+    keep[::4] = False
+    rk, _ = P.gpu_forward(dataclasses.replace(wl, scene=dele.subset(keep)))
+    assert torch.equal(rd.image, rk.image)  # mask 0 == Gaussian deleted
+
+
+def test_gaussian_order_does_not_matter(P):
+    wl = scenes.tiny(n=300, seed=8, deg=2, width=64, height=48)
+    print("[edge] permutation invariance", flush=True)
+    a, _ = P.gpu_forward(wl)
+    perm = np.random.default_rng(0).permutation(wl.scene.n)
+    b, _ = P.gpu_forward(dataclasses.replace(wl, scene=wl.scene.subset(perm)))
+    assert torch.equal(a.image, b.image)
+
+
+@pytest.mark.parametrize("cfg", [2, 3, 4])
+def test_full_size_sampled_parity(P, cfg):
+    """Full-size workload in the benchmark's launch configuration; binning bit-exact in full,
+    compositing and gradients on a random sample of tiles."""
+    from oracle import oracle as O
+    from paper_2501_14534_amd import autotune
+    wl = scenes.config(cfg)
+    opts = autotune.best_opts(wl)
+    print(f"[full] config {cfg}: n={wl.scene.n} views={len(wl.cams)} tile {opts.tile_w}x{opts.tile_h} "
+          f"batch {opts.batch_depth} ppt {opts.pixels_per_thread}", flush=True)
+    r, params = P.gpu_forward(wl, opts)
+    gl = P.check_binning(wl, opts, r)
+    rng = np.random.default_rng(cfg)
+    T = r.total_tiles
+    sample = rng.choice(T, size=min(T, 64), replace=False)
+    mask = np.zeros(T, np.uint8)
+    mask[sample] = 1
+    sp = P.records(r)
+    fw = O.composite_fwd(wl.cams, opts, wl.scene.n, sp, gl["ids"], gl["ranges"], eps=P.FLAG_EPS, tile_mask=mask)
+    # pixels of the sampled tiles
+    pix_mask = np.zeros(r.total_pixels, bool)
+    off = 0
+    for v, c in enumerate(wl.cams):
+        TX = -(-c.width // opts.tile_w)
+        t0 = int(sum(-(-cc.width // opts.tile_w) * -(-cc.height // opts.tile_h) for cc in wl.cams[:v]))
+        ys, xs = np.mgrid[0:c.height, 0:c.width]
+        gt = t0 + (ys // opts.tile_h) * TX + xs // opts.tile_w
+        pix_mask[off:off + c.pixels] = mask[gt.reshape(-1)] == 1
+        off += c.pixels
+    ok = pix_mask & (fw["flags"] == 0)
+    img = r.image.cpu().numpy().reshape(-1)
+    ok3 = np.concatenate([np.tile(ok[o:o + c.pixels], 3) for o, c in
+                          zip(np.cumsum([0] + [c.pixels for c in wl.cams[:-1]]), wl.cams)])
+    err = np.abs(img[ok3] - fw["image"][ok3]).max()
+    print(f"  sampled {ok.sum()} pixels, max image err {err:.2e}, flagged {int((pix_mask & (fw['flags'] != 0)).sum())}")
+    assert err <= P.IMG_TOL
+    assert np.array_equal(r.last.cpu().numpy()[ok], fw["last_contrib"][ok])
+    # gradients from the sampled, unflagged pixels only
+    w = np.zeros(3 * r.total_pixels, np.float32)
+    w[ok3] = (rng.standard_normal(int(ok3.sum())) * 1e-3).astype(np.float32)
+    grads = r.zero_grads(params)
+    r.backward(params, torch.from_numpy(w).cuda(), grads)
+    torch.cuda.synchronize()
+    grad_rec = O.composite_bwd(wl.cams, opts, wl.scene.n, sp, gl["ids"], gl["ranges"], w.astype(np.float64),
+                               tile_mask=mask)
+    og = O.zero_grads(wl.scene)
+    n = wl.scene.n
+    for v, c in enumerate(wl.cams):
+        O.project_bwd(wl.scene, c, opts, grad_rec[v * n:(v + 1) * n], og)
+    bad = {k: P.r24_violations(grads[k].cpu().numpy(), ref) for k, ref in og.items()}
+    print(" ", bad)
+    for k, (nb, worst) in bad.items():
+        assert nb == 0, (k, nb, worst)

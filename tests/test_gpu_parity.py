@@ -1,0 +1,78 @@
+"""HIP path vs the FP64 oracle, stage by stage, through the C ABI (GPU only)."""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2501_14534_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2501_14534_amd import gs
+    gs.load()
+
+
+def _cases():
+    return {
+        "tiny_masked": lambda: scenes.tiny(n=300, seed=1, width=70, height=45, deg=3, masks=True, band_masks=True),
+        "cfg1": lambda: scenes.config(1),
+        "cfg2_small": lambda: scenes.scaled(2, n=20000, shrink=4),
+        "cfg3_small": lambda: scenes.scaled(3, n=40000, shrink=8),
+        "cfg4_small": lambda: scenes.scaled(4, n=20000, shrink=4),
+        "cfg5_small": lambda: scenes.scaled(5, n=60000, views=[0, 4], shrink=8),
+    }
+
+
+CASES = _cases()
+
+
+@pytest.fixture(scope="module")
+def P():
+    from tests import parity
+    return parity
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_project_parity(P, case):
+    wl = CASES[case]()
+    print(f"[project] {case}: n={wl.scene.n} views={len(wl.cams)}", flush=True)
+    r, _ = P.gpu_forward(wl)
+    res = P.check_projection(wl, wl.opts, r)
+    print(res)
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_bin_sort_bit_exact(P, case):
+    wl = CASES[case]()
+    print(f"[bin_sort] {case}", flush=True)
+    r, _ = P.gpu_forward(wl)
+    gl = P.check_binning(wl, wl.opts, r)
+    assert gl["K"] > 0
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_render_fwd_parity(P, case):
+    wl = CASES[case]()
+    print(f"[render_fwd] {case}", flush=True)
+    r, _ = P.gpu_forward(wl)
+    res = P.check_forward(wl, wl.opts, r)
+    print({k: v for k, v in res.items() if k not in ("fw", "flagged")})
+    assert res["flagged_frac"] <= 1e-3
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_render_bwd_parity(P, case):
+    wl = CASES[case]()
+    print(f"[render_bwd] {case}", flush=True)
+    r, params = P.gpu_forward(wl)
+    fwd = P.check_forward(wl, wl.opts, r)
+    res = P.check_backward(wl, wl.opts, r, params, fwd["flagged"], seed=3)
+    print(res)
+    for k, (bad, worst) in res.items():
+        assert bad == 0, (k, bad, worst)
