@@ -47,7 +47,10 @@ def parse():
     ap.add_argument("--tile", type=str, default=None, help="WxH tile override, e.g. 16x16")
     ap.add_argument("--batch-depth", type=int, default=None)
     ap.add_argument("--ppt", type=int, default=None)
+    ap.add_argument("--cull", type=int, default=None, choices=[0, 1], help="sub-tile culling override")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target CPU work of the oracle sample")
+    ap.add_argument("--calibration-copy-bytes", type=int, default=0,
+                    help="also launch a plain copy kernel (elementwise x1) of this many bytes, for counter scaling")
     return ap.parse_args()
 
 
@@ -94,6 +97,13 @@ def main():
     gs.load()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.calibration_copy_bytes > 0:
+        src = torch.ones(args.calibration_copy_bytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
 
     wl = scenes.config(args.config)
     opts = autotune.best_opts(wl)
@@ -104,6 +114,8 @@ def main():
         opts = dataclasses.replace(opts, batch_depth=args.batch_depth)
     if args.ppt:
         opts = dataclasses.replace(opts, pixels_per_thread=args.ppt)
+    if args.cull is not None:
+        opts = dataclasses.replace(opts, subtile_cull=args.cull)
     sc = wl.scene
     V = len(wl.cams)
     pixels = wl.pixels
@@ -169,12 +181,11 @@ def main():
     stream = torch.cuda.current_stream()
     names = ["project", "bin_sort", "render_fwd", "blend_bwd", "project_bwd"]
     acc = {k: 0.0 for k in names}
-    grad_rec = torch.zeros(V * sc.n * gs.GRAD_FLOATS, dtype=torch.float32, device=dev)
+    grad_pair = torch.zeros(r.capacity * gs.GRAD_FLOATS, dtype=torch.float32, device=dev)
     nrep = max(3, min(args.steps, 10))
     dL = step.dL
     for _ in range(nrep):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
-        grad_rec.zero_()
         for g in step.grads.values():
             g.zero_()
         ev[0].record(stream)
@@ -184,9 +195,9 @@ def main():
         ev[2].record(stream)
         r.render_fwd()
         ev[3].record(stream)
-        r.blend_bwd(dL, grad_rec)
+        r.blend_bwd(dL, grad_pair)
         ev[4].record(stream)
-        r.project_bwd(params, grad_rec, step.grads)
+        r.project_bwd(params, grad_pair, step.grads)
         ev[5].record(stream)
         torch.cuda.synchronize()
         for i, k in enumerate(names):
@@ -242,7 +253,8 @@ def main():
         "config": {"workload": wl.name, "gaussians": sc.n, "views": V, "pixels_per_step": pixels,
                    "resolutions": [f"{c.width}x{c.height}" for c in wl.cams], "sh_degree": sc.sh_degree,
                    "tile": f"{opts.tile_w}x{opts.tile_h}", "batch_depth": opts.batch_depth,
-                   "pixels_per_thread": opts.pixels_per_thread, "graph": not args.no_graph},
+                   "pixels_per_thread": opts.pixels_per_thread, "subtile_cull": opts.subtile_cull,
+                   "graph": not args.no_graph},
         "per_view": per_view,
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "pairs": K,

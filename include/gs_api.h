@@ -89,6 +89,8 @@ typedef struct gs_opts {
   int32_t tile_h;    /* tile height in pixels, power of two; tile_w*tile_h in [64, 1024]   */
   int32_t batch_depth;       /* splats staged per tile batch, 1..GS_MAX_BATCH              */
   int32_t pixels_per_thread; /* 1, 2 or 4; tile_w*tile_h/ppt a multiple of 64, <= 256      */
+  int32_t subtile_cull;      /* 1: each wave walks only the splats whose alpha >= 1/255
+                                footprint can reach its pixels (same result, less work); 0: off */
 } gs_opts;
 
 /* Projected (view, Gaussian) records, written by gs_project.
@@ -106,10 +108,16 @@ typedef struct gs_projected {
   uint32_t* tiles_touched;
 } gs_projected;
 
-/* Sorted (tile, depth) lists.  keys/ids hold `capacity` entries; after a
- * successful gs_bin_sort the first K = *count are sorted by key, then by id:
+/* Sorted (tile, depth) lists.  keys/ids/pair_index hold `capacity` entries;
+ * after a successful gs_bin_sort the first K = *count are sorted by key, then
+ * by id:
  *   key = (global tile << 32) | IEEE bits of the record's depth
  *   id  = record index (view * n + gaussian)
+ *   pair_index = position of the pair in emission order, where each record's
+ *                pairs are contiguous, records in index order, and a record's
+ *                tiles in row-major order of its tile rectangle
+ * offsets: [V*n] first emission position of each record's pairs (its
+ *          tiles_touched consecutive positions follow).
  * ranges: [total_tiles][2] = [start, end) into keys/ids, [0,0) when empty.
  * count, status: device words written by gs_bin_sort.  status = 0 on success,
  * 1 when K > capacity: then no list is written, every range is empty and
@@ -117,6 +125,8 @@ typedef struct gs_projected {
 typedef struct gs_binning {
   uint64_t* keys;
   uint32_t* ids;
+  uint32_t* pair_index;
+  uint32_t* offsets;
   uint32_t* ranges;
   uint64_t capacity; /* < 2^32 */
   uint32_t* count;   /* device, 1 word */
@@ -176,10 +186,13 @@ int gs_render_fwd(const gs_projected* proj, const gs_binning* bins, const gs_cam
 
 /* Backward of gs_render_fwd and gs_project for dL/dimage (layout of image):
  * each tile's list is walked back to front from its largest last_contrib,
- * transmittance recovered by division, per-splat partials reduced across the
- * wave and the workgroup before one atomic per attribute per (tile, splat),
- * then the chain rule to the raw parameters including the straight-through
- * mask gradients (Eq. 3, Eq. 5).  Gradients are accumulated into `grads`.
+ * transmittance recovered by division; per (tile, splat) the 9 partials are
+ * summed over the workgroup's pixels in a fixed order and stored once, at the
+ * pair's emission position; then, per Gaussian, its pairs are summed in
+ * emission order and the chain rule runs to the raw parameters including the
+ * straight-through mask gradients (Eq. 3, Eq. 5).  No atomics: the result is
+ * bitwise reproducible, and a batched call equals the sum of per-view calls
+ * made in view order.  Gradients are accumulated into `grads`.
  * Needs ws_bytes >= gs_workspace_size(...). */
 int gs_render_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t V, const gs_opts* opts,
                   const gs_projected* proj, const gs_binning* bins, const float* T_final,
@@ -187,16 +200,18 @@ int gs_render_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t V, const
                   size_t ws_bytes, gs_stream_t stream);
 
 /* The two halves of gs_render_bwd, for callers that schedule or time them
- * separately.  gs_blend_bwd: the per-tile back-to-front walk only; ADDS the
- * per-record splat gradients (u, v, A, B, C, o', r, g, b) into grad_rec
- * ([V*n][9], caller-zeroed).  gs_project_bwd: the chain rule from grad_rec
- * to the raw parameters (same math as the second half of gs_render_bwd),
- * accumulated into `grads`.                                                 */
+ * separately.  gs_blend_bwd: the per-tile back-to-front walk only; WRITES
+ * the per-pair splat gradients (u, v, A, B, C, o', r, g, b) of all K pairs
+ * to grad_pair ([capacity][9], indexed by pair_index; no zeroing needed).
+ * gs_project_bwd: per Gaussian, the sum of its pairs' gradients in emission
+ * order, then the chain rule to the raw parameters (the second half of
+ * gs_render_bwd), accumulated into `grads`.                                */
 int gs_blend_bwd(const gs_camera* cams, int32_t V, int64_t n, const gs_opts* opts, const gs_projected* proj,
                  const gs_binning* bins, const float* T_final, const int32_t* last_contrib, const float* dL_dimage,
-                 float* grad_rec, gs_stream_t stream);
+                 float* grad_pair, gs_stream_t stream);
 int gs_project_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t V, const gs_opts* opts,
-                   const float* grad_rec, gs_grads* grads, gs_stream_t stream);
+                   const gs_projected* proj, const gs_binning* bins, const float* grad_pair, gs_grads* grads,
+                   gs_stream_t stream);
 
 /* Static description of a return code. */
 const char* gs_strerror(int code);

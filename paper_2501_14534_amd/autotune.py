@@ -15,13 +15,13 @@ from typing import Dict, Iterable, List, Optional, Tuple
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "autotune_cache.json")
 
-# (tile_w, tile_h, batch_depth, pixels_per_thread)
-CANDIDATES: List[Tuple[int, int, int, int]] = [
-    (16, 16, 256, 1), (16, 16, 128, 1), (16, 16, 64, 1),
-    (16, 16, 256, 2), (16, 16, 128, 2),
-    (16, 16, 256, 4), (16, 16, 128, 4), (16, 16, 64, 4),
-    (8, 8, 64, 1), (16, 8, 128, 1), (16, 8, 128, 2), (32, 8, 256, 1), (32, 8, 128, 2),
-    (32, 16, 256, 2), (32, 16, 256, 4),
+# (tile_w, tile_h, batch_depth, pixels_per_thread, subtile_cull)
+CANDIDATES: List[Tuple[int, int, int, int, int]] = [
+    (16, 16, 256, 1, 0), (16, 16, 256, 1, 1), (16, 16, 128, 1, 1), (16, 16, 64, 1, 1),
+    (16, 16, 256, 2, 1), (16, 16, 128, 2, 1), (16, 16, 64, 2, 1),
+    (16, 16, 256, 4, 1), (16, 16, 128, 4, 1), (16, 16, 64, 4, 1), (16, 16, 32, 4, 1),
+    (8, 8, 64, 1, 1), (8, 8, 32, 1, 1), (16, 8, 128, 1, 1), (16, 8, 64, 2, 1), (32, 8, 256, 1, 1),
+    (32, 8, 128, 2, 1), (32, 16, 256, 2, 1), (32, 16, 128, 4, 1),
 ]
 
 
@@ -56,11 +56,11 @@ def best_opts(wl, arch: Optional[str] = None):
     if not e:
         return wl.opts
     return dataclasses.replace(wl.opts, tile_w=e["tile_w"], tile_h=e["tile_h"], batch_depth=e["batch_depth"],
-                               pixels_per_thread=e["pixels_per_thread"])
+                               pixels_per_thread=e["pixels_per_thread"], subtile_cull=e.get("subtile_cull", 1))
 
 
-def tune(wl, candidates: Iterable[Tuple[int, int, int, int]] = CANDIDATES, steps: int = 5, warmup: int = 2,
-         write: bool = True, verbose: bool = True) -> dict:
+def tune(wl, candidates: Iterable[Tuple[int, int, int, int, int]] = CANDIDATES, steps: int = 5, warmup: int = 2,
+         write: bool = True, verbose: bool = True, cache_path: Optional[str] = None) -> dict:
     """Time each candidate's fwd+bwd step and store the fastest in the cache."""
     import time
 
@@ -74,8 +74,9 @@ def tune(wl, candidates: Iterable[Tuple[int, int, int, int]] = CANDIDATES, steps
     target = torch.from_numpy(np.concatenate([t.reshape(-1) for t in wl.targets])).cuda()
     results = []
     ref_img = None
-    for tw, th, bd, ppt in candidates:
-        o = dataclasses.replace(wl.opts, tile_w=tw, tile_h=th, batch_depth=bd, pixels_per_thread=ppt)
+    for tw, th, bd, ppt, cull in candidates:
+        o = dataclasses.replace(wl.opts, tile_w=tw, tile_h=th, batch_depth=bd, pixels_per_thread=ppt,
+                                subtile_cull=cull)
         r = raster.Rasterizer(sc.n, sc.sh_degree, wl.cams, o, mask_eps=sc.mask_eps, sh_mask_eps=sc.sh_mask_eps)
         st = raster.Step(r, params, target, graph=True)
         st.run()
@@ -91,16 +92,36 @@ def tune(wl, candidates: Iterable[Tuple[int, int, int, int]] = CANDIDATES, steps
         if ref_img is None:
             ref_img = img
         same = bool(torch.equal(img, ref_img))
-        results.append(dict(tile_w=tw, tile_h=th, batch_depth=bd, pixels_per_thread=ppt, ms=ms, image_equal=same))
+        results.append(dict(tile_w=tw, tile_h=th, batch_depth=bd, pixels_per_thread=ppt, subtile_cull=cull, ms=ms,
+                            image_equal=same))
         if verbose:
-            print(f"  tile {tw}x{th} batch {bd} ppt {ppt}: {ms:.3f} ms/step, image identical: {same}", flush=True)
+            print(f"  tile {tw}x{th} batch {bd} ppt {ppt} cull {cull}: {ms:.3f} ms/step, image identical: {same}",
+                  flush=True)
         del st, r
         torch.cuda.empty_cache()
     ok = [x for x in results if x["image_equal"]]
     best = min(ok, key=lambda x: x["ms"])
     if write:
-        cache = load_cache()
+        path = cache_path or CACHE
+        cache = json.load(open(path)) if os.path.exists(path) else {}
         cache[f"{_arch()}|{workload_key(wl)}"] = best
-        with open(CACHE, "w") as f:
+        with open(path, "w") as f:
             json.dump(cache, f, indent=1, sort_keys=True)
     return dict(best=best, results=results)
+
+
+if __name__ == "__main__":
+    import argparse
+
+    from . import scenes
+
+    ap = argparse.ArgumentParser(description="time the candidate launch shapes of a workload and cache the fastest")
+    ap.add_argument("--config", type=int, nargs="+", default=[4])
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--cache", default=None, help="cache file to update (default: the package cache)")
+    a = ap.parse_args()
+    for k in a.config:
+        wl = scenes.config(k)
+        print(f"workload {k}: {wl.name}", flush=True)
+        res = tune(wl, steps=a.steps, cache_path=a.cache)
+        print(f"best: {res['best']}", flush=True)

@@ -105,12 +105,16 @@ __global__ __launch_bounds__(1024) void scan_top(const uint32_t* __restrict__ su
   }
 }
 
+// Emission: pair e of record r (e in [offsets[r], offsets[r] + tiles_touched[r]),
+// the record's tiles in row-major order) gets key (tile << 32 | depth bits),
+// value e, and owner[e] = r.
 __global__ __launch_bounds__(kScanThreads) void emit_keys(const float4* __restrict__ splats,
                                                           const uint32_t* __restrict__ tt, int64_t nrec, int64_t n,
                                                           const uint32_t* __restrict__ block_offsets,
                                                           const int32_t* __restrict__ status, ViewTable vt,
                                                           float inv_tw, float inv_th, uint64_t* __restrict__ keys,
-                                                          uint32_t* __restrict__ ids) {
+                                                          uint32_t* __restrict__ vals, uint32_t* __restrict__ owner,
+                                                          uint32_t* __restrict__ offsets) {
   __shared__ uint32_t s_wave[kScanThreads / kWave];
   __shared__ uint32_t s_pref[kScanTile];
   __shared__ uint32_t s_base[kScanTile];
@@ -151,6 +155,11 @@ __global__ __launch_bounds__(kScanThreads) void emit_keys(const float4* __restri
   }
   __syncthreads();
   const uint32_t out0 = block_offsets[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t r = blk + li0 + k;
+    if (r < nrec) offsets[r] = out0 + s_pref[li0 + k];
+  }
   for (uint32_t slot = threadIdx.x; slot < total; slot += kScanThreads) {
     // last record whose exclusive prefix is <= slot
     int lo = 0, hi = kScanTile;  // invariant: s_pref[lo] <= slot < s_pref[hi] (virtual s_pref[kScanTile] = total)
@@ -162,8 +171,10 @@ __global__ __launch_bounds__(kScanThreads) void emit_keys(const float4* __restri
     const uint32_t w = s_w[lo];
     const uint32_t ty = j / w, tx = j - ty * w;
     const uint32_t gt = s_base[lo] + ty * s_tx[lo] + tx;
-    keys[(uint64_t)out0 + slot] = ((uint64_t)gt << 32) | s_depth[lo];
-    ids[(uint64_t)out0 + slot] = (uint32_t)(blk + lo);
+    const uint32_t e = out0 + slot;
+    keys[e] = ((uint64_t)gt << 32) | s_depth[lo];
+    vals[e] = e;
+    owner[e] = (uint32_t)(blk + lo);
   }
 }
 
@@ -284,11 +295,15 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter(const uint64_t* __
   }
 }
 
-__global__ void tile_ranges(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ count,
-                            const int32_t* __restrict__ status, uint32_t* __restrict__ ranges) {
+// Per sorted pair: record id from its emission position, and the tile's run boundaries.
+__global__ void tile_ranges(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ pair_index,
+                            const uint32_t* __restrict__ owner, const uint32_t* __restrict__ count,
+                            const int32_t* __restrict__ status, uint32_t* __restrict__ ids,
+                            uint32_t* __restrict__ ranges) {
   const uint32_t K = effective_count(count, status);
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= K) return;
+  ids[i] = owner[pair_index[i]];
   const uint32_t t = (uint32_t)(keys[i] >> 32);
   if (i == 0 || (uint32_t)(keys[i - 1] >> 32) != t) ranges[2 * (int64_t)t] = (uint32_t)i;
   if (i == (int64_t)K - 1 || (uint32_t)(keys[i + 1] >> 32) != t) ranges[2 * (int64_t)t + 1] = (uint32_t)(i + 1);
@@ -311,7 +326,8 @@ struct SortWs {
   uint32_t* block_sums;
   uint32_t* block_offsets;
   uint64_t* keys_alt;
-  uint32_t* ids_alt;
+  uint32_t* vals_alt;
+  uint32_t* owner;
   uint32_t* hist;
   uint32_t* digit_total;
   size_t bytes;
@@ -324,7 +340,8 @@ static SortWs carve(const SortPlan& p, uint64_t capacity, void* ws) {
   w.block_sums = (uint32_t*)(b + o), o += align256(sizeof(uint32_t) * (size_t)p.scan_blocks);
   w.block_offsets = (uint32_t*)(b + o), o += align256(sizeof(uint32_t) * (size_t)p.scan_blocks);
   w.keys_alt = (uint64_t*)(b + o), o += align256(sizeof(uint64_t) * (size_t)capacity);
-  w.ids_alt = (uint32_t*)(b + o), o += align256(sizeof(uint32_t) * (size_t)capacity);
+  w.vals_alt = (uint32_t*)(b + o), o += align256(sizeof(uint32_t) * (size_t)capacity);
+  w.owner = (uint32_t*)(b + o), o += align256(sizeof(uint32_t) * (size_t)capacity);
   w.hist = (uint32_t*)(b + o), o += align256(sizeof(uint32_t) * kRadix * (size_t)p.sort_blocks);
   w.digit_total = (uint32_t*)(b + o), o += align256(sizeof(uint32_t) * kRadix);
   w.bytes = o;
@@ -336,25 +353,27 @@ size_t bin_sort_ws_bytes(const SortPlan& p) {
 }
 
 hipError_t launch_bin_sort(const SortPlan& plan, const float4* splats, const uint32_t* tiles_touched, int64_t n,
-                           const ViewTable& vt, float inv_tw, float inv_th, uint64_t* keys, uint32_t* ids,
-                           uint32_t* ranges, uint64_t capacity, uint32_t* count, int32_t* status, void* ws,
-                           hipStream_t s) {
+                           const ViewTable& vt, float inv_tw, float inv_th, const BinOut& out, uint64_t capacity,
+                           void* ws, hipStream_t s) {
   const SortWs w = carve(plan, (uint64_t)plan.sort_blocks * kSortTile, ws);
   hipError_t e;
-  if ((e = launch_fill_u32(ranges, 2 * (int64_t)vt.total_tiles, 0u, s)) != hipSuccess) return e;
+  if ((e = launch_fill_u32(out.ranges, 2 * (int64_t)vt.total_tiles, 0u, s)) != hipSuccess) return e;
   const int64_t nb = plan.scan_blocks;
   if (nb > 0) {
     hipLaunchKernelGGL(count_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, tiles_touched, plan.nrec,
                        w.block_sums);
   }
-  hipLaunchKernelGGL(scan_top, dim3(1), dim3(1024), 0, s, w.block_sums, nb, w.block_offsets, capacity, count, status);
-  // ping-pong so that the last pass lands in (keys, ids)
-  uint64_t* kbuf[2] = {keys, w.keys_alt};
-  uint32_t* vbuf[2] = {ids, w.ids_alt};
+  hipLaunchKernelGGL(scan_top, dim3(1), dim3(1024), 0, s, w.block_sums, nb, w.block_offsets, capacity, out.count,
+                     out.status);
+  // ping-pong so that the last pass lands in (keys, pair_index)
+  uint64_t* kbuf[2] = {out.keys, w.keys_alt};
+  uint32_t* vbuf[2] = {out.pair_index, w.vals_alt};
   int cur = (plan.passes % 2 == 0) ? 0 : 1;
+  uint32_t* count = out.count;
+  int32_t* status = out.status;
   if (nb > 0) {
     hipLaunchKernelGGL(emit_keys, dim3((unsigned)nb), dim3(kScanThreads), 0, s, splats, tiles_touched, plan.nrec, n,
-                       w.block_offsets, status, vt, inv_tw, inv_th, kbuf[cur], vbuf[cur]);
+                       w.block_offsets, status, vt, inv_tw, inv_th, kbuf[cur], vbuf[cur], w.owner, out.offsets);
   }
   const int64_t sb = plan.sort_blocks;
   for (int p = 0; p < plan.passes && sb > 0; ++p) {
@@ -368,7 +387,8 @@ hipError_t launch_bin_sort(const SortPlan& plan, const float4* splats, const uin
   }
   const int64_t cap_blocks = ((int64_t)capacity + 255) / 256;
   if (cap_blocks > 0)
-    hipLaunchKernelGGL(tile_ranges, dim3((unsigned)cap_blocks), dim3(256), 0, s, keys, count, status, ranges);
+    hipLaunchKernelGGL(tile_ranges, dim3((unsigned)cap_blocks), dim3(256), 0, s, out.keys, out.pair_index, w.owner,
+                       count, status, out.ids, out.ranges);
   return hipGetLastError();
 }
 

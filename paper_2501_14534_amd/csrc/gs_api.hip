@@ -51,6 +51,7 @@ bool opts_ok(const gs_opts* o) {
   if (px % (64 * o->pixels_per_thread) != 0) return false;
   if (px / o->pixels_per_thread > 256) return false;  // render kernels run <= 256 threads per tile
   if (o->batch_depth < 1 || o->batch_depth > GS_MAX_BATCH) return false;
+  if (o->subtile_cull != 0 && o->subtile_cull != 1) return false;
   if (!std::isfinite(o->lowpass) || o->lowpass < 0.0f) return false;
   if (!std::isfinite(o->near_plane)) return false;
   if (!(o->tan_clamp > 0.0f)) return false;
@@ -127,27 +128,41 @@ RenderArgs render_args(const gs_projected* p, const gs_binning* b, const gs_opts
   RenderArgs a;
   a.splats = (const float4*)p->splats;
   a.ids = b->ids;
+  a.pair_index = b->pair_index;
   a.ranges = b->ranges;
   a.status = b->status;
   a.log2_tw = ilog2(o->tile_w);
   a.log2_th = ilog2(o->tile_h);
   a.batch = o->batch_depth;
   a.ppt = o->pixels_per_thread;
+  a.cull = o->subtile_cull;
   for (int c = 0; c < 3; ++c) a.bg[c] = o->bg[c];
   return a;
 }
 
 int launched(hipError_t e) { return e == hipSuccess ? GS_OK : GS_E_HIP; }
 
-ProjectBwdArgs project_bwd_args(ProjectArgs pa, const gs_opts* opts, const float* grad_rec, const gs_grads* grads,
-                                int deg) {
+bool binning_ok(const gs_binning* b, int64_t nrec) {
+  if (!b || !b->ranges || !b->count || !b->status || b->capacity >= (1ull << 32)) return false;
+  if (b->capacity > 0 && (!b->keys || !b->ids || !b->pair_index)) return false;
+  if (nrec > 0 && !b->offsets) return false;
+  return true;
+}
+
+size_t grad_pair_bytes(uint64_t capacity) { return align256(sizeof(float) * GS_GRAD_FLOATS * (size_t)capacity); }
+
+ProjectBwdArgs project_bwd_args(ProjectArgs pa, const gs_opts* opts, const gs_projected* proj, const gs_binning* bins,
+                                const float* grad_pair, const gs_grads* grads, int deg) {
   pa.near_plane = opts->near_plane;
   pa.lowpass = opts->lowpass;
   pa.inv_tw = 1.0f / (float)opts->tile_w;
   pa.inv_th = 1.0f / (float)opts->tile_h;
   ProjectBwdArgs b;
   b.p = pa;
-  b.grad_rec = grad_rec;
+  b.grad_pair = grad_pair;
+  b.tiles_touched = proj->tiles_touched;
+  b.offsets = bins->offsets;
+  b.status = bins->status;
   b.g_means = grads->means;
   b.g_log_scales = grads->log_scales;
   b.g_quats = grads->quats;
@@ -190,7 +205,7 @@ size_t gs_workspace_size(int64_t n, int32_t V, const gs_camera* cams, const gs_o
   if (n < 0 || capacity >= (1ull << 32) || !view_table(cams, V, opts, &vt, nullptr)) return 0;
   const SortPlan p = sort_plan(n, V, vt.total_tiles, capacity);
   const size_t sort_bytes = bin_sort_ws_bytes(p);
-  const size_t bwd_bytes = align256(sizeof(float) * GS_GRAD_FLOATS * (size_t)V * (size_t)n);
+  const size_t bwd_bytes = grad_pair_bytes(capacity);
   return sort_bytes > bwd_bytes ? sort_bytes : bwd_bytes;
 }
 
@@ -215,26 +230,33 @@ int gs_project(const gs_gaussians* g, const gs_camera* cams, int32_t V, const gs
 int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int32_t V, int64_t n, const gs_opts* opts,
                 gs_binning* out, void* ws, size_t ws_bytes, gs_stream_t stream) {
   ViewTable vt;
-  if (!proj || !out || n < 0 || n >= (1ll << 31) || !view_table(cams, V, opts, &vt, nullptr)) return GS_E_INVALID;
+  if (!proj || n < 0 || n >= (1ll << 31) || !view_table(cams, V, opts, &vt, nullptr)) return GS_E_INVALID;
   if ((int64_t)V * n >= (1ll << 32)) return GS_E_INVALID;
   if (n > 0 && (!proj->splats || !proj->tiles_touched)) return GS_E_INVALID;
-  if (!out->ranges || !out->count || !out->status || out->capacity >= (1ull << 32)) return GS_E_INVALID;
-  if (out->capacity > 0 && (!out->keys || !out->ids)) return GS_E_INVALID;
+  if (!binning_ok(out, (int64_t)V * n)) return GS_E_INVALID;
   if (ws_bytes < gs_workspace_size(n, V, cams, opts, out->capacity) || (!ws && ws_bytes > 0)) return GS_E_INVALID;
   const int d = device_ok();
   if (d != GS_OK) return d;
   const SortPlan p = sort_plan(n, V, vt.total_tiles, out->capacity);
+  BinOut bo;
+  bo.keys = out->keys;
+  bo.ids = out->ids;
+  bo.pair_index = out->pair_index;
+  bo.offsets = out->offsets;
+  bo.ranges = out->ranges;
+  bo.count = out->count;
+  bo.status = out->status;
   return launched(launch_bin_sort(p, (const float4*)proj->splats, proj->tiles_touched, n, vt,
-                                  1.0f / (float)opts->tile_w, 1.0f / (float)opts->tile_h, out->keys, out->ids,
-                                  out->ranges, out->capacity, out->count, out->status, ws, (hipStream_t)stream));
+                                  1.0f / (float)opts->tile_w, 1.0f / (float)opts->tile_h, bo, out->capacity, ws,
+                                  (hipStream_t)stream));
 }
 
 int gs_render_fwd(const gs_projected* proj, const gs_binning* bins, const gs_camera* cams, int32_t V, int64_t n,
                   const gs_opts* opts, float* image, float* T_final, int32_t* last_contrib, gs_stream_t stream) {
   ViewTable vt;
-  if (!proj || !bins || n < 0 || !view_table(cams, V, opts, &vt, nullptr)) return GS_E_INVALID;
-  if (!image || !T_final || !last_contrib || !bins->ranges || !bins->status) return GS_E_INVALID;
-  if (n > 0 && (!proj->splats || (bins->capacity > 0 && !bins->ids))) return GS_E_INVALID;
+  if (!proj || n < 0 || !view_table(cams, V, opts, &vt, nullptr)) return GS_E_INVALID;
+  if (!image || !T_final || !last_contrib || !binning_ok(bins, (int64_t)V * n)) return GS_E_INVALID;
+  if (n > 0 && !proj->splats) return GS_E_INVALID;
   const int d = device_ok();
   if (d != GS_OK) return d;
   const RenderArgs a = render_args(proj, bins, opts);
@@ -248,46 +270,47 @@ int gs_render_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t V, const
   ProjectArgs pa;
   ViewTable vt;
   if (!gaussians_ok(g, &pa) || !view_table(cams, V, opts, &vt, nullptr)) return GS_E_INVALID;
-  if (!proj || !bins || !T_final || !last_contrib || !dL_dimage || !grads) return GS_E_INVALID;
-  if (!bins->ranges || !bins->status) return GS_E_INVALID;
-  if (g->n > 0 && (!proj->splats || (bins->capacity > 0 && !bins->ids))) return GS_E_INVALID;
-  const size_t need = align256(sizeof(float) * GS_GRAD_FLOATS * (size_t)V * (size_t)g->n);
+  if (!proj || !T_final || !last_contrib || !dL_dimage || !grads) return GS_E_INVALID;
+  if (!binning_ok(bins, (int64_t)V * g->n)) return GS_E_INVALID;
+  if (g->n > 0 && (!proj->splats || !proj->tiles_touched)) return GS_E_INVALID;
+  const size_t need = grad_pair_bytes(bins->capacity);
   if (ws_bytes < need || (!ws && need > 0)) return GS_E_INVALID;
   const int d = device_ok();
   if (d != GS_OK) return d;
   hipStream_t s = (hipStream_t)stream;
-  float* grad_rec = (float*)ws;
-  hipError_t e = launch_fill_u32((uint32_t*)grad_rec, (int64_t)GS_GRAD_FLOATS * V * g->n, 0u, s);
-  if (e != hipSuccess) return GS_E_HIP;
+  float* grad_pair = (float*)ws;
   const RenderArgs ra = render_args(proj, bins, opts);
-  e = launch_render_bwd(ra, vt, T_final, last_contrib, dL_dimage, grad_rec, s);
+  hipError_t e = launch_render_bwd(ra, vt, T_final, last_contrib, dL_dimage, grad_pair, s);
   if (e != hipSuccess) return GS_E_HIP;
-  return launched(launch_project_bwd(project_bwd_args(pa, opts, grad_rec, grads, g->sh_degree), vt, g->sh_degree, s));
+  return launched(
+      launch_project_bwd(project_bwd_args(pa, opts, proj, bins, grad_pair, grads, g->sh_degree), vt, g->sh_degree, s));
 }
 
 int gs_blend_bwd(const gs_camera* cams, int32_t V, int64_t n, const gs_opts* opts, const gs_projected* proj,
                  const gs_binning* bins, const float* T_final, const int32_t* last_contrib, const float* dL_dimage,
-                 float* grad_rec, gs_stream_t stream) {
+                 float* grad_pair, gs_stream_t stream) {
   ViewTable vt;
   if (n < 0 || !view_table(cams, V, opts, &vt, nullptr)) return GS_E_INVALID;
-  if (!proj || !bins || !T_final || !last_contrib || !dL_dimage || !bins->ranges || !bins->status) return GS_E_INVALID;
-  if (n > 0 && (!proj->splats || !grad_rec || (bins->capacity > 0 && !bins->ids))) return GS_E_INVALID;
+  if (!proj || !T_final || !last_contrib || !dL_dimage || !binning_ok(bins, (int64_t)V * n)) return GS_E_INVALID;
+  if (n > 0 && (!proj->splats || !grad_pair)) return GS_E_INVALID;
   const int d = device_ok();
   if (d != GS_OK) return d;
   const RenderArgs ra = render_args(proj, bins, opts);
-  return launched(launch_render_bwd(ra, vt, T_final, last_contrib, dL_dimage, grad_rec, (hipStream_t)stream));
+  return launched(launch_render_bwd(ra, vt, T_final, last_contrib, dL_dimage, grad_pair, (hipStream_t)stream));
 }
 
 int gs_project_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t V, const gs_opts* opts,
-                   const float* grad_rec, gs_grads* grads, gs_stream_t stream) {
+                   const gs_projected* proj, const gs_binning* bins, const float* grad_pair, gs_grads* grads,
+                   gs_stream_t stream) {
   ProjectArgs pa;
   ViewTable vt;
   if (!gaussians_ok(g, &pa) || !view_table(cams, V, opts, &vt, nullptr)) return GS_E_INVALID;
-  if (!grads || (g->n > 0 && !grad_rec)) return GS_E_INVALID;
+  if (!proj || !grads || !binning_ok(bins, (int64_t)V * g->n)) return GS_E_INVALID;
+  if (g->n > 0 && (!grad_pair || !proj->tiles_touched)) return GS_E_INVALID;
   const int d = device_ok();
   if (d != GS_OK) return d;
-  return launched(launch_project_bwd(project_bwd_args(pa, opts, grad_rec, grads, g->sh_degree), vt, g->sh_degree,
-                                     (hipStream_t)stream));
+  return launched(launch_project_bwd(project_bwd_args(pa, opts, proj, bins, grad_pair, grads, g->sh_degree), vt,
+                                     g->sh_degree, (hipStream_t)stream));
 }
 
 }  // extern "C"

@@ -30,17 +30,32 @@ struct ProjectArgs {
 struct RenderArgs {
   const float4* splats;
   const uint32_t* ids;
+  const uint32_t* pair_index;
   const uint32_t* ranges;
   const int32_t* status;
   int32_t log2_tw, log2_th;
   int32_t batch;
   int32_t ppt;
+  int32_t cull;
   float bg[3];
 };
 
+struct BinOut {
+  uint64_t* keys;
+  uint32_t* ids;
+  uint32_t* pair_index;
+  uint32_t* offsets;
+  uint32_t* ranges;
+  uint32_t* count;
+  int32_t* status;
+};
+
 struct ProjectBwdArgs {
-  ProjectArgs p;           // forward inputs (outputs unused)
-  const float* grad_rec;   // [V*n][9]
+  ProjectArgs p;                   // forward inputs (outputs unused)
+  const float* grad_pair;          // [K][9], emission order
+  const uint32_t* tiles_touched;   // [V*n]
+  const uint32_t* offsets;         // [V*n] first emission position of each record
+  const int32_t* status;
   float* g_means;
   float* g_log_scales;
   float* g_quats;
@@ -64,15 +79,14 @@ struct SortPlan {
 hipError_t launch_project(const ProjectArgs& a, const ViewTable& vt, int deg, hipStream_t s);
 
 hipError_t launch_bin_sort(const SortPlan& plan, const float4* splats, const uint32_t* tiles_touched, int64_t n,
-                           const ViewTable& vt, float inv_tw, float inv_th, uint64_t* keys, uint32_t* ids,
-                           uint32_t* ranges, uint64_t capacity, uint32_t* count, int32_t* status, void* ws,
-                           hipStream_t s);
+                           const ViewTable& vt, float inv_tw, float inv_th, const BinOut& out, uint64_t capacity,
+                           void* ws, hipStream_t s);
 
 hipError_t launch_render_fwd(const RenderArgs& a, const ViewTable& vt, float* image, float* T_final,
                              int32_t* last_contrib, hipStream_t s);
 
 hipError_t launch_render_bwd(const RenderArgs& a, const ViewTable& vt, const float* T_final,
-                             const int32_t* last_contrib, const float* dL_dimage, float* grad_rec, hipStream_t s);
+                             const int32_t* last_contrib, const float* dL_dimage, float* grad_pair, hipStream_t s);
 
 hipError_t launch_project_bwd(const ProjectBwdArgs& a, const ViewTable& vt, int deg, hipStream_t s);
 

@@ -70,16 +70,11 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs b, View
   const int64_t n = a.n;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  if (*b.status != 0) return;  // binning overflowed: no lists, no gradients
   const int V = vt.nviews;
-
-  // Skip Gaussians that received no splat gradient in any view.
   bool any = false;
-  for (int v = 0; v < V && !any; ++v) {
-    const float* g = b.grad_rec + ((size_t)v * n + i) * GS_GRAD_FLOATS;
-#pragma unroll
-    for (int k = 0; k < GS_GRAD_FLOATS; ++k) any |= g[k] != 0.0f;
-  }
-  if (!any) return;  // culled records never receive splat gradients
+  for (int v = 0; v < V; ++v) any |= b.tiles_touched[(size_t)v * n + i] != 0u;
+  if (!any) return;  // culled or off-screen in every view
 
   float mu[3], ls[3], q[4], dc[3];
 #pragma unroll
@@ -111,142 +106,179 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs b, View
       for (int c = 0; c < 3; ++c) rest[k - 1][c] = a.sh_rest[((k - 1) * 3 + c) * n + i];
   }
 
-  // forward quantities shared by all views
-  const float qn = sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-  const float iq = 1.0f / qn;
-  const float w = q[0] * iq, x = q[1] * iq, y = q[2] * iq, z = q[3] * iq;
-  float Rq[3][3] = {{1.f - 2.f * (y * y + z * z), 2.f * (x * y - w * z), 2.f * (x * z + w * y)},
-                    {2.f * (x * y + w * z), 1.f - 2.f * (x * x + z * z), 2.f * (y * z - w * x)},
-                    {2.f * (x * z - w * y), 2.f * (y * z + w * x), 1.f - 2.f * (x * x + y * y)}};
-  float s[3];
+  // geometry shared by all views, in double precision (this kernel is bound by memory traffic)
+  const double q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3];
+  const double qn = sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+  const double iq = 1.0 / qn;
+  const double w = q0 * iq, x = q1 * iq, y = q2 * iq, z = q3 * iq;
+  const double Rq[3][3] = {{1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y)},
+                           {2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x)},
+                           {2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)}};
+  double s[3];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) s[k] = __expf(ls[k]);
-  float M[3][3];  // Rq diag(s)
+  for (int k = 0; k < 3; ++k) s[k] = exp((double)ls[k]);
+  double M[3][3];  // Rq diag(s)
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
     for (int k = 0; k < 3; ++k) M[r][k] = Rq[r][k] * s[k];
-  float Sig[3][3];
+  double Sig[3][3];
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
     for (int c = 0; c < 3; ++c) Sig[r][c] = M[r][0] * M[c][0] + M[r][1] * M[c][1] + M[r][2] * M[c][2];
-  const float op = sigmoidf(ol);
+  const double op = 1.0 / (1.0 + exp(-(double)ol));
+  double sm = 0.0;
+  if (a.mask_logits) sm = 1.0 / (1.0 + exp(-(double)a.mask_logits[i]));
 
-  // accumulated gradients
-  float gmu[3] = {0.f, 0.f, 0.f};
-  float gSig[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
-  float gop = 0.f;
-  float gdc[3] = {0.f, 0.f, 0.f};
-  float grest[NR][3];
-  float gbm[3] = {0.f, 0.f, 0.f};
+  // totals over views, single precision, added view by view (the association a
+  // sequence of per-view calls produces)
+  float tmu[3] = {0.f, 0.f, 0.f}, tls[3] = {0.f, 0.f, 0.f}, tq[4] = {0.f, 0.f, 0.f, 0.f};
+  float top = 0.f, tmask = 0.f, tdc[3] = {0.f, 0.f, 0.f}, tbm[3] = {0.f, 0.f, 0.f};
+  float trest[NR][3];
 #pragma unroll
-  for (int k = 0; k < NR; ++k) grest[k][0] = grest[k][1] = grest[k][2] = 0.f;
+  for (int k = 0; k < NR; ++k) trest[k][0] = trest[k][1] = trest[k][2] = 0.f;
 
   for (int v = 0; v < V; ++v) {
-    const float* gr = b.grad_rec + ((size_t)v * n + i) * GS_GRAD_FLOATS;
-    const float gu = gr[0], gv = gr[1], gA = gr[2], gB = gr[3], gC = gr[4], go = gr[5];
-    const float grgb[3] = {gr[6], gr[7], gr[8]};
+    const size_t r = (size_t)v * n + i;
+    const uint32_t cntp = b.tiles_touched[r];
+    if (cntp == 0) continue;
+    // this record's pairs, in emission order
+    double gsum[GS_GRAD_FLOATS] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const float* gp = b.grad_pair + (size_t)b.offsets[r] * GS_GRAD_FLOATS;
+    for (uint32_t k = 0; k < cntp; ++k)
+#pragma unroll
+      for (int c = 0; c < GS_GRAD_FLOATS; ++c) gsum[c] += (double)gp[(size_t)k * GS_GRAD_FLOATS + c];
     bool nz = false;
 #pragma unroll
-    for (int k = 0; k < GS_GRAD_FLOATS; ++k) nz |= gr[k] != 0.0f;
+    for (int c = 0; c < GS_GRAD_FLOATS; ++c) nz |= gsum[c] != 0.0;
     if (!nz) continue;
+    const double gu = gsum[0], gv = gsum[1], gA = gsum[2], gB = gsum[3], gC = gsum[4], go = gsum[5];
+    if (b.g_mean2d) {
+      b.g_mean2d[((size_t)v * 2 + 0) * n + i] += (float)gu;
+      b.g_mean2d[((size_t)v * 2 + 1) * n + i] += (float)gv;
+    }
     const ViewArgs& c = vt.v[v];
-    const float t0 = c.R[0] * mu[0] + c.R[1] * mu[1] + c.R[2] * mu[2] + c.t[0];
-    const float t1 = c.R[3] * mu[0] + c.R[4] * mu[1] + c.R[5] * mu[2] + c.t[1];
-    const float t2 = c.R[6] * mu[0] + c.R[7] * mu[1] + c.R[8] * mu[2] + c.t[2];
-    const float iz = 1.0f / t2;
-    const float ux = t0 * iz, uy = t1 * iz;
-    const bool inx = ux >= -c.limx && ux <= c.limx;
-    const bool iny = uy >= -c.limy && uy <= c.limy;
-    const float rx = fminf(fmaxf(ux, -c.limx), c.limx);
-    const float ry = fminf(fmaxf(uy, -c.limy), c.limy);
-    const float j00 = c.fx * iz, j02 = -c.fx * rx * iz, j11 = c.fy * iz, j12 = -c.fy * ry * iz;
-    float Tm[2][3];
+    double R[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) R[k] = c.R[k];
+    const double fx = c.fx, fy = c.fy;
+    const double t0 = R[0] * mu[0] + R[1] * mu[1] + R[2] * mu[2] + (double)c.t[0];
+    const double t1 = R[3] * mu[0] + R[4] * mu[1] + R[5] * mu[2] + (double)c.t[1];
+    const double t2 = R[6] * mu[0] + R[7] * mu[1] + R[8] * mu[2] + (double)c.t[2];
+    const double iz = 1.0 / t2;
+    const double ux = t0 * iz, uy = t1 * iz;
+    const double lx = c.limx, ly = c.limy;
+    const bool inx = ux >= -lx && ux <= lx;
+    const bool iny = uy >= -ly && uy <= ly;
+    const double rx = fmin(fmax(ux, -lx), lx);
+    const double ry = fmin(fmax(uy, -ly), ly);
+    const double j00 = fx * iz, j02 = -fx * rx * iz, j11 = fy * iz, j12 = -fy * ry * iz;
+    double Tm[2][3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      Tm[0][k] = j00 * c.R[k] + j02 * c.R[6 + k];
-      Tm[1][k] = j11 * c.R[3 + k] + j12 * c.R[6 + k];
+      Tm[0][k] = j00 * R[k] + j02 * R[6 + k];
+      Tm[1][k] = j11 * R[3 + k] + j12 * R[6 + k];
     }
-    float TS[2][3];  // T Sigma
+    double TS[2][3];  // T Sigma
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
+    for (int rr = 0; rr < 2; ++rr)
 #pragma unroll
-      for (int k = 0; k < 3; ++k) TS[r][k] = Tm[r][0] * Sig[0][k] + Tm[r][1] * Sig[1][k] + Tm[r][2] * Sig[2][k];
-    const float ca = TS[0][0] * Tm[0][0] + TS[0][1] * Tm[0][1] + TS[0][2] * Tm[0][2] + a.lowpass;
-    const float cb = TS[0][0] * Tm[1][0] + TS[0][1] * Tm[1][1] + TS[0][2] * Tm[1][2];
-    const float cc = TS[1][0] * Tm[1][0] + TS[1][1] * Tm[1][1] + TS[1][2] * Tm[1][2] + a.lowpass;
-    const float idet = 1.0f / (ca * cc - cb * cb);
-    const float QA = cc * idet, QB = -cb * idet, QC = ca * idet;
+      for (int k = 0; k < 3; ++k) TS[rr][k] = Tm[rr][0] * Sig[0][k] + Tm[rr][1] * Sig[1][k] + Tm[rr][2] * Sig[2][k];
+    const double ca = TS[0][0] * Tm[0][0] + TS[0][1] * Tm[0][1] + TS[0][2] * Tm[0][2] + (double)a.lowpass;
+    const double cb = TS[0][0] * Tm[1][0] + TS[0][1] * Tm[1][1] + TS[0][2] * Tm[1][2];
+    const double cc = TS[1][0] * Tm[1][0] + TS[1][1] * Tm[1][1] + TS[1][2] * Tm[1][2] + (double)a.lowpass;
+    const double idet = 1.0 / (ca * cc - cb * cb);
+    const double QA = cc * idet, QB = -cb * idet, QC = ca * idet;
     // dL/dSigma' = -Q G_Q Q
-    const float P00 = QA * gA + QB * 0.5f * gB, P01 = QA * 0.5f * gB + QB * gC;
-    const float P10 = QB * gA + QC * 0.5f * gB, P11 = QB * 0.5f * gB + QC * gC;
-    const float G00 = -(P00 * QA + P01 * QB);
-    const float G01 = -(P00 * QB + P01 * QC);
-    const float G11 = -(P10 * QB + P11 * QC);
-    // dL/dSigma += T^T G T
+    const double P00 = QA * gA + QB * 0.5 * gB, P01 = QA * 0.5 * gB + QB * gC;
+    const double P10 = QB * gA + QC * 0.5 * gB, P11 = QB * 0.5 * gB + QC * gC;
+    const double G00 = -(P00 * QA + P01 * QB);
+    const double G01 = -(P00 * QB + P01 * QC);
+    const double G11 = -(P10 * QB + P11 * QC);
+    // dL/dSigma = T^T G T
+    double gSig[3][3];
 #pragma unroll
-    for (int r = 0; r < 3; ++r)
+    for (int rr = 0; rr < 3; ++rr)
 #pragma unroll
       for (int k = 0; k < 3; ++k)
-        gSig[r][k] += Tm[0][r] * (G00 * Tm[0][k] + G01 * Tm[1][k]) + Tm[1][r] * (G01 * Tm[0][k] + G11 * Tm[1][k]);
-    // dL/dT = 2 G T Sigma
-    float gT[2][3];
+        gSig[rr][k] = Tm[0][rr] * (G00 * Tm[0][k] + G01 * Tm[1][k]) + Tm[1][rr] * (G01 * Tm[0][k] + G11 * Tm[1][k]);
+    // dL/dT = 2 G T Sigma; T = J W with J00, J02, J11, J12 varying
+    double gT[2][3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      gT[0][k] = 2.f * (G00 * TS[0][k] + G01 * TS[1][k]);
-      gT[1][k] = 2.f * (G01 * TS[0][k] + G11 * TS[1][k]);
+      gT[0][k] = 2.0 * (G00 * TS[0][k] + G01 * TS[1][k]);
+      gT[1][k] = 2.0 * (G01 * TS[0][k] + G11 * TS[1][k]);
     }
-    // T = J W: only J00, J02, J11, J12 vary
-    const float gj00 = gT[0][0] * c.R[0] + gT[0][1] * c.R[1] + gT[0][2] * c.R[2];
-    const float gj02 = gT[0][0] * c.R[6] + gT[0][1] * c.R[7] + gT[0][2] * c.R[8];
-    const float gj11 = gT[1][0] * c.R[3] + gT[1][1] * c.R[4] + gT[1][2] * c.R[5];
-    const float gj12 = gT[1][0] * c.R[6] + gT[1][1] * c.R[7] + gT[1][2] * c.R[8];
-    const float iz2 = iz * iz;
-    float gt0 = gu * c.fx * iz, gt1 = gv * c.fy * iz;
-    float gt2 = -gu * c.fx * t0 * iz2 - gv * c.fy * t1 * iz2;
-    gt2 += -gj00 * c.fx * iz2 - gj11 * c.fy * iz2;
-    // J02 = -fx rx / z with rx = clamp(x / z): d/dx = -fx/z^2 (unclamped), d/dz = fx rx/z^2 + fx x/z^3 (unclamped)
-    gt2 += gj02 * c.fx * rx * iz2 + gj12 * c.fy * ry * iz2;
+    const double gj00 = gT[0][0] * R[0] + gT[0][1] * R[1] + gT[0][2] * R[2];
+    const double gj02 = gT[0][0] * R[6] + gT[0][1] * R[7] + gT[0][2] * R[8];
+    const double gj11 = gT[1][0] * R[3] + gT[1][1] * R[4] + gT[1][2] * R[5];
+    const double gj12 = gT[1][0] * R[6] + gT[1][1] * R[7] + gT[1][2] * R[8];
+    const double iz2 = iz * iz;
+    double gt0 = gu * fx * iz, gt1 = gv * fy * iz;
+    double gt2 = -gu * fx * t0 * iz2 - gv * fy * t1 * iz2;
+    gt2 += -gj00 * fx * iz2 - gj11 * fy * iz2;
+    // J02 = -fx rx / z, rx = clamp(x / z): d/dx = -fx/z^2 (unclamped); d/dz = fx rx/z^2 (+ fx x/z^3 unclamped)
+    gt2 += gj02 * fx * rx * iz2 + gj12 * fy * ry * iz2;
     if (inx) {
-      gt0 += -gj02 * c.fx * iz2;
-      gt2 += gj02 * c.fx * t0 * iz2 * iz;
+      gt0 += -gj02 * fx * iz2;
+      gt2 += gj02 * fx * t0 * iz2 * iz;
     }
     if (iny) {
-      gt1 += -gj12 * c.fy * iz2;
-      gt2 += gj12 * c.fy * t1 * iz2 * iz;
+      gt1 += -gj12 * fy * iz2;
+      gt2 += gj12 * fy * t1 * iz2 * iz;
     }
+    double gmu[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) gmu[k] += c.R[k] * gt0 + c.R[3 + k] * gt1 + c.R[6 + k] * gt2;
-    gop += go;
-    if (b.g_mean2d) {
-      b.g_mean2d[((size_t)v * 2 + 0) * n + i] += gu;
-      b.g_mean2d[((size_t)v * 2 + 1) * n + i] += gv;
+    for (int k = 0; k < 3; ++k) gmu[k] = R[k] * gt0 + R[3 + k] * gt1 + R[6 + k] * gt2;
+    // Sigma = M M^T -> dL/dM = (G + G^T) M; scales and rotation
+    double gsc[3], gR[3][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+#pragma unroll
+      for (int c2 = 0; c2 < 3; ++c2) {
+        acc0 += (gSig[0][c2] + gSig[c2][0]) * M[c2][k];
+        acc1 += (gSig[1][c2] + gSig[c2][1]) * M[c2][k];
+        acc2 += (gSig[2][c2] + gSig[c2][2]) * M[c2][k];
+      }
+      gsc[k] = acc0 * Rq[0][k] + acc1 * Rq[1][k] + acc2 * Rq[2][k];
+      gR[0][k] = acc0 * s[k];
+      gR[1][k] = acc1 * s[k];
+      gR[2][k] = acc2 * s[k];
     }
-    // colour
-    float d0 = mu[0] - c.campos[0], d1 = mu[1] - c.campos[1], d2 = mu[2] - c.campos[2];
+    const double gw = 2.0 * (-z * gR[0][1] + y * gR[0][2] + z * gR[1][0] - x * gR[1][2] - y * gR[2][0] + x * gR[2][1]);
+    const double gx = 2.0 * (y * gR[0][1] + z * gR[0][2] + y * gR[1][0] - 2.0 * x * gR[1][1] - w * gR[1][2] +
+                             z * gR[2][0] + w * gR[2][1] - 2.0 * x * gR[2][2]);
+    const double gy = 2.0 * (-2.0 * y * gR[0][0] + x * gR[0][1] + w * gR[0][2] + x * gR[1][0] + z * gR[1][2] -
+                             w * gR[2][0] + z * gR[2][1] - 2.0 * y * gR[2][2]);
+    const double gz = 2.0 * (-2.0 * z * gR[0][0] - w * gR[0][1] + x * gR[0][2] + w * gR[1][0] - 2.0 * z * gR[1][1] +
+                             y * gR[1][2] + x * gR[2][0] + y * gR[2][1]);
+    const double qd = w * gw + x * gx + y * gy + z * gz;
+    // colour (single precision: sums of small products, well conditioned)
+    const float grgb[3] = {(float)gsum[6], (float)gsum[7], (float)gsum[8]};
+    float pre[3] = {dc[0], dc[1], dc[2]};
     float Y[15];
-    float il = 1.0f, dx = 0.f, dy = 0.f, dz = 0.f;
+    float dx = 0.f, dy = 0.f, dz = 0.f, il = 1.f;
     if (DEG > 0) {
+      const float d0 = mu[0] - c.campos[0], d1 = mu[1] - c.campos[1], d2 = mu[2] - c.campos[2];
       il = 1.0f / sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
       dx = d0 * il, dy = d1 * il, dz = d2 * il;
       sh_basis15(dx, dy, dz, Y);
-    }
-    float pre[3] = {dc[0], dc[1], dc[2]};
 #pragma unroll
-    for (int l = 1; l <= DEG; ++l) {
-      if (!band_on[l]) continue;
+      for (int l = 1; l <= DEG; ++l) {
+        if (!band_on[l]) continue;
 #pragma unroll
-      for (int k = l * l; k < (l + 1) * (l + 1); ++k)
+        for (int k = l * l; k < (l + 1) * (l + 1); ++k)
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) pre[ch] += Y[k - 1] * rest[k - 1][ch];
+          for (int ch = 0; ch < 3; ++ch) pre[ch] += Y[k - 1] * rest[k - 1][ch];
+      }
     }
     float gpre[3];
 #pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-      gpre[ch] = pre[ch] < 0.f ? 0.f : grgb[ch];
-      gdc[ch] += gpre[ch];
-    }
+    for (int ch = 0; ch < 3; ++ch) gpre[ch] = pre[ch] < 0.f ? 0.f : grgb[ch];
+    float gmu_col[3] = {0.f, 0.f, 0.f};
+    float gbm_v[3] = {0.f, 0.f, 0.f};
     if (DEG > 0) {
       float wY[15];
 #pragma unroll
@@ -258,80 +290,69 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs b, View
         for (int k = l * l; k < (l + 1) * (l + 1); ++k) {
           const float cg = rest[k - 1][0] * gpre[0] + rest[k - 1][1] * gpre[1] + rest[k - 1][2] * gpre[2];
           band += Y[k - 1] * cg;
-          if (band_on[l]) {
-            wY[k - 1] = cg;
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) grest[k - 1][ch] += Y[k - 1] * gpre[ch];
-          }
+          if (band_on[l]) wY[k - 1] = cg;
         }
-        gbm[l - 1] += band;
+        gbm_v[l - 1] = band;
       }
       float gdx, gdy, gdz;
       sh_grad15(dx, dy, dz, wY, &gdx, &gdy, &gdz);
       const float dot = dx * gdx + dy * gdy + dz * gdz;
-      gmu[0] += (gdx - dx * dot) * il;
-      gmu[1] += (gdy - dy * dot) * il;
-      gmu[2] += (gdz - dz * dot) * il;
+      gmu_col[0] = (gdx - dx * dot) * il;
+      gmu_col[1] = (gdy - dy * dot) * il;
+      gmu_col[2] = (gdz - dz * dot) * il;
     }
-  }
-
-  // Sigma = M M^T -> dL/dM = 2 G_Sigma M (G_Sigma symmetrised)
-  float gM[3][3];
-#pragma unroll
-  for (int r = 0; r < 3; ++r)
+    // add this view's contribution to the totals
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      float acc = 0.f;
-#pragma unroll
-      for (int c2 = 0; c2 < 3; ++c2) acc += (gSig[r][c2] + gSig[c2][r]) * M[c2][k];
-      gM[r][k] = acc;
+      tmu[k] += (float)(gmu[k] + (double)gmu_col[k]);
+      tls[k] += (float)(gsc[k] * s[k]);
+      tdc[k] += gpre[k];
     }
-  float gsc[3], gR[3][3];
+    tq[0] += (float)((gw - w * qd) * iq);
+    tq[1] += (float)((gx - x * qd) * iq);
+    tq[2] += (float)((gy - y * qd) * iq);
+    tq[3] += (float)((gz - z * qd) * iq);
+    top += (float)(go * op * (1.0 - op));
+    if (a.mask_logits) {
+      // o' = M o, s' = M s (M = 1 here): dL/dM = o dL/do' + sum_k s_k dL/ds'_k
+      tmask += (float)((go * op + gsc[0] * s[0] + gsc[1] * s[1] + gsc[2] * s[2]) * sm * (1.0 - sm));
+    }
+    if (DEG > 0) {
 #pragma unroll
-  for (int k = 0; k < 3; ++k) gsc[k] = gM[0][k] * Rq[0][k] + gM[1][k] * Rq[1][k] + gM[2][k] * Rq[2][k];
+      for (int l = 1; l <= DEG; ++l) {
+        if (band_on[l]) {
 #pragma unroll
-  for (int r = 0; r < 3; ++r)
+          for (int k = l * l; k < (l + 1) * (l + 1); ++k)
 #pragma unroll
-    for (int k = 0; k < 3; ++k) gR[r][k] = gM[r][k] * s[k];
-  const float gw = 2.f * (-z * gR[0][1] + y * gR[0][2] + z * gR[1][0] - x * gR[1][2] - y * gR[2][0] + x * gR[2][1]);
-  const float gx = 2.f * (y * gR[0][1] + z * gR[0][2] + y * gR[1][0] - 2.f * x * gR[1][1] - w * gR[1][2] +
-                          z * gR[2][0] + w * gR[2][1] - 2.f * x * gR[2][2]);
-  const float gy = 2.f * (-2.f * y * gR[0][0] + x * gR[0][1] + w * gR[0][2] + x * gR[1][0] + z * gR[1][2] -
-                          w * gR[2][0] + z * gR[2][1] - 2.f * y * gR[2][2]);
-  const float gz = 2.f * (-2.f * z * gR[0][0] - w * gR[0][1] + x * gR[0][2] + w * gR[1][0] - 2.f * z * gR[1][1] +
-                          y * gR[1][2] + x * gR[2][0] + y * gR[2][1]);
-  const float qd = w * gw + x * gx + y * gy + z * gz;
-  const float gq[4] = {(gw - w * qd) * iq, (gx - x * qd) * iq, (gy - y * qd) * iq, (gz - z * qd) * iq};
+            for (int ch = 0; ch < 3; ++ch) trest[k - 1][ch] += Y[k - 1] * gpre[ch];
+        }
+        const float sb = sigmoidf(bm[l - 1]);
+        tbm[l - 1] += gbm_v[l - 1] * sb * (1.f - sb);
+      }
+    }
+  }
 
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    if (b.g_means) b.g_means[k * n + i] += gmu[k];
-    if (b.g_log_scales) b.g_log_scales[k * n + i] += gsc[k] * s[k];
-    if (b.g_sh_dc) b.g_sh_dc[k * n + i] += gdc[k];
+    if (b.g_means) b.g_means[k * n + i] += tmu[k];
+    if (b.g_log_scales) b.g_log_scales[k * n + i] += tls[k];
+    if (b.g_sh_dc) b.g_sh_dc[k * n + i] += tdc[k];
   }
 #pragma unroll
   for (int k = 0; k < 4; ++k)
-    if (b.g_quats) b.g_quats[k * n + i] += gq[k];
-  if (b.g_opacity_logits) b.g_opacity_logits[i] += gop * op * (1.f - op);
-  if (b.g_mask_logits && a.mask_logits) {
-    // o' = M o, s' = M s (M = 1 here): dL/dM = o dL/do' + sum_k s_k dL/ds'_k
-    const float sm = sigmoidf(a.mask_logits[i]);
-    const float gMask = gop * op + gsc[0] * s[0] + gsc[1] * s[1] + gsc[2] * s[2];
-    b.g_mask_logits[i] += gMask * sm * (1.f - sm);
-  }
+    if (b.g_quats) b.g_quats[k * n + i] += tq[k];
+  if (b.g_opacity_logits) b.g_opacity_logits[i] += top;
+  if (b.g_mask_logits && a.mask_logits) b.g_mask_logits[i] += tmask;
   if (DEG > 0) {
     if (b.g_sh_rest) {
 #pragma unroll
       for (int k = 1; k <= NR; ++k)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) b.g_sh_rest[((k - 1) * 3 + c) * n + i] += grest[k - 1][c];
+        for (int c = 0; c < 3; ++c) b.g_sh_rest[((k - 1) * 3 + c) * n + i] += trest[k - 1][c];
     }
     if (b.g_sh_mask_logits && a.sh_mask_logits) {
 #pragma unroll
-      for (int l = 1; l <= DEG; ++l) {
-        const float sm = sigmoidf(bm[l - 1]);
-        b.g_sh_mask_logits[(l - 1) * n + i] += gbm[l - 1] * sm * (1.f - sm);
-      }
+      for (int l = 1; l <= DEG; ++l) b.g_sh_mask_logits[(l - 1) * n + i] += tbm[l - 1];
     }
   }
 }

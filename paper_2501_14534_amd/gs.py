@@ -39,7 +39,7 @@ class GsCamera(C.Structure):
 class GsOpts(C.Structure):
     _fields_ = [("near_plane", C.c_float), ("tan_clamp", C.c_float), ("lowpass", C.c_float),
                 ("bg", C.c_float * 3), ("tile_w", C.c_int32), ("tile_h", C.c_int32),
-                ("batch_depth", C.c_int32), ("pixels_per_thread", C.c_int32)]
+                ("batch_depth", C.c_int32), ("pixels_per_thread", C.c_int32), ("subtile_cull", C.c_int32)]
 
 
 class GsProjected(C.Structure):
@@ -47,8 +47,8 @@ class GsProjected(C.Structure):
 
 
 class GsBinning(C.Structure):
-    _fields_ = [("keys", vp), ("ids", vp), ("ranges", vp), ("capacity", C.c_uint64), ("count", vp),
-                ("status", vp)]
+    _fields_ = [("keys", vp), ("ids", vp), ("pair_index", vp), ("offsets", vp), ("ranges", vp),
+                ("capacity", C.c_uint64), ("count", vp), ("status", vp)]
 
 
 class GsGrads(C.Structure):
@@ -90,7 +90,8 @@ def load():
     L.gs_blend_bwd.argtypes = [P(GsCamera), C.c_int32, C.c_int64, P(GsOpts), P(GsProjected), P(GsBinning), vp, vp,
                                vp, vp, vp]
     L.gs_blend_bwd.restype = C.c_int
-    L.gs_project_bwd.argtypes = [P(GsGaussians), P(GsCamera), C.c_int32, P(GsOpts), vp, P(GsGrads), vp]
+    L.gs_project_bwd.argtypes = [P(GsGaussians), P(GsCamera), C.c_int32, P(GsOpts), P(GsProjected), P(GsBinning),
+                                 vp, P(GsGrads), vp]
     L.gs_project_bwd.restype = C.c_int
     L.gs_strerror.argtypes = [C.c_int]
     L.gs_strerror.restype = C.c_char_p
@@ -130,6 +131,7 @@ def options(o) -> GsOpts:
     s.bg = (C.c_float * 3)(*[float(b) for b in o.bg])
     s.tile_w, s.tile_h = int(o.tile_w), int(o.tile_h)
     s.batch_depth, s.pixels_per_thread = int(o.batch_depth), int(o.pixels_per_thread)
+    s.subtile_cull = int(getattr(o, "subtile_cull", 1))
     return s
 
 
@@ -169,10 +171,11 @@ def render_bwd(g, cams_arr, V, opts_s, proj, bins, T_final, last, dL_dimage, gra
                                 dL_dimage, C.byref(grads), ws, ws_bytes, stream)
 
 
-def blend_bwd(cams_arr, V, n, opts_s, proj, bins, T_final, last, dL_dimage, grad_rec, stream) -> int:
+def blend_bwd(cams_arr, V, n, opts_s, proj, bins, T_final, last, dL_dimage, grad_pair, stream) -> int:
     return load().gs_blend_bwd(cams_arr, V, int(n), C.byref(opts_s), C.byref(proj), C.byref(bins), T_final, last,
-                               dL_dimage, grad_rec, stream)
+                               dL_dimage, grad_pair, stream)
 
 
-def project_bwd(g, cams_arr, V, opts_s, grad_rec, grads, stream) -> int:
-    return load().gs_project_bwd(C.byref(g), cams_arr, V, C.byref(opts_s), grad_rec, C.byref(grads), stream)
+def project_bwd(g, cams_arr, V, opts_s, proj, bins, grad_pair, grads, stream) -> int:
+    return load().gs_project_bwd(C.byref(g), cams_arr, V, C.byref(opts_s), C.byref(proj), C.byref(bins), grad_pair,
+                                 C.byref(grads), stream)

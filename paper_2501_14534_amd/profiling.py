@@ -1,0 +1,149 @@
+"""Summaries of rocprofv3 output for the kernels of libgs.
+
+  python -m paper_2501_14534_amd.profiling stats DIR --cmd "..." --out profiles/NAME.md
+      per-kernel call count and average/total duration from a
+      `rocprofv3 --kernel-trace --stats --output-format csv` run.
+  python -m paper_2501_14534_amd.profiling traffic FETCH_DIR WRITE_DIR --kernel K --workload W
+      --copy-bytes B --cmd "..." [--json profiles/pmc_traffic.json] [--out profiles/NAME.md]
+      HBM bytes per launch of kernel K from two `--pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs
+      (KiB per dispatch), each scaled by what the same counter reads for the plain copy kernel
+      of B bytes that `bench.py --calibration-copy-bytes B` launches (an elementwise multiply
+      by one: B read, B written).
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import statistics
+import sys
+from collections import defaultdict
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _csvs(d, suffix):
+    return sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True))
+
+
+def kernel_stats(d):
+    rows = []
+    for f in _csvs(d, "kernel_stats.csv"):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                rows.append(dict(name=r["Name"], calls=int(r["Calls"]), total_ns=float(r["TotalDurationNs"]),
+                                 avg_ns=float(r["AverageNs"]), pct=float(r["Percentage"])))
+    rows.sort(key=lambda r: -r["total_ns"])
+    return rows
+
+
+def counter_values(d):
+    """{kernel name: [value per dispatch]} summed over the counter's instances."""
+    per = defaultdict(lambda: defaultdict(float))
+    names = {}
+    for f in _csvs(d, "counter_collection.csv"):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                did = r.get("Dispatch_Id") or r.get("Correlation_Id")
+                k = r.get("Kernel_Name") or r.get("Kernel-Name")
+                names[did] = k
+                per[did][r["Counter_Name"]] += float(r["Counter_Value"])
+    out = defaultdict(list)
+    for did, cs in per.items():
+        for _, v in cs.items():
+            out[names[did]].append(v)
+    return out
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2501_14534_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(f.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _match(values, pattern):
+    return {k: v for k, v in values.items() if pattern in k}
+
+
+def cmd_stats(a):
+    rows = kernel_stats(a.dir)
+    lines = [f"# rocprofv3 kernel statistics: {a.title}", "", "Command:", "", "```", a.cmd, "```", "",
+             "| kernel | calls | avg us | total ms | % |", "|---|---|---|---|---|"]
+    for r in rows[: a.top]:
+        lines.append(f"| `{r['name'][:90]}` | {r['calls']} | {r['avg_ns'] / 1e3:.2f} | {r['total_ns'] / 1e6:.3f} | "
+                     f"{r['pct']:.2f} |")
+    text = "\n".join(lines) + "\n"
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write(text)
+    print(text)
+
+
+def cmd_traffic(a):
+    fetch = counter_values(a.fetch_dir)
+    write = counter_values(a.write_dir)
+    copy_f = [v for k, vs in _match(fetch, a.copy_pattern).items() for v in vs]
+    copy_w = [v for k, vs in _match(write, a.copy_pattern).items() for v in vs]
+    kib = a.copy_bytes / 1024.0
+    # the calibration copy is the largest elementwise dispatch of the run
+    cf = kib / max(copy_f) if copy_f else None
+    cw = kib / max(copy_w) if copy_w else None
+    kf = [v for k, vs in _match(fetch, a.kernel).items() for v in vs]
+    kw = [v for k, vs in _match(write, a.kernel).items() for v in vs]
+    if not kf or not kw or cf is None or cw is None:
+        sys.exit(f"missing counters: kernel fetch {len(kf)} write {len(kw)}, copy fetch {len(copy_f)} "
+                 f"write {len(copy_w)}")
+    f_med, w_med = statistics.median(kf), statistics.median(kw)
+    byts = (f_med * cf + w_med * cw) * 1024.0
+    entry = dict(kernel=a.kernel, workload=a.workload, source_hash=kernel_source_hash(),
+                 fetch_kib_per_launch=f_med, write_kib_per_launch=w_med, copy_scale_fetch=cf, copy_scale_write=cw,
+                 hbm_bytes_per_launch=byts, dispatches=len(kf), command=a.cmd)
+    if a.json:
+        d = json.load(open(a.json)) if os.path.exists(a.json) else {}
+        d[f"{a.kernel}@{a.workload}"] = entry
+        with open(a.json, "w") as f:
+            json.dump(d, f, indent=1, sort_keys=True)
+    text = "\n".join([
+        f"# HBM traffic of `{a.kernel}` ({a.workload})", "", "Commands (FETCH_SIZE run, then WRITE_SIZE run):", "",
+        "```", a.cmd, "```", "",
+        f"- FETCH_SIZE median over {len(kf)} dispatches: {f_med:.1f} KiB; WRITE_SIZE: {w_med:.1f} KiB",
+        f"- calibration copy of {a.copy_bytes} B: FETCH_SIZE scale {cf:.4f}, WRITE_SIZE scale {cw:.4f}",
+        f"- HBM bytes per launch: {byts:.4e}", f"- kernel source hash: {entry['source_hash']}", ""])
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write(text)
+    print(text)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="what", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("dir")
+    s.add_argument("--cmd", required=True)
+    s.add_argument("--title", default="")
+    s.add_argument("--out")
+    s.add_argument("--top", type=int, default=25)
+    t = sub.add_parser("traffic")
+    t.add_argument("fetch_dir")
+    t.add_argument("write_dir")
+    t.add_argument("--kernel", required=True)
+    t.add_argument("--workload", required=True)
+    t.add_argument("--copy-bytes", type=int, required=True)
+    t.add_argument("--copy-pattern", default="elementwise")
+    t.add_argument("--cmd", required=True)
+    t.add_argument("--json")
+    t.add_argument("--out")
+    a = ap.parse_args(argv)
+    {"stats": cmd_stats, "traffic": cmd_traffic}[a.what](a)
+
+
+if __name__ == "__main__":
+    main()

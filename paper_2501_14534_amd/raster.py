@@ -57,6 +57,7 @@ class Rasterizer:
         nrec = self.V * self.n
         self.splats = torch.zeros(max(nrec, 1) * gs.SPLAT_FLOATS, dtype=torch.float32, device=dev)
         self.tiles_touched = torch.zeros(max(nrec, 1), dtype=torch.int32, device=dev)
+        self.offsets = torch.zeros(max(nrec, 1), dtype=torch.int32, device=dev)
         self.ranges = torch.zeros(max(self.total_tiles, 1) * 2, dtype=torch.int32, device=dev)
         self.count = torch.zeros(1, dtype=torch.int32, device=dev)
         self.status = torch.zeros(1, dtype=torch.int32, device=dev)
@@ -73,12 +74,13 @@ class Rasterizer:
         self.capacity = capacity
         self.keys = torch.zeros(capacity, dtype=torch.int64, device=self.device)
         self.ids = torch.zeros(capacity, dtype=torch.int32, device=self.device)
+        self.pair_index = torch.zeros(capacity, dtype=torch.int32, device=self.device)
         self.ws_bytes = gs.workspace_size(self.n, self.cams_arr, self.V, self.opts_s, capacity)
         if self.ws_bytes == 0:
             raise gs.GsError("invalid configuration for gs_workspace_size")
         self.ws = torch.zeros(self.ws_bytes, dtype=torch.uint8, device=self.device)
-        self.bins = gs.GsBinning(gs.ptr(self.keys), gs.ptr(self.ids), gs.ptr(self.ranges), capacity,
-                                 gs.ptr(self.count), gs.ptr(self.status))
+        self.bins = gs.GsBinning(gs.ptr(self.keys), gs.ptr(self.ids), gs.ptr(self.pair_index), gs.ptr(self.offsets),
+                                 gs.ptr(self.ranges), capacity, gs.ptr(self.count), gs.ptr(self.status))
 
     def gaussians(self, params: Dict[str, torch.Tensor]) -> gs.GsGaussians:
         for k, t in params.items():
@@ -111,16 +113,18 @@ class Rasterizer:
                                gs.ptr(self.last), gs.ptr(dL_dimage), gr, gs.ptr(self.ws), self.ws_bytes, _stream()),
                  "gs_render_bwd")
 
-    def blend_bwd(self, dL_dimage: torch.Tensor, grad_rec: torch.Tensor) -> None:
-        """Back-to-front walk only: adds per-record splat gradients into grad_rec [V*n, 9] (zeroed by the caller)."""
+    def blend_bwd(self, dL_dimage: torch.Tensor, grad_pair: torch.Tensor) -> None:
+        """Back-to-front walk only: writes the per-pair splat gradients [capacity, 9] (emission order)."""
+        if grad_pair.numel() < self.capacity * gs.GRAD_FLOATS:
+            raise ValueError("grad_pair must hold capacity x 9 floats")
         gs.check(gs.blend_bwd(self.cams_arr, self.V, self.n, self.opts_s, self.proj, self.bins, gs.ptr(self.T_final),
-                              gs.ptr(self.last), gs.ptr(dL_dimage), gs.ptr(grad_rec), _stream()), "gs_blend_bwd")
+                              gs.ptr(self.last), gs.ptr(dL_dimage), gs.ptr(grad_pair), _stream()), "gs_blend_bwd")
 
-    def project_bwd(self, params, grad_rec: torch.Tensor, grads: Dict[str, torch.Tensor], mean2d=None) -> None:
+    def project_bwd(self, params, grad_pair: torch.Tensor, grads: Dict[str, torch.Tensor], mean2d=None) -> None:
         g = self.gaussians(params)
         gr = gs.GsGrads(*[gs.ptr(grads.get(k)) for k in PARAM_NAMES], gs.ptr(mean2d))
-        gs.check(gs.project_bwd(g, self.cams_arr, self.V, self.opts_s, gs.ptr(grad_rec), gr, _stream()),
-                 "gs_project_bwd")
+        gs.check(gs.project_bwd(g, self.cams_arr, self.V, self.opts_s, self.proj, self.bins, gs.ptr(grad_pair), gr,
+                                _stream()), "gs_project_bwd")
 
     def overflowed(self) -> bool:
         return bool(self.status.item())
@@ -158,10 +162,20 @@ class Rasterizer:
     def splat_records(self) -> torch.Tensor:
         return self.splats[: self.V * self.n * gs.SPLAT_FLOATS].view(self.V * self.n, gs.SPLAT_FLOATS)
 
+    def grad_pairs(self) -> torch.Tensor:
+        """Per-pair splat gradients (emission order) left in the workspace by the last backward."""
+        k = self.pairs() * gs.GRAD_FLOATS
+        return self.ws[: 4 * k].view(torch.float32).view(-1, gs.GRAD_FLOATS)
+
     def grad_records(self) -> torch.Tensor:
-        """Per-record splat gradients left in the workspace by the last backward."""
-        k = self.V * self.n * gs.GRAD_FLOATS
-        return self.ws[: 4 * k].view(torch.float32).view(self.V * self.n, gs.GRAD_FLOATS)
+        """Per-record sums of the last backward's pair gradients [V*n, 9] (float64, for inspection)."""
+        nrec = self.V * self.n
+        gp = self.grad_pairs().double()
+        tt = self.tiles_touched[:nrec].long()
+        owner = torch.repeat_interleave(torch.arange(nrec, device=gp.device), tt)
+        out = torch.zeros(nrec, gs.GRAD_FLOATS, dtype=torch.float64, device=gp.device)
+        out.index_add_(0, owner, gp[: owner.numel()])
+        return out
 
     def zero_grads(self, params) -> Dict[str, torch.Tensor]:
         return {k: torch.zeros_like(v) for k, v in params.items() if v is not None}

@@ -107,6 +107,7 @@ class Opts:
     tile_h: int = 16
     batch_depth: int = 256
     pixels_per_thread: int = 1
+    subtile_cull: int = 1
 
 
 @dataclasses.dataclass

@@ -118,10 +118,16 @@ def test_other_entry_points_reject_null_buffers(lib):
     cams = gs.cameras(wl.cams)
     o = gs.options(wl.opts)
     proj = gs.GsProjected(4096, 4096)
-    bins = gs.GsBinning(4096, 4096, None, 100, 4096, 4096)  # ranges missing
+    bins = gs.GsBinning(4096, 4096, 4096, 4096, None, 100, 4096, 4096)  # ranges missing
     assert lib.gs_bin_sort(C.byref(proj), cams, 1, 64, C.byref(o), C.byref(bins), 4096, 1 << 30, None) == \
         gs.GS_E_INVALID
-    bins = gs.GsBinning(4096, 4096, 4096, 100, 4096, 4096)
+    bins = gs.GsBinning(4096, 4096, None, 4096, 4096, 100, 4096, 4096)  # pair_index missing
+    assert lib.gs_bin_sort(C.byref(proj), cams, 1, 64, C.byref(o), C.byref(bins), 4096, 1 << 30, None) == \
+        gs.GS_E_INVALID
+    bins = gs.GsBinning(4096, 4096, 4096, None, 4096, 100, 4096, 4096)  # offsets missing
+    assert lib.gs_bin_sort(C.byref(proj), cams, 1, 64, C.byref(o), C.byref(bins), 4096, 1 << 30, None) == \
+        gs.GS_E_INVALID
+    bins = gs.GsBinning(4096, 4096, 4096, 4096, 4096, 100, 4096, 4096)
     assert lib.gs_bin_sort(C.byref(proj), cams, 1, 64, C.byref(o), C.byref(bins), 4096, 16, None) == \
         gs.GS_E_INVALID  # workspace too small
     assert lib.gs_render_fwd(C.byref(proj), C.byref(bins), cams, 1, 64, C.byref(o), None, 4096, 4096, None) == \
