@@ -205,13 +205,15 @@ int gs_render_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t V, const
  * to grad_pair ([capacity][9], indexed by pair_index; no zeroing needed).
  * gs_project_bwd: per Gaussian, the sum of its pairs' gradients in emission
  * order, then the chain rule to the raw parameters (the second half of
- * gs_render_bwd), accumulated into `grads`.                                */
+ * gs_render_bwd), accumulated into `grads`.  ws has gs_render_bwd's layout
+ * (ws_bytes >= gs_workspace_size(...)); grad_pair may point at its start, as
+ * it does inside gs_render_bwd.                                             */
 int gs_blend_bwd(const gs_camera* cams, int32_t V, int64_t n, const gs_opts* opts, const gs_projected* proj,
                  const gs_binning* bins, const float* T_final, const int32_t* last_contrib, const float* dL_dimage,
                  float* grad_pair, gs_stream_t stream);
 int gs_project_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t V, const gs_opts* opts,
                    const gs_projected* proj, const gs_binning* bins, const float* grad_pair, gs_grads* grads,
-                   gs_stream_t stream);
+                   void* ws, size_t ws_bytes, gs_stream_t stream);
 
 /* Static description of a return code. */
 const char* gs_strerror(int code);

@@ -133,6 +133,20 @@ RenderArgs render_args(const gs_projected* p, const gs_binning* b, const gs_opts
   a.status = b->status;
   a.log2_tw = ilog2(o->tile_w);
   a.log2_th = ilog2(o->tile_h);
+  // one sub-tile of 64 * ppt pixels per wave, as square as the tile allows (wider on ties)
+  const int log2_waves = a.log2_tw + a.log2_th - 6 - ilog2(o->pixels_per_thread);
+  int best = -1;
+  for (int sx = 0; sx <= log2_waves; ++sx) {
+    const int sw = a.log2_tw - sx, sh = a.log2_th - (log2_waves - sx);
+    if (sw < 0 || sh < 0) continue;
+    if (best < 0 || std::abs(sw - sh) < std::abs(a.log2_sw - a.log2_sh) ||
+        (std::abs(sw - sh) == std::abs(a.log2_sw - a.log2_sh) && sw > a.log2_sw)) {
+      best = sx;
+      a.log2_sx = sx;
+      a.log2_sw = sw;
+      a.log2_sh = sh;
+    }
+  }
   a.batch = o->batch_depth;
   a.ppt = o->pixels_per_thread;
   a.cull = o->subtile_cull;
@@ -149,10 +163,17 @@ bool binning_ok(const gs_binning* b, int64_t nrec) {
   return true;
 }
 
+// Backward workspace: per-pair gradients [capacity][9] floats, then per-record
+// geometry sums [V*n][6] doubles and colour mean terms [V*n][4] floats.
 size_t grad_pair_bytes(uint64_t capacity) { return align256(sizeof(float) * GS_GRAD_FLOATS * (size_t)capacity); }
+size_t rec_geo_bytes(int64_t nrec) { return align256(sizeof(double) * 6 * (size_t)nrec); }
+size_t rec_mu_bytes(int64_t nrec) { return align256(sizeof(float) * 4 * (size_t)nrec); }
+size_t bwd_ws_bytes(uint64_t capacity, int64_t nrec) {
+  return grad_pair_bytes(capacity) + rec_geo_bytes(nrec) + rec_mu_bytes(nrec);
+}
 
 ProjectBwdArgs project_bwd_args(ProjectArgs pa, const gs_opts* opts, const gs_projected* proj, const gs_binning* bins,
-                                const float* grad_pair, const gs_grads* grads, int deg) {
+                                const float* grad_pair, const gs_grads* grads, int deg, void* ws, int64_t nrec) {
   pa.near_plane = opts->near_plane;
   pa.lowpass = opts->lowpass;
   pa.inv_tw = 1.0f / (float)opts->tile_w;
@@ -160,6 +181,8 @@ ProjectBwdArgs project_bwd_args(ProjectArgs pa, const gs_opts* opts, const gs_pr
   ProjectBwdArgs b;
   b.p = pa;
   b.grad_pair = grad_pair;
+  b.rec_geo = (double*)((char*)ws + grad_pair_bytes(bins->capacity));
+  b.rec_mu = (float*)((char*)ws + grad_pair_bytes(bins->capacity) + rec_geo_bytes(nrec));
   b.tiles_touched = proj->tiles_touched;
   b.offsets = bins->offsets;
   b.status = bins->status;
@@ -205,7 +228,7 @@ size_t gs_workspace_size(int64_t n, int32_t V, const gs_camera* cams, const gs_o
   if (n < 0 || capacity >= (1ull << 32) || !view_table(cams, V, opts, &vt, nullptr)) return 0;
   const SortPlan p = sort_plan(n, V, vt.total_tiles, capacity);
   const size_t sort_bytes = bin_sort_ws_bytes(p);
-  const size_t bwd_bytes = grad_pair_bytes(capacity);
+  const size_t bwd_bytes = bwd_ws_bytes(capacity, (int64_t)V * n);
   return sort_bytes > bwd_bytes ? sort_bytes : bwd_bytes;
 }
 
@@ -273,7 +296,8 @@ int gs_render_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t V, const
   if (!proj || !T_final || !last_contrib || !dL_dimage || !grads) return GS_E_INVALID;
   if (!binning_ok(bins, (int64_t)V * g->n)) return GS_E_INVALID;
   if (g->n > 0 && (!proj->splats || !proj->tiles_touched)) return GS_E_INVALID;
-  const size_t need = grad_pair_bytes(bins->capacity);
+  const int64_t nrec = (int64_t)V * g->n;
+  const size_t need = bwd_ws_bytes(bins->capacity, nrec);
   if (ws_bytes < need || (!ws && need > 0)) return GS_E_INVALID;
   const int d = device_ok();
   if (d != GS_OK) return d;
@@ -282,8 +306,8 @@ int gs_render_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t V, const
   const RenderArgs ra = render_args(proj, bins, opts);
   hipError_t e = launch_render_bwd(ra, vt, T_final, last_contrib, dL_dimage, grad_pair, s);
   if (e != hipSuccess) return GS_E_HIP;
-  return launched(
-      launch_project_bwd(project_bwd_args(pa, opts, proj, bins, grad_pair, grads, g->sh_degree), vt, g->sh_degree, s));
+  return launched(launch_project_bwd(project_bwd_args(pa, opts, proj, bins, grad_pair, grads, g->sh_degree, ws, nrec),
+                                     vt, g->sh_degree, s));
 }
 
 int gs_blend_bwd(const gs_camera* cams, int32_t V, int64_t n, const gs_opts* opts, const gs_projected* proj,
@@ -301,16 +325,19 @@ int gs_blend_bwd(const gs_camera* cams, int32_t V, int64_t n, const gs_opts* opt
 
 int gs_project_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t V, const gs_opts* opts,
                    const gs_projected* proj, const gs_binning* bins, const float* grad_pair, gs_grads* grads,
-                   gs_stream_t stream) {
+                   void* ws, size_t ws_bytes, gs_stream_t stream) {
   ProjectArgs pa;
   ViewTable vt;
   if (!gaussians_ok(g, &pa) || !view_table(cams, V, opts, &vt, nullptr)) return GS_E_INVALID;
   if (!proj || !grads || !binning_ok(bins, (int64_t)V * g->n)) return GS_E_INVALID;
   if (g->n > 0 && (!grad_pair || !proj->tiles_touched)) return GS_E_INVALID;
+  const int64_t nrec = (int64_t)V * g->n;
+  const size_t need = bwd_ws_bytes(bins->capacity, nrec);
+  if (ws_bytes < need || (!ws && need > 0)) return GS_E_INVALID;
   const int d = device_ok();
   if (d != GS_OK) return d;
-  return launched(launch_project_bwd(project_bwd_args(pa, opts, proj, bins, grad_pair, grads, g->sh_degree), vt,
-                                     g->sh_degree, (hipStream_t)stream));
+  return launched(launch_project_bwd(project_bwd_args(pa, opts, proj, bins, grad_pair, grads, g->sh_degree, ws, nrec),
+                                     vt, g->sh_degree, (hipStream_t)stream));
 }
 
 }  // extern "C"

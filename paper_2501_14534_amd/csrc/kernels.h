@@ -34,6 +34,8 @@ struct RenderArgs {
   const uint32_t* ranges;
   const int32_t* status;
   int32_t log2_tw, log2_th;
+  int32_t log2_sw, log2_sh;  // sub-tile (one per wave) width and height
+  int32_t log2_sx;           // sub-tiles along x
   int32_t batch;
   int32_t ppt;
   int32_t cull;
@@ -56,6 +58,8 @@ struct ProjectBwdArgs {
   const uint32_t* tiles_touched;   // [V*n]
   const uint32_t* offsets;         // [V*n] first emission position of each record
   const int32_t* status;
+  double* rec_geo;                 // [V*n][6] per-record sums of (u, v, A, B, C, o') gradients
+  float* rec_mu;                   // [V*n][4] per-record colour term of the mean gradient
   float* g_means;
   float* g_log_scales;
   float* g_quats;

@@ -1,17 +1,25 @@
-// Backward of the projection: per-record splat gradients (u, v, A, B, C, o',
+// Backward of the projection: per-pair splat gradients (u, v, A, B, C, o',
 // r, g, b) -> raw Gaussian parameters, accumulated over the V views of the
-// call (one thread per Gaussian, so no atomics), then added (+=) to the
-// caller's gradient arrays.  Straight-through estimator for the hard masks
-// (Eq. 3, Eq. 5): d(mask)/d(logit) = sigmoid'(logit).
+// call and added (+=) to the caller's gradient arrays.  Straight-through
+// estimator for the hard masks (Eq. 3, Eq. 5): d(mask)/d(logit) = sigmoid'.
 //
-// Chain, per view (Sigma' = T Sigma T^T + sI, T = J W, Q = Sigma'^-1 = conic):
-//   dL/dSigma'  = -Q G_Q Q              (G_Q symmetric: [[gA, gB/2], [gB/2, gC]])
-//   dL/dSigma   = T^T dL/dSigma' T,     dL/dT = 2 dL/dSigma' T Sigma
-//   dL/dJ       = dL/dT W^T  -> camera-space mean t (through J's entries and
-//                 the clamp of the lateral ratios), plus the screen mean (u, v)
-//   dL/dmu      = W^T dL/dt  + view-direction term of the SH colour
-//   dL/dM       = 2 dL/dSigma M  with M = Rq diag(s) -> scales and rotation,
-//                 then through the quaternion normalisation.
+// Two kernels, one thread per Gaussian each (no atomics):
+//   colour:   sums each record's pairs in emission order (double), keeps the
+//             geometry sums for the second kernel, and runs the SH chain
+//             (diffuse colour, bands 1..3, band-mask logits, and the
+//             view-direction term of the mean) in single precision;
+//   geometry: the EWA chain in double precision (this half is bound by
+//             memory traffic, and the 2x2 inverse amplifies rounding by the
+//             condition number of Sigma'):
+//     dL/dSigma'  = -Q G_Q Q              (G_Q = [[gA, gB/2], [gB/2, gC]], Q = conic)
+//     dL/dSigma   = T^T dL/dSigma' T,     dL/dT = 2 dL/dSigma' T Sigma,  T = J W
+//     dL/dJ -> camera-space mean (J's entries, the clamp of the lateral ratios),
+//     plus the screen mean (u, v); dL/dmu = W^T dL/dt + colour term;
+//     dL/dM = 2 dL/dSigma M with M = Rq diag(s) -> scales, rotation, through
+//     the quaternion normalisation; opacity and volume mask.
+// Each view's contribution is rounded to float and added to the running
+// totals in view order with non-contracted adds: the association a sequence
+// of per-view calls produces, so a batched call equals the per-view calls.
 #include "gs_common.h"
 #include "kernels.h"
 
@@ -64,8 +72,19 @@ __device__ __forceinline__ void sh_grad15(float x, float y, float z, const float
   *gz = az;
 }
 
+// t + x without fusing into a preceding multiply (same rounding as two calls).
+__device__ __forceinline__ float acc_add(float t, float x) {
+#pragma clang fp contract(off)
+  return t + x;
+}
+__device__ __forceinline__ float acc_mul_add(float t, float a, float b) {
+#pragma clang fp contract(off)
+  const float p = a * b;
+  return t + p;
+}
+
 template <int DEG>
-__global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs b, ViewTable vt) {
+__global__ __launch_bounds__(256) void project_bwd_color_kernel(ProjectBwdArgs b, ViewTable vt) {
   const ProjectArgs& a = b.p;
   const int64_t n = a.n;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -76,16 +95,12 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs b, View
   for (int v = 0; v < V; ++v) any |= b.tiles_touched[(size_t)v * n + i] != 0u;
   if (!any) return;  // culled or off-screen in every view
 
-  float mu[3], ls[3], q[4], dc[3];
+  float mu[3], dc[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     mu[k] = a.means[k * n + i];
-    ls[k] = a.log_scales[k * n + i];
     dc[k] = a.sh_dc[k * n + i];
   }
-#pragma unroll
-  for (int k = 0; k < 4; ++k) q[k] = a.quats[k * n + i];
-  const float ol = a.opacity_logits[i];
   constexpr int NR = DEG > 0 ? (DEG + 1) * (DEG + 1) - 1 : 1;
   float rest[NR][3];
   float bm[3] = {0.f, 0.f, 0.f};
@@ -105,36 +120,7 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs b, View
 #pragma unroll
       for (int c = 0; c < 3; ++c) rest[k - 1][c] = a.sh_rest[((k - 1) * 3 + c) * n + i];
   }
-
-  // geometry shared by all views, in double precision (this kernel is bound by memory traffic)
-  const double q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3];
-  const double qn = sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
-  const double iq = 1.0 / qn;
-  const double w = q0 * iq, x = q1 * iq, y = q2 * iq, z = q3 * iq;
-  const double Rq[3][3] = {{1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y)},
-                           {2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x)},
-                           {2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)}};
-  double s[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) s[k] = exp((double)ls[k]);
-  double M[3][3];  // Rq diag(s)
-#pragma unroll
-  for (int r = 0; r < 3; ++r)
-#pragma unroll
-    for (int k = 0; k < 3; ++k) M[r][k] = Rq[r][k] * s[k];
-  double Sig[3][3];
-#pragma unroll
-  for (int r = 0; r < 3; ++r)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) Sig[r][c] = M[r][0] * M[c][0] + M[r][1] * M[c][1] + M[r][2] * M[c][2];
-  const double op = 1.0 / (1.0 + exp(-(double)ol));
-  double sm = 0.0;
-  if (a.mask_logits) sm = 1.0 / (1.0 + exp(-(double)a.mask_logits[i]));
-
-  // totals over views, single precision, added view by view (the association a
-  // sequence of per-view calls produces)
-  float tmu[3] = {0.f, 0.f, 0.f}, tls[3] = {0.f, 0.f, 0.f}, tq[4] = {0.f, 0.f, 0.f, 0.f};
-  float top = 0.f, tmask = 0.f, tdc[3] = {0.f, 0.f, 0.f}, tbm[3] = {0.f, 0.f, 0.f};
+  float tdc[3] = {0.f, 0.f, 0.f}, tbm[3] = {0.f, 0.f, 0.f};
   float trest[NR][3];
 #pragma unroll
   for (int k = 0; k < NR; ++k) trest[k][0] = trest[k][1] = trest[k][2] = 0.f;
@@ -149,114 +135,20 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs b, View
     for (uint32_t k = 0; k < cntp; ++k)
 #pragma unroll
       for (int c = 0; c < GS_GRAD_FLOATS; ++c) gsum[c] += (double)gp[(size_t)k * GS_GRAD_FLOATS + c];
-    bool nz = false;
+    double* geo = b.rec_geo + r * 6;
 #pragma unroll
-    for (int c = 0; c < GS_GRAD_FLOATS; ++c) nz |= gsum[c] != 0.0;
-    if (!nz) continue;
-    const double gu = gsum[0], gv = gsum[1], gA = gsum[2], gB = gsum[3], gC = gsum[4], go = gsum[5];
+    for (int c = 0; c < 6; ++c) geo[c] = gsum[c];
     if (b.g_mean2d) {
-      b.g_mean2d[((size_t)v * 2 + 0) * n + i] += (float)gu;
-      b.g_mean2d[((size_t)v * 2 + 1) * n + i] += (float)gv;
+      b.g_mean2d[((size_t)v * 2 + 0) * n + i] += (float)gsum[0];
+      b.g_mean2d[((size_t)v * 2 + 1) * n + i] += (float)gsum[1];
+    }
+    float* cmu = b.rec_mu + r * 4;
+    const float grgb[3] = {(float)gsum[6], (float)gsum[7], (float)gsum[8]};
+    if (grgb[0] == 0.f && grgb[1] == 0.f && grgb[2] == 0.f) {
+      cmu[0] = cmu[1] = cmu[2] = 0.f;
+      continue;
     }
     const ViewArgs& c = vt.v[v];
-    double R[9];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) R[k] = c.R[k];
-    const double fx = c.fx, fy = c.fy;
-    const double t0 = R[0] * mu[0] + R[1] * mu[1] + R[2] * mu[2] + (double)c.t[0];
-    const double t1 = R[3] * mu[0] + R[4] * mu[1] + R[5] * mu[2] + (double)c.t[1];
-    const double t2 = R[6] * mu[0] + R[7] * mu[1] + R[8] * mu[2] + (double)c.t[2];
-    const double iz = 1.0 / t2;
-    const double ux = t0 * iz, uy = t1 * iz;
-    const double lx = c.limx, ly = c.limy;
-    const bool inx = ux >= -lx && ux <= lx;
-    const bool iny = uy >= -ly && uy <= ly;
-    const double rx = fmin(fmax(ux, -lx), lx);
-    const double ry = fmin(fmax(uy, -ly), ly);
-    const double j00 = fx * iz, j02 = -fx * rx * iz, j11 = fy * iz, j12 = -fy * ry * iz;
-    double Tm[2][3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      Tm[0][k] = j00 * R[k] + j02 * R[6 + k];
-      Tm[1][k] = j11 * R[3 + k] + j12 * R[6 + k];
-    }
-    double TS[2][3];  // T Sigma
-#pragma unroll
-    for (int rr = 0; rr < 2; ++rr)
-#pragma unroll
-      for (int k = 0; k < 3; ++k) TS[rr][k] = Tm[rr][0] * Sig[0][k] + Tm[rr][1] * Sig[1][k] + Tm[rr][2] * Sig[2][k];
-    const double ca = TS[0][0] * Tm[0][0] + TS[0][1] * Tm[0][1] + TS[0][2] * Tm[0][2] + (double)a.lowpass;
-    const double cb = TS[0][0] * Tm[1][0] + TS[0][1] * Tm[1][1] + TS[0][2] * Tm[1][2];
-    const double cc = TS[1][0] * Tm[1][0] + TS[1][1] * Tm[1][1] + TS[1][2] * Tm[1][2] + (double)a.lowpass;
-    const double idet = 1.0 / (ca * cc - cb * cb);
-    const double QA = cc * idet, QB = -cb * idet, QC = ca * idet;
-    // dL/dSigma' = -Q G_Q Q
-    const double P00 = QA * gA + QB * 0.5 * gB, P01 = QA * 0.5 * gB + QB * gC;
-    const double P10 = QB * gA + QC * 0.5 * gB, P11 = QB * 0.5 * gB + QC * gC;
-    const double G00 = -(P00 * QA + P01 * QB);
-    const double G01 = -(P00 * QB + P01 * QC);
-    const double G11 = -(P10 * QB + P11 * QC);
-    // dL/dSigma = T^T G T
-    double gSig[3][3];
-#pragma unroll
-    for (int rr = 0; rr < 3; ++rr)
-#pragma unroll
-      for (int k = 0; k < 3; ++k)
-        gSig[rr][k] = Tm[0][rr] * (G00 * Tm[0][k] + G01 * Tm[1][k]) + Tm[1][rr] * (G01 * Tm[0][k] + G11 * Tm[1][k]);
-    // dL/dT = 2 G T Sigma; T = J W with J00, J02, J11, J12 varying
-    double gT[2][3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      gT[0][k] = 2.0 * (G00 * TS[0][k] + G01 * TS[1][k]);
-      gT[1][k] = 2.0 * (G01 * TS[0][k] + G11 * TS[1][k]);
-    }
-    const double gj00 = gT[0][0] * R[0] + gT[0][1] * R[1] + gT[0][2] * R[2];
-    const double gj02 = gT[0][0] * R[6] + gT[0][1] * R[7] + gT[0][2] * R[8];
-    const double gj11 = gT[1][0] * R[3] + gT[1][1] * R[4] + gT[1][2] * R[5];
-    const double gj12 = gT[1][0] * R[6] + gT[1][1] * R[7] + gT[1][2] * R[8];
-    const double iz2 = iz * iz;
-    double gt0 = gu * fx * iz, gt1 = gv * fy * iz;
-    double gt2 = -gu * fx * t0 * iz2 - gv * fy * t1 * iz2;
-    gt2 += -gj00 * fx * iz2 - gj11 * fy * iz2;
-    // J02 = -fx rx / z, rx = clamp(x / z): d/dx = -fx/z^2 (unclamped); d/dz = fx rx/z^2 (+ fx x/z^3 unclamped)
-    gt2 += gj02 * fx * rx * iz2 + gj12 * fy * ry * iz2;
-    if (inx) {
-      gt0 += -gj02 * fx * iz2;
-      gt2 += gj02 * fx * t0 * iz2 * iz;
-    }
-    if (iny) {
-      gt1 += -gj12 * fy * iz2;
-      gt2 += gj12 * fy * t1 * iz2 * iz;
-    }
-    double gmu[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) gmu[k] = R[k] * gt0 + R[3 + k] * gt1 + R[6 + k] * gt2;
-    // Sigma = M M^T -> dL/dM = (G + G^T) M; scales and rotation
-    double gsc[3], gR[3][3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
-#pragma unroll
-      for (int c2 = 0; c2 < 3; ++c2) {
-        acc0 += (gSig[0][c2] + gSig[c2][0]) * M[c2][k];
-        acc1 += (gSig[1][c2] + gSig[c2][1]) * M[c2][k];
-        acc2 += (gSig[2][c2] + gSig[c2][2]) * M[c2][k];
-      }
-      gsc[k] = acc0 * Rq[0][k] + acc1 * Rq[1][k] + acc2 * Rq[2][k];
-      gR[0][k] = acc0 * s[k];
-      gR[1][k] = acc1 * s[k];
-      gR[2][k] = acc2 * s[k];
-    }
-    const double gw = 2.0 * (-z * gR[0][1] + y * gR[0][2] + z * gR[1][0] - x * gR[1][2] - y * gR[2][0] + x * gR[2][1]);
-    const double gx = 2.0 * (y * gR[0][1] + z * gR[0][2] + y * gR[1][0] - 2.0 * x * gR[1][1] - w * gR[1][2] +
-                             z * gR[2][0] + w * gR[2][1] - 2.0 * x * gR[2][2]);
-    const double gy = 2.0 * (-2.0 * y * gR[0][0] + x * gR[0][1] + w * gR[0][2] + x * gR[1][0] + z * gR[1][2] -
-                             w * gR[2][0] + z * gR[2][1] - 2.0 * y * gR[2][2]);
-    const double gz = 2.0 * (-2.0 * z * gR[0][0] - w * gR[0][1] + x * gR[0][2] + w * gR[1][0] - 2.0 * z * gR[1][1] +
-                             y * gR[1][2] + x * gR[2][0] + y * gR[2][1]);
-    const double qd = w * gw + x * gx + y * gy + z * gz;
-    // colour (single precision: sums of small products, well conditioned)
-    const float grgb[3] = {(float)gsum[6], (float)gsum[7], (float)gsum[8]};
     float pre[3] = {dc[0], dc[1], dc[2]};
     float Y[15];
     float dx = 0.f, dy = 0.f, dz = 0.f, il = 1.f;
@@ -276,9 +168,11 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs b, View
     }
     float gpre[3];
 #pragma unroll
-    for (int ch = 0; ch < 3; ++ch) gpre[ch] = pre[ch] < 0.f ? 0.f : grgb[ch];
+    for (int ch = 0; ch < 3; ++ch) {
+      gpre[ch] = pre[ch] < 0.f ? 0.f : grgb[ch];
+      tdc[ch] = acc_add(tdc[ch], gpre[ch]);
+    }
     float gmu_col[3] = {0.f, 0.f, 0.f};
-    float gbm_v[3] = {0.f, 0.f, 0.f};
     if (DEG > 0) {
       float wY[15];
 #pragma unroll
@@ -290,9 +184,14 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs b, View
         for (int k = l * l; k < (l + 1) * (l + 1); ++k) {
           const float cg = rest[k - 1][0] * gpre[0] + rest[k - 1][1] * gpre[1] + rest[k - 1][2] * gpre[2];
           band += Y[k - 1] * cg;
-          if (band_on[l]) wY[k - 1] = cg;
+          if (band_on[l]) {
+            wY[k - 1] = cg;
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) trest[k - 1][ch] = acc_mul_add(trest[k - 1][ch], Y[k - 1], gpre[ch]);
+          }
         }
-        gbm_v[l - 1] = band;
+        const float sb = sigmoidf(bm[l - 1]);
+        tbm[l - 1] = acc_mul_add(tbm[l - 1], band, sb * (1.f - sb));
       }
       float gdx, gdy, gdz;
       sh_grad15(dx, dy, dz, wY, &gdx, &gdy, &gdz);
@@ -301,48 +200,14 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs b, View
       gmu_col[1] = (gdy - dy * dot) * il;
       gmu_col[2] = (gdz - dz * dot) * il;
     }
-    // add this view's contribution to the totals
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      tmu[k] += (float)(gmu[k] + (double)gmu_col[k]);
-      tls[k] += (float)(gsc[k] * s[k]);
-      tdc[k] += gpre[k];
-    }
-    tq[0] += (float)((gw - w * qd) * iq);
-    tq[1] += (float)((gx - x * qd) * iq);
-    tq[2] += (float)((gy - y * qd) * iq);
-    tq[3] += (float)((gz - z * qd) * iq);
-    top += (float)(go * op * (1.0 - op));
-    if (a.mask_logits) {
-      // o' = M o, s' = M s (M = 1 here): dL/dM = o dL/do' + sum_k s_k dL/ds'_k
-      tmask += (float)((go * op + gsc[0] * s[0] + gsc[1] * s[1] + gsc[2] * s[2]) * sm * (1.0 - sm));
-    }
-    if (DEG > 0) {
-#pragma unroll
-      for (int l = 1; l <= DEG; ++l) {
-        if (band_on[l]) {
-#pragma unroll
-          for (int k = l * l; k < (l + 1) * (l + 1); ++k)
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) trest[k - 1][ch] += Y[k - 1] * gpre[ch];
-        }
-        const float sb = sigmoidf(bm[l - 1]);
-        tbm[l - 1] += gbm_v[l - 1] * sb * (1.f - sb);
-      }
-    }
+    cmu[0] = gmu_col[0];
+    cmu[1] = gmu_col[1];
+    cmu[2] = gmu_col[2];
   }
 
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    if (b.g_means) b.g_means[k * n + i] += tmu[k];
-    if (b.g_log_scales) b.g_log_scales[k * n + i] += tls[k];
+  for (int k = 0; k < 3; ++k)
     if (b.g_sh_dc) b.g_sh_dc[k * n + i] += tdc[k];
-  }
-#pragma unroll
-  for (int k = 0; k < 4; ++k)
-    if (b.g_quats) b.g_quats[k * n + i] += tq[k];
-  if (b.g_opacity_logits) b.g_opacity_logits[i] += top;
-  if (b.g_mask_logits && a.mask_logits) b.g_mask_logits[i] += tmask;
   if (DEG > 0) {
     if (b.g_sh_rest) {
 #pragma unroll
@@ -357,15 +222,194 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(ProjectBwdArgs b, View
   }
 }
 
+__global__ __launch_bounds__(256) void project_bwd_geom_kernel(ProjectBwdArgs b, ViewTable vt) {
+  const ProjectArgs& a = b.p;
+  const int64_t n = a.n;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (*b.status != 0) return;
+  const int V = vt.nviews;
+  bool any = false;
+  for (int v = 0; v < V; ++v) any |= b.tiles_touched[(size_t)v * n + i] != 0u;
+  if (!any) return;
+
+  float mu[3], ls[3], q[4];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    mu[k] = a.means[k * n + i];
+    ls[k] = a.log_scales[k * n + i];
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) q[k] = a.quats[k * n + i];
+  const float ol = a.opacity_logits[i];
+
+  const double q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3];
+  const double iq = 1.0 / sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+  const double w = q0 * iq, x = q1 * iq, y = q2 * iq, z = q3 * iq;
+  const double Rq[3][3] = {{1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y)},
+                           {2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x)},
+                           {2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)}};
+  double s[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) s[k] = exp((double)ls[k]);
+  double Sig[6];  // xx, xy, xz, yy, yz, zz
+  {
+    double M[3][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) M[r][k] = Rq[r][k] * s[k];
+    Sig[0] = M[0][0] * M[0][0] + M[0][1] * M[0][1] + M[0][2] * M[0][2];
+    Sig[1] = M[0][0] * M[1][0] + M[0][1] * M[1][1] + M[0][2] * M[1][2];
+    Sig[2] = M[0][0] * M[2][0] + M[0][1] * M[2][1] + M[0][2] * M[2][2];
+    Sig[3] = M[1][0] * M[1][0] + M[1][1] * M[1][1] + M[1][2] * M[1][2];
+    Sig[4] = M[1][0] * M[2][0] + M[1][1] * M[2][1] + M[1][2] * M[2][2];
+    Sig[5] = M[2][0] * M[2][0] + M[2][1] * M[2][1] + M[2][2] * M[2][2];
+  }
+  const double op = 1.0 / (1.0 + exp(-(double)ol));
+  double sm = 0.0;
+  if (a.mask_logits) sm = 1.0 / (1.0 + exp(-(double)a.mask_logits[i]));
+
+  float tmu[3] = {0.f, 0.f, 0.f}, tls[3] = {0.f, 0.f, 0.f}, tq[4] = {0.f, 0.f, 0.f, 0.f};
+  float top = 0.f, tmask = 0.f;
+  for (int v = 0; v < V; ++v) {
+    const size_t r = (size_t)v * n + i;
+    if (b.tiles_touched[r] == 0) continue;
+    const double* geo = b.rec_geo + r * 6;
+    const float* cmu = b.rec_mu + r * 4;
+    const double gu = geo[0], gv = geo[1], gA = geo[2], gB = geo[3], gC = geo[4], go = geo[5];
+    const float cm0 = cmu[0], cm1 = cmu[1], cm2 = cmu[2];
+    if (gu == 0.0 && gv == 0.0 && gA == 0.0 && gB == 0.0 && gC == 0.0 && go == 0.0 && cm0 == 0.f && cm1 == 0.f &&
+        cm2 == 0.f)
+      continue;
+    const ViewArgs& c = vt.v[v];
+    const double fx = c.fx, fy = c.fy;
+    const double t0 = (double)c.R[0] * mu[0] + (double)c.R[1] * mu[1] + (double)c.R[2] * mu[2] + (double)c.t[0];
+    const double t1 = (double)c.R[3] * mu[0] + (double)c.R[4] * mu[1] + (double)c.R[5] * mu[2] + (double)c.t[1];
+    const double t2 = (double)c.R[6] * mu[0] + (double)c.R[7] * mu[1] + (double)c.R[8] * mu[2] + (double)c.t[2];
+    const double iz = 1.0 / t2;
+    const double ux = t0 * iz, uy = t1 * iz;
+    const double lx = c.limx, ly = c.limy;
+    const bool inx = ux >= -lx && ux <= lx;
+    const bool iny = uy >= -ly && uy <= ly;
+    const double rx = fmin(fmax(ux, -lx), lx);
+    const double ry = fmin(fmax(uy, -ly), ly);
+    const double j00 = fx * iz, j02 = -fx * rx * iz, j11 = fy * iz, j12 = -fy * ry * iz;
+    double Tm[2][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      Tm[0][k] = j00 * (double)c.R[k] + j02 * (double)c.R[6 + k];
+      Tm[1][k] = j11 * (double)c.R[3 + k] + j12 * (double)c.R[6 + k];
+    }
+    double TS[2][3];  // T Sigma
+#pragma unroll
+    for (int rr = 0; rr < 2; ++rr) {
+      TS[rr][0] = Tm[rr][0] * Sig[0] + Tm[rr][1] * Sig[1] + Tm[rr][2] * Sig[2];
+      TS[rr][1] = Tm[rr][0] * Sig[1] + Tm[rr][1] * Sig[3] + Tm[rr][2] * Sig[4];
+      TS[rr][2] = Tm[rr][0] * Sig[2] + Tm[rr][1] * Sig[4] + Tm[rr][2] * Sig[5];
+    }
+    const double ca = TS[0][0] * Tm[0][0] + TS[0][1] * Tm[0][1] + TS[0][2] * Tm[0][2] + (double)a.lowpass;
+    const double cb = TS[0][0] * Tm[1][0] + TS[0][1] * Tm[1][1] + TS[0][2] * Tm[1][2];
+    const double cc = TS[1][0] * Tm[1][0] + TS[1][1] * Tm[1][1] + TS[1][2] * Tm[1][2] + (double)a.lowpass;
+    const double idet = 1.0 / (ca * cc - cb * cb);
+    const double QA = cc * idet, QB = -cb * idet, QC = ca * idet;
+    // dL/dSigma' = -Q G_Q Q
+    const double P00 = QA * gA + QB * 0.5 * gB, P01 = QA * 0.5 * gB + QB * gC;
+    const double P10 = QB * gA + QC * 0.5 * gB, P11 = QB * 0.5 * gB + QC * gC;
+    const double G00 = -(P00 * QA + P01 * QB);
+    const double G01 = -(P00 * QB + P01 * QC);
+    const double G11 = -(P10 * QB + P11 * QC);
+    // dL/dT = 2 G T Sigma; T = J W with J00, J02, J11, J12 varying
+    double gT[2][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      gT[0][k] = 2.0 * (G00 * TS[0][k] + G01 * TS[1][k]);
+      gT[1][k] = 2.0 * (G01 * TS[0][k] + G11 * TS[1][k]);
+    }
+    const double gj00 = gT[0][0] * c.R[0] + gT[0][1] * c.R[1] + gT[0][2] * c.R[2];
+    const double gj02 = gT[0][0] * c.R[6] + gT[0][1] * c.R[7] + gT[0][2] * c.R[8];
+    const double gj11 = gT[1][0] * c.R[3] + gT[1][1] * c.R[4] + gT[1][2] * c.R[5];
+    const double gj12 = gT[1][0] * c.R[6] + gT[1][1] * c.R[7] + gT[1][2] * c.R[8];
+    const double iz2 = iz * iz;
+    double gt0 = gu * fx * iz, gt1 = gv * fy * iz;
+    double gt2 = -gu * fx * t0 * iz2 - gv * fy * t1 * iz2;
+    gt2 += -gj00 * fx * iz2 - gj11 * fy * iz2;
+    // J02 = -fx rx / z, rx = clamp(x / z): d/dx = -fx/z^2 (unclamped); d/dz = fx rx/z^2 (+ fx x/z^3 unclamped)
+    gt2 += gj02 * fx * rx * iz2 + gj12 * fy * ry * iz2;
+    if (inx) {
+      gt0 += -gj02 * fx * iz2;
+      gt2 += gj02 * fx * t0 * iz2 * iz;
+    }
+    if (iny) {
+      gt1 += -gj12 * fy * iz2;
+      gt2 += gj12 * fy * t1 * iz2 * iz;
+    }
+    // dL/dSigma = T^T G T (symmetric), then dL/dM = (G + G^T) M = 2 G M
+    double gS[3][3];
+#pragma unroll
+    for (int rr = 0; rr < 3; ++rr)
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        gS[rr][k] = Tm[0][rr] * (G00 * Tm[0][k] + G01 * Tm[1][k]) + Tm[1][rr] * (G01 * Tm[0][k] + G11 * Tm[1][k]);
+    double gsc[3], gR[3][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      double acc[3];
+#pragma unroll
+      for (int rr = 0; rr < 3; ++rr)
+        acc[rr] = (gS[rr][0] + gS[0][rr]) * Rq[0][k] * s[k] + (gS[rr][1] + gS[1][rr]) * Rq[1][k] * s[k] +
+                  (gS[rr][2] + gS[2][rr]) * Rq[2][k] * s[k];
+      gsc[k] = acc[0] * Rq[0][k] + acc[1] * Rq[1][k] + acc[2] * Rq[2][k];
+      gR[0][k] = acc[0] * s[k];
+      gR[1][k] = acc[1] * s[k];
+      gR[2][k] = acc[2] * s[k];
+    }
+    const double gw = 2.0 * (-z * gR[0][1] + y * gR[0][2] + z * gR[1][0] - x * gR[1][2] - y * gR[2][0] + x * gR[2][1]);
+    const double gx = 2.0 * (y * gR[0][1] + z * gR[0][2] + y * gR[1][0] - 2.0 * x * gR[1][1] - w * gR[1][2] +
+                             z * gR[2][0] + w * gR[2][1] - 2.0 * x * gR[2][2]);
+    const double gy = 2.0 * (-2.0 * y * gR[0][0] + x * gR[0][1] + w * gR[0][2] + x * gR[1][0] + z * gR[1][2] -
+                             w * gR[2][0] + z * gR[2][1] - 2.0 * y * gR[2][2]);
+    const double gz = 2.0 * (-2.0 * z * gR[0][0] - w * gR[0][1] + x * gR[0][2] + w * gR[1][0] - 2.0 * z * gR[1][1] +
+                             y * gR[1][2] + x * gR[2][0] + y * gR[2][1]);
+    const double qd = w * gw + x * gx + y * gy + z * gz;
+    // this view's contribution, rounded to float, added in view order
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double gmu = (double)c.R[k] * gt0 + (double)c.R[3 + k] * gt1 + (double)c.R[6 + k] * gt2;
+      tmu[k] = acc_add(tmu[k], (float)(gmu + (double)cmu[k]));
+      tls[k] = acc_add(tls[k], (float)(gsc[k] * s[k]));
+    }
+    tq[0] = acc_add(tq[0], (float)((gw - w * qd) * iq));
+    tq[1] = acc_add(tq[1], (float)((gx - x * qd) * iq));
+    tq[2] = acc_add(tq[2], (float)((gy - y * qd) * iq));
+    tq[3] = acc_add(tq[3], (float)((gz - z * qd) * iq));
+    top = acc_add(top, (float)(go * op * (1.0 - op)));
+    if (a.mask_logits)  // o' = M o, s' = M s (M = 1 here): dL/dM = o dL/do' + sum_k s_k dL/ds'_k
+      tmask = acc_add(tmask, (float)((go * op + gsc[0] * s[0] + gsc[1] * s[1] + gsc[2] * s[2]) * sm * (1.0 - sm)));
+  }
+
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (b.g_means) b.g_means[k * n + i] += tmu[k];
+    if (b.g_log_scales) b.g_log_scales[k * n + i] += tls[k];
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (b.g_quats) b.g_quats[k * n + i] += tq[k];
+  if (b.g_opacity_logits) b.g_opacity_logits[i] += top;
+  if (b.g_mask_logits && a.mask_logits) b.g_mask_logits[i] += tmask;
+}
+
 hipError_t launch_project_bwd(const ProjectBwdArgs& a, const ViewTable& vt, int deg, hipStream_t s) {
   if (a.p.n == 0) return hipSuccess;
   const dim3 block(256), grid((unsigned)((a.p.n + 255) / 256));
   switch (deg) {
-    case 0: hipLaunchKernelGGL(project_bwd_kernel<0>, grid, block, 0, s, a, vt); break;
-    case 1: hipLaunchKernelGGL(project_bwd_kernel<1>, grid, block, 0, s, a, vt); break;
-    case 2: hipLaunchKernelGGL(project_bwd_kernel<2>, grid, block, 0, s, a, vt); break;
-    default: hipLaunchKernelGGL(project_bwd_kernel<3>, grid, block, 0, s, a, vt); break;
+    case 0: hipLaunchKernelGGL(project_bwd_color_kernel<0>, grid, block, 0, s, a, vt); break;
+    case 1: hipLaunchKernelGGL(project_bwd_color_kernel<1>, grid, block, 0, s, a, vt); break;
+    case 2: hipLaunchKernelGGL(project_bwd_color_kernel<2>, grid, block, 0, s, a, vt); break;
+    default: hipLaunchKernelGGL(project_bwd_color_kernel<3>, grid, block, 0, s, a, vt); break;
   }
+  hipLaunchKernelGGL(project_bwd_geom_kernel, grid, block, 0, s, a, vt);
   return hipGetLastError();
 }
 

@@ -51,31 +51,36 @@ __device__ __forceinline__ TileCtx tile_ctx(const ViewTable& vt, const RenderArg
   return c;
 }
 
-// Pixel-centre box covered by wave w (lanes handle consecutive row-major
-// pixel runs of length PPT).
+// Pixels of a tile are split into one sub-tile per wave (as square as the
+// tile allows, chosen on the host); a lane covers PPT consecutive pixels of a
+// sub-tile row.  Pixel p of thread t:
+__device__ __forceinline__ void pixel_of(const RenderArgs& a, int ppt, int t, int p, int tx, int ty, int* x, int* y) {
+  const int w = t >> 6, l = t & (kWave - 1);
+  const int sxi = w & ((1 << a.log2_sx) - 1), syi = w >> a.log2_sx;
+  const int li = l * ppt + p;
+  *x = (tx << a.log2_tw) + (sxi << a.log2_sw) + (li & ((1 << a.log2_sw) - 1));
+  *y = (ty << a.log2_th) + (syi << a.log2_sh) + (li >> a.log2_sw);
+}
+
+// Pixel-centre box of wave w's sub-tile.
 struct Box {
   float x0, x1, y0, y1;
 };
 
-__device__ __forceinline__ Box wave_box(int w, int ppt, int log2_tw, int tx, int ty, int log2_th) {
-  const int tw = 1 << log2_tw;
-  const int first = w * kWave * ppt, last = first + kWave * ppt - 1;
-  int xa = 0, xb = tw - 1;
-  if (kWave * ppt < tw) {
-    xa = first & (tw - 1);
-    xb = last & (tw - 1);
-  }
+__device__ __forceinline__ Box wave_box(const RenderArgs& a, int w, int tx, int ty) {
+  const int sxi = w & ((1 << a.log2_sx) - 1), syi = w >> a.log2_sx;
+  const int x0 = (tx << a.log2_tw) + (sxi << a.log2_sw), y0 = (ty << a.log2_th) + (syi << a.log2_sh);
   Box b;
-  b.x0 = (float)((tx << log2_tw) + xa) + 0.5f;
-  b.x1 = (float)((tx << log2_tw) + xb) + 0.5f;
-  b.y0 = (float)((ty << log2_th) + (first >> log2_tw)) + 0.5f;
-  b.y1 = (float)((ty << log2_th) + (last >> log2_tw)) + 0.5f;
+  b.x0 = (float)x0 + 0.5f;
+  b.x1 = (float)(x0 + (1 << a.log2_sw) - 1) + 0.5f;
+  b.y0 = (float)y0 + 0.5f;
+  b.y1 = (float)(y0 + (1 << a.log2_sh) - 1) + 0.5f;
   return b;
 }
 
 // Bit w set when record (u, v, conic, o', radius) may composite some pixel of wave w.
-__device__ __forceinline__ uint32_t footprint_mask(float4 ra, float4 rb, int nwaves, int ppt, int log2_tw,
-                                                   int log2_th, int tx, int ty) {
+__device__ __forceinline__ uint32_t footprint_mask(const RenderArgs& a, float4 ra, float4 rb, int nwaves, int tx,
+                                                   int ty) {
   const float u = ra.x, v = ra.y, A = ra.z, B = ra.w, C = rb.x, o = rb.y, r = rb.z;
   if (!(o >= kAlphaMin * 0.999f)) return 0u;  // alpha <= o' < 1/255 at every pixel
   float ex = r, ey = r;
@@ -94,7 +99,7 @@ __device__ __forceinline__ uint32_t footprint_mask(float4 ra, float4 rb, int nwa
   ey += 0.5f;
   uint32_t m = 0u;
   for (int w = 0; w < nwaves; ++w) {
-    const Box b = wave_box(w, ppt, log2_tw, tx, ty, log2_th);
+    const Box b = wave_box(a, w, tx, ty);
     const bool hit = (u + ex >= b.x0) && (u - ex <= b.x1) && (v + ey >= b.y0) && (v - ey <= b.y1);
     m |= hit ? (1u << w) : 0u;
   }
@@ -180,7 +185,6 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable
   const TileCtx tc = tile_ctx(vt, a, gtile);
   const ViewArgs& va = vt.v[tc.view];
   const int nthreads = blockDim.x;
-  const int tw = 1 << a.log2_tw;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave, nwaves = nthreads / kWave;
   const Lds L = lds_carve(smem, a.batch, nwaves, false);
   float4* s_a = L.a;
@@ -194,9 +198,8 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable
   bool done[PPT];
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
-    const int li = threadIdx.x * PPT + p;
-    const int x = tc.tx * tw + (li & (tw - 1));
-    const int y = (tc.ty << a.log2_th) + (li >> a.log2_tw);
+    int x, y;
+    pixel_of(a, PPT, threadIdx.x, p, tc.tx, tc.ty, &x, &y);
     px[p] = (float)x + 0.5f;
     py[p] = (float)y + 0.5f;
     T[p] = 1.0f;
@@ -223,7 +226,7 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable
       s_a[i] = ra;
       s_b[i] = rb;
       s_c[i] = a.splats[(size_t)rec * 3 + 2];
-      if (CULL) s_mask[i] = (uint8_t)footprint_mask(ra, rb, nwaves, PPT, a.log2_tw, a.log2_th, tc.tx, tc.ty);
+      if (CULL) s_mask[i] = (uint8_t)footprint_mask(a, ra, rb, nwaves, tc.tx, tc.ty);
     }
     __syncthreads();
     int len = cnt;
@@ -285,7 +288,6 @@ __global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs a, ViewTable
   const TileCtx tc = tile_ctx(vt, a, gtile);
   const ViewArgs& va = vt.v[tc.view];
   const int nthreads = blockDim.x;
-  const int tw = 1 << a.log2_tw;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave, nwaves = nthreads / kWave;
   const int64_t plane = (int64_t)va.W * va.H;
   const int batch = bwd_batch(a.batch, nwaves);
@@ -303,9 +305,8 @@ __global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs a, ViewTable
   int my_max = 0;
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
-    const int li = threadIdx.x * PPT + p;
-    const int x = tc.tx * tw + (li & (tw - 1));
-    const int y = (tc.ty << a.log2_th) + (li >> a.log2_tw);
+    int x, y;
+    pixel_of(a, PPT, threadIdx.x, p, tc.tx, tc.ty, &x, &y);
     px[p] = (float)x + 0.5f;
     py[p] = (float)y + 0.5f;
     T[p] = 1.0f;
@@ -351,7 +352,7 @@ __global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs a, ViewTable
       s_a[i] = ra;
       s_b[i] = rb;
       s_c[i] = a.splats[(size_t)rec * 3 + 2];
-      if (CULL) s_mask[i] = (uint8_t)footprint_mask(ra, rb, nwaves, PPT, a.log2_tw, a.log2_th, tc.tx, tc.ty);
+      if (CULL) s_mask[i] = (uint8_t)footprint_mask(a, ra, rb, nwaves, tc.tx, tc.ty);
     }
     for (int i = threadIdx.x; i < nwaves * batch * GS_GRAD_FLOATS; i += nthreads) s_part[i] = 0.0f;
     __syncthreads();

@@ -91,7 +91,7 @@ def load():
                                vp, vp, vp]
     L.gs_blend_bwd.restype = C.c_int
     L.gs_project_bwd.argtypes = [P(GsGaussians), P(GsCamera), C.c_int32, P(GsOpts), P(GsProjected), P(GsBinning),
-                                 vp, P(GsGrads), vp]
+                                 vp, P(GsGrads), vp, C.c_size_t, vp]
     L.gs_project_bwd.restype = C.c_int
     L.gs_strerror.argtypes = [C.c_int]
     L.gs_strerror.restype = C.c_char_p
@@ -176,6 +176,6 @@ def blend_bwd(cams_arr, V, n, opts_s, proj, bins, T_final, last, dL_dimage, grad
                                dL_dimage, grad_pair, stream)
 
 
-def project_bwd(g, cams_arr, V, opts_s, proj, bins, grad_pair, grads, stream) -> int:
+def project_bwd(g, cams_arr, V, opts_s, proj, bins, grad_pair, grads, ws, ws_bytes, stream) -> int:
     return load().gs_project_bwd(C.byref(g), cams_arr, V, C.byref(opts_s), C.byref(proj), C.byref(bins), grad_pair,
-                                 C.byref(grads), stream)
+                                 C.byref(grads), ws, ws_bytes, stream)

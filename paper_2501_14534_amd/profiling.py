@@ -40,6 +40,17 @@ def kernel_stats(d):
     return rows
 
 
+def launch_shapes(d):
+    """{(kernel name, grid size): [duration ns per dispatch]} from the kernel trace."""
+    out = defaultdict(list)
+    for f in _csvs(d, "kernel_trace.csv"):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                grid = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+                out[(r["Kernel_Name"], grid)].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    return out
+
+
 def counter_values(d):
     """{kernel name: [value per dispatch]} summed over the counter's instances."""
     per = defaultdict(lambda: defaultdict(float))
@@ -79,6 +90,16 @@ def cmd_stats(a):
     for r in rows[: a.top]:
         lines.append(f"| `{r['name'][:90]}` | {r['calls']} | {r['avg_ns'] / 1e3:.2f} | {r['total_ns'] / 1e6:.3f} | "
                      f"{r['pct']:.2f} |")
+    shapes = launch_shapes(a.dir)
+    if shapes:
+        lines += ["", "Per launch shape (grid = total work-items), kernels of libgs only:", "",
+                  "| kernel | grid | calls | avg us | min us | max us |", "|---|---|---|---|---|---|"]
+        for (name, grid), ds in sorted(shapes.items(), key=lambda kv: -sum(kv[1])):
+            if "gs::" not in name:
+                continue
+            lines.append(f"| `{name[:60]}` | {grid} | {len(ds)} | {statistics.mean(ds) / 1e3:.2f} | "
+                         f"{min(ds) / 1e3:.2f} | {max(ds) / 1e3:.2f} |")
+    lines.append(f"\nkernel source hash: {kernel_source_hash()}")
     text = "\n".join(lines) + "\n"
     if a.out:
         with open(a.out, "w") as f:

@@ -124,7 +124,7 @@ class Rasterizer:
         g = self.gaussians(params)
         gr = gs.GsGrads(*[gs.ptr(grads.get(k)) for k in PARAM_NAMES], gs.ptr(mean2d))
         gs.check(gs.project_bwd(g, self.cams_arr, self.V, self.opts_s, self.proj, self.bins, gs.ptr(grad_pair), gr,
-                                _stream()), "gs_project_bwd")
+                                gs.ptr(self.ws), self.ws_bytes, _stream()), "gs_project_bwd")
 
     def overflowed(self) -> bool:
         return bool(self.status.item())
@@ -274,11 +274,14 @@ class Step:
         else:
             self._body()
 
-    def run(self):
-        """One step with the capacity check (synchronises)."""
+    def run(self, headroom: float = 1.25):
+        """One step with the capacity check (synchronises): grows the binning
+        buffers on overflow and shrinks them when they exceed twice the need,
+        re-capturing the graph in both cases."""
         self.launch()
-        if self.rast.overflowed():
-            self.rast.set_capacity(int(self.rast.pairs() * 1.25) + 1024)
+        need = self.rast.pairs()
+        if self.rast.overflowed() or self.rast.capacity > 2 * headroom * need + (1 << 20):
+            self.rast.set_capacity(int(need * headroom) + 1024)
             self.graph = None
             self.launch()
             assert not self.rast.overflowed()
