@@ -206,9 +206,9 @@ def main():
     K = r.pairs()
     useful_pairs = int(r.last.to(torch.int64).sum())
 
-    # dominant single-kernel stage
-    single = {"render_fwd": "render_fwd_kernel", "blend_bwd": "render_bwd_kernel", "project": "project_kernel",
-              "project_bwd": "project_bwd_kernel"}
+    # dominant single-kernel stage (project_bwd runs two kernels: colour, then geometry;
+    # render_fwd's stage also holds a fill of the chunk-slot owners, ~5 us)
+    single = {"render_fwd": "render_fwd_kernel", "blend_bwd": "render_bwd_kernel", "project": "project_kernel"}
     dom = max(single, key=lambda k: stage_ms[k])
     src_hash = kernel_source_hash()
     workload = f"config{args.config}"
@@ -220,10 +220,7 @@ def main():
                     frac=round(achieved / PEAK_FP32_TFLOPS, 5))
     else:
         nrec = V * sc.n
-        if dom == "project":
-            byts = 252.0 * sc.n + 52.0 * nrec
-        else:
-            byts = 36.0 * nrec + 504.0 * sc.n
+        byts = 252.0 * sc.n + 52.0 * nrec  # project: parameters read once, 48 + 4 B per record
         achieved = byts / t_s / 1e9
         roof = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
                     frac=round(achieved / PEAK_HBM_GBS, 5))

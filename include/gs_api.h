@@ -91,6 +91,10 @@ typedef struct gs_opts {
   int32_t pixels_per_thread; /* 1, 2 or 4; tile_w*tile_h/ppt a multiple of 64, <= 256      */
   int32_t subtile_cull;      /* 1: each wave walks only the splats whose alpha >= 1/255
                                 footprint can reach its pixels (same result, less work); 0: off */
+  int32_t bwd_chunk;         /* entries of a tile's list per backward work item: a power of
+                                two in [16, 2^20], or 0 for one item per tile.  The forward
+                                records each pixel's state at every multiple of bwd_chunk so
+                                the backward can walk the chunks of one long list in parallel. */
 } gs_opts;
 
 /* Projected (view, Gaussian) records, written by gs_project.
@@ -111,7 +115,8 @@ typedef struct gs_projected {
 /* Sorted (tile, depth) lists.  keys/ids/pair_index hold `capacity` entries;
  * after a successful gs_bin_sort the first K = *count are sorted by key, then
  * by id:
- *   key = (global tile << 32) | IEEE bits of the record's depth
+ *   key = (global tile << 32) | IEEE bits of the record's depth (keys may be
+ *         NULL: the compositing calls do not read them)
  *   id  = record index (view * n + gaussian)
  *   pair_index = position of the pair in emission order, where each record's
  *                pairs are contiguous, records in index order, and a record's
@@ -119,6 +124,12 @@ typedef struct gs_projected {
  * offsets: [V*n] first emission position of each record's pairs (its
  *          tiles_touched consecutive positions follow).
  * ranges: [total_tiles][2] = [start, end) into keys/ids, [0,0) when empty.
+ * order: [total_tiles] or NULL.  When given, gs_bin_sort writes a
+ *        permutation of the global tile ids, longest list first (lengths
+ *        grouped by powers of two, order within a group unspecified), and
+ *        the compositing calls process tiles in that order, so the deepest
+ *        tiles of every view start first.  The order affects timing only:
+ *        every tile's results are computed independently.  NULL: tile-id order.
  * count, status: device words written by gs_bin_sort.  status = 0 on success,
  * 1 when K > capacity: then no list is written, every range is empty and
  * *count still holds K, so the caller can grow the buffers and run again. */
@@ -128,6 +139,7 @@ typedef struct gs_binning {
   uint32_t* pair_index;
   uint32_t* offsets;
   uint32_t* ranges;
+  uint32_t* order;   /* optional */
   uint64_t capacity; /* < 2^32 */
   uint32_t* count;   /* device, 1 word */
   int32_t* status;   /* device, 1 word */
@@ -152,8 +164,12 @@ typedef struct gs_grads {
 int gs_view_sizes(const gs_camera* cams, int32_t V, const gs_opts* opts, int64_t* total_tiles,
                   int64_t* total_pixels);
 
-/* Bytes of scratch memory that gs_bin_sort and gs_render_bwd need for n
- * Gaussians, V views and a list capacity (host only; 0 on invalid input). */
+/* Bytes of the one workspace buffer that gs_bin_sort, gs_render_fwd and
+ * gs_render_bwd (or gs_blend_bwd + gs_project_bwd) share for n Gaussians, V
+ * views and a list capacity (host only; 0 on invalid input).  gs_bin_sort
+ * uses it as scratch; gs_render_fwd writes the per-chunk pixel states there,
+ * and the backward of the same step reads them, so the buffer must not be
+ * reused for anything else between the forward and the backward. */
 size_t gs_workspace_size(int64_t n, int32_t V, const gs_camera* cams, const gs_opts* opts, uint64_t capacity);
 
 /* Projection of every Gaussian into every view (Sec. 3.1 Eq. 1, Sec. 3.2.4,
@@ -167,9 +183,11 @@ int gs_project(const gs_gaussians* g, const gs_camera* cams, int32_t V, const gs
                gs_projected* out, gs_stream_t stream);
 
 /* Tile binning and ordering of the records of a gs_project call: device-wide
- * scan of tiles_touched, emission of one (tile, depth) key per touched tile,
- * LSD radix sort over the significant key bits (stable, so equal keys keep
- * id order), per-tile ranges.  Needs ws_bytes >= gs_workspace_size(...). */
+ * scans of tiles_touched, a stable LSD radix sort of the visible records by
+ * their depth bits, emission of one pair per touched tile in that order, a
+ * stable LSD radix sort of the pairs by tile id (together: the order of keys
+ * then ids described above), per-tile ranges and, if order is given, the
+ * heaviest-first tile schedule.  Needs ws_bytes >= gs_workspace_size(...). */
 int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int32_t V, int64_t n, const gs_opts* opts,
                 gs_binning* out, void* ws, size_t ws_bytes, gs_stream_t stream);
 
@@ -179,14 +197,19 @@ int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int32_t V, int6
  * transmittance under 1e-4, output C + T bg.
  * image: [sum_v 3*H_v*W_v] planar per view ([3][H][W]), views concatenated.
  * T_final, last_contrib: [sum_v H_v*W_v]; last_contrib counts the list
- * entries of the pixel's tile up to and including the last composited one. */
+ * entries of the pixel's tile up to and including the last composited one.
+ * ws (ws_bytes >= gs_workspace_size(...)): receives, for every multiple of
+ * opts->bwd_chunk that the walk of a tile passes, each pixel's transmittance
+ * there and the colour composited after it; the backward reads them. */
 int gs_render_fwd(const gs_projected* proj, const gs_binning* bins, const gs_camera* cams, int32_t V,
                   int64_t n, const gs_opts* opts, float* image, float* T_final, int32_t* last_contrib,
-                  gs_stream_t stream);
+                  void* ws, size_t ws_bytes, gs_stream_t stream);
 
 /* Backward of gs_render_fwd and gs_project for dL/dimage (layout of image):
- * each tile's list is walked back to front from its largest last_contrib,
- * transmittance recovered by division; per (tile, splat) the 9 partials are
+ * each tile's list is walked back to front from its largest last_contrib, in
+ * chunks of opts->bwd_chunk entries that run in parallel, each starting from
+ * the state the forward recorded at its end; transmittance is recovered by
+ * division within a chunk; per (tile, splat) the 9 partials are
  * summed over the workgroup's pixels in a fixed order and stored once, at the
  * pair's emission position; then, per Gaussian, its pairs are summed in
  * emission order and the chain rule runs to the raw parameters including the
@@ -205,12 +228,12 @@ int gs_render_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t V, const
  * to grad_pair ([capacity][9], indexed by pair_index; no zeroing needed).
  * gs_project_bwd: per Gaussian, the sum of its pairs' gradients in emission
  * order, then the chain rule to the raw parameters (the second half of
- * gs_render_bwd), accumulated into `grads`.  ws has gs_render_bwd's layout
- * (ws_bytes >= gs_workspace_size(...)); grad_pair may point at its start, as
- * it does inside gs_render_bwd.                                             */
+ * gs_render_bwd), accumulated into `grads`.  ws is the workspace of the
+ * step's gs_render_fwd (ws_bytes >= gs_workspace_size(...)); grad_pair may
+ * point at its start, as it does inside gs_render_bwd.                      */
 int gs_blend_bwd(const gs_camera* cams, int32_t V, int64_t n, const gs_opts* opts, const gs_projected* proj,
                  const gs_binning* bins, const float* T_final, const int32_t* last_contrib, const float* dL_dimage,
-                 float* grad_pair, gs_stream_t stream);
+                 float* grad_pair, const void* ws, size_t ws_bytes, gs_stream_t stream);
 int gs_project_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t V, const gs_opts* opts,
                    const gs_projected* proj, const gs_binning* bins, const float* grad_pair, gs_grads* grads,
                    void* ws, size_t ws_bytes, gs_stream_t stream);

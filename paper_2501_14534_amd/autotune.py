@@ -1,9 +1,11 @@
-"""Tile-shape / batch-depth / pixels-per-thread autotuner with a JSON cache.
+"""Tile-shape / batch-depth / pixels-per-thread / backward-chunk autotuner with a JSON cache.
 
 The image does not depend on these choices (every pixel walks the same splats
 in the same order whatever the tiling: each pixel applies the square test), so
 the tuner may pick freely by time.  Candidates are timed as whole fwd+bwd
-steps of the workload; the winner is stored per (device arch, workload key).
+steps of the workload: first the tilings with the default backward chunk,
+then the backward chunk lengths for the fastest tiling; the winner is stored
+per (device arch, workload key).
 """
 from __future__ import annotations
 
@@ -23,6 +25,8 @@ CANDIDATES: List[Tuple[int, int, int, int, int]] = [
     (8, 8, 64, 1, 1), (8, 8, 32, 1, 1), (16, 8, 128, 1, 1), (16, 8, 64, 2, 1), (32, 8, 256, 1, 1),
     (32, 8, 128, 2, 1), (32, 16, 256, 2, 1), (32, 16, 128, 4, 1),
 ]
+# list entries per backward work item (0: one item per tile)
+CHUNKS: List[int] = [256, 512, 1024, 2048, 4096, 0]
 
 
 def workload_key(wl) -> str:
@@ -56,14 +60,14 @@ def best_opts(wl, arch: Optional[str] = None):
     if not e:
         return wl.opts
     return dataclasses.replace(wl.opts, tile_w=e["tile_w"], tile_h=e["tile_h"], batch_depth=e["batch_depth"],
-                               pixels_per_thread=e["pixels_per_thread"], subtile_cull=e.get("subtile_cull", 1))
+                               pixels_per_thread=e["pixels_per_thread"], subtile_cull=e.get("subtile_cull", 1),
+                               bwd_chunk=e.get("bwd_chunk", wl.opts.bwd_chunk))
 
 
-def tune(wl, candidates: Iterable[Tuple[int, int, int, int, int]] = CANDIDATES, steps: int = 5, warmup: int = 2,
-         write: bool = True, verbose: bool = True, cache_path: Optional[str] = None) -> dict:
+def tune(wl, candidates: Iterable[Tuple[int, int, int, int, int]] = CANDIDATES, chunks: Iterable[int] = CHUNKS,
+         steps: int = 5, warmup: int = 2, write: bool = True, verbose: bool = True,
+         cache_path: Optional[str] = None) -> dict:
     """Time each candidate's fwd+bwd step and store the fastest in the cache."""
-    import time
-
     import numpy as np
     import torch
 
@@ -74,31 +78,25 @@ def tune(wl, candidates: Iterable[Tuple[int, int, int, int, int]] = CANDIDATES, 
     target = torch.from_numpy(np.concatenate([t.reshape(-1) for t in wl.targets])).cuda()
     results = []
     ref_img = None
-    for tw, th, bd, ppt, cull in candidates:
-        o = dataclasses.replace(wl.opts, tile_w=tw, tile_h=th, batch_depth=bd, pixels_per_thread=ppt,
-                                subtile_cull=cull)
-        r = raster.Rasterizer(sc.n, sc.sh_degree, wl.cams, o, mask_eps=sc.mask_eps, sh_mask_eps=sc.sh_mask_eps)
-        st = raster.Step(r, params, target, graph=True)
-        st.run()
-        for _ in range(warmup):
-            st.launch()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            st.launch()
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / steps
-        img = r.image.clone()
-        if ref_img is None:
-            ref_img = img
-        same = bool(torch.equal(img, ref_img))
-        results.append(dict(tile_w=tw, tile_h=th, batch_depth=bd, pixels_per_thread=ppt, subtile_cull=cull, ms=ms,
-                            image_equal=same))
-        if verbose:
-            print(f"  tile {tw}x{th} batch {bd} ppt {ppt} cull {cull}: {ms:.3f} ms/step, image identical: {same}",
-                  flush=True)
-        del st, r
-        torch.cuda.empty_cache()
+    grid = [(tw, th, bd, ppt, cull, wl.opts.bwd_chunk) for tw, th, bd, ppt, cull in candidates]
+    tried = set()
+
+    def run(cands):
+        nonlocal ref_img
+        for cand in cands:
+            if cand in tried:
+                continue
+            tried.add(cand)
+            results.append(_time_one(wl, params, target, cand, steps, warmup, verbose))
+            if ref_img is None:
+                ref_img = results[-1].pop("_img")
+            else:
+                results[-1]["image_equal"] = bool(torch.equal(results[-1].pop("_img"), ref_img))
+
+    run(grid)
+    ok = [x for x in results if x["image_equal"]]
+    b = min(ok, key=lambda x: x["ms"])
+    run([(b["tile_w"], b["tile_h"], b["batch_depth"], b["pixels_per_thread"], b["subtile_cull"], ch) for ch in chunks])
     ok = [x for x in results if x["image_equal"]]
     best = min(ok, key=lambda x: x["ms"])
     if write:
@@ -108,6 +106,38 @@ def tune(wl, candidates: Iterable[Tuple[int, int, int, int, int]] = CANDIDATES, 
         with open(path, "w") as f:
             json.dump(cache, f, indent=1, sort_keys=True)
     return dict(best=best, results=results)
+
+
+def _time_one(wl, params, target, cand, steps, warmup, verbose) -> dict:
+    """One candidate's fwd+bwd step time (graph replays) and its image."""
+    import time
+
+    import torch
+
+    from . import raster
+
+    sc = wl.scene
+    tw, th, bd, ppt, cull, chunk = cand
+    o = dataclasses.replace(wl.opts, tile_w=tw, tile_h=th, batch_depth=bd, pixels_per_thread=ppt,
+                            subtile_cull=cull, bwd_chunk=chunk)
+    r = raster.Rasterizer(sc.n, sc.sh_degree, wl.cams, o, mask_eps=sc.mask_eps, sh_mask_eps=sc.sh_mask_eps)
+    st = raster.Step(r, params, target, graph=True)
+    st.run()
+    for _ in range(warmup):
+        st.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st.launch()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    out = dict(tile_w=tw, tile_h=th, batch_depth=bd, pixels_per_thread=ppt, subtile_cull=cull, bwd_chunk=chunk,
+               ms=ms, image_equal=True, _img=r.image.clone())
+    if verbose:
+        print(f"  tile {tw}x{th} batch {bd} ppt {ppt} cull {cull} chunk {chunk}: {ms:.3f} ms/step", flush=True)
+    del st, r
+    torch.cuda.empty_cache()
+    return out
 
 
 if __name__ == "__main__":

@@ -1,18 +1,30 @@
-// Tile binning and (tile, depth) ordering of projected records.
+// Tile binning and (tile, depth) ordering of projected records, depth first.
 //
-//   1. count_reduce + scan_top: device-wide exclusive scan of tiles_touched
-//      (1024 records per block); the top level also writes K and the
-//      capacity status.
-//   2. emit_keys: each block rescans its 1024 counts, then its threads fill
-//      the block's contiguous output range slot by slot (binary search of the
-//      owning record in LDS), so writes are coalesced and big Gaussians do not
-//      serialise a lane.  Keys come out in record order.
-//   3. LSD radix sort, 8-bit digits, over the significant key bits only
-//      (32 depth bits + ceil(log2 #tiles) tile bits).  Each pass: per-block
-//      digit histogram, per-digit scan across blocks, stable scatter ranked
-//      with 64-lane ballots.  Stability keeps record order among equal keys.
-//   4. tile_ranges: [start, end) of every tile from run boundaries.
-// Every kernel reads K from device memory, so nothing waits for the host.
+//   1. count_reduce + scan_top: device-wide exclusive scans of tiles_touched
+//      (the canonical emission offsets, K and the capacity status) and of
+//      the visibility flags (tiles_touched > 0), 1024 records per block.
+//   2. compact_visible: writes each record's canonical offset and packs each
+//      visible record as (depth bits, compact index) plus a 16-byte emission
+//      descriptor (first tile, rect width and height, canonical offset, id).
+//   3. LSD radix sort of the visible records by their 32 depth bits (four
+//      8-bit passes; stable, so equal depths keep record order).
+//   4. emit_pairs: the records, now in depth order, emit one (tile, canonical
+//      pair index, record id) per touched tile into a contiguous
+//      depth-ordered range; a block fills its range slot by slot (binary
+//      search of the owning record in LDS), so writes are coalesced and big
+//      Gaussians do not serialise a lane.
+//   5. LSD radix sort of the pairs by tile id only (ceil(log2 #tiles) bits,
+//      two passes up to 65536 tiles), carrying pair index and record id.
+//      Stability keeps depth order, and record order among equal depths,
+//      inside every tile: the order of a sort by (tile << 32 | depth bits)
+//      then record id.
+//   6. tile_ranges: [start, end) of every tile and, if asked for, the 64-bit keys.
+//   7. tile_order_*: the heaviest-first tile schedule.
+// The sort passes move 8 bytes per element: 4 passes over the visible
+// records plus 2 over the pairs, instead of 6 passes of 12 bytes over the
+// pairs.  Each pass: per-block digit histogram, per-digit scan across blocks,
+// stable scatter ranked with 64-lane ballots.  Every kernel reads its
+// element count from device memory, so nothing waits for the host.
 #include "gs_common.h"
 #include "kernels.h"
 
@@ -53,23 +65,33 @@ __device__ __forceinline__ uint32_t block_exclusive_scan_256(uint32_t x, uint32_
   return incl - x + off;
 }
 
+// Per block of 1024 records: sum of tiles_touched and number of visible records.
 __global__ __launch_bounds__(kScanThreads) void count_reduce(const uint32_t* __restrict__ tt, int64_t len,
-                                                             uint32_t* __restrict__ block_sums) {
+                                                             uint32_t* __restrict__ block_sums,
+                                                             uint32_t* __restrict__ vis_sums) {
   __shared__ uint32_t s_wave[kScanThreads / kWave];
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-  uint32_t s = 0;
+  uint32_t s = 0, v = 0;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k)
-    if (base + k < len) s += tt[base + k];
+    if (base + k < len) {
+      const uint32_t c = tt[base + k];
+      s += c;
+      v += c != 0u;
+    }
   uint32_t tot;
   block_exclusive_scan_256(s, &tot, s_wave);
   if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
+  block_exclusive_scan_256(v, &tot, s_wave);
+  if (threadIdx.x == 0) vis_sums[blockIdx.x] = tot;
 }
 
-// Single block: exclusive scan of nb block sums; total K in 64 bits.
+// Single block: exclusive scan of nb block sums and their total (64-bit
+// accumulation, saturated to 32 bits).  With a status word: status = 1 when
+// the total exceeds capacity.
 __global__ __launch_bounds__(1024) void scan_top(const uint32_t* __restrict__ sums, int64_t nb,
                                                  uint32_t* __restrict__ offsets, uint64_t capacity,
-                                                 uint32_t* count, int32_t* status) {
+                                                 uint32_t* total_out, int32_t* status) {
   __shared__ uint32_t s_wave[16];
   __shared__ unsigned long long s_carry;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
@@ -98,68 +120,135 @@ __global__ __launch_bounds__(1024) void scan_top(const uint32_t* __restrict__ su
     if (threadIdx.x == 0) s_carry = carry + tot;
     __syncthreads();
   }
-  if (threadIdx.x == 0 && count) {
+  if (threadIdx.x == 0) {
     const unsigned long long K = s_carry;
-    *count = K > 0xffffffffull ? 0xffffffffu : (uint32_t)K;
-    *status = K > (unsigned long long)capacity ? 1 : 0;
+    *total_out = K > 0xffffffffull ? 0xffffffffu : (uint32_t)K;
+    if (status) *status = K > (unsigned long long)capacity ? 1 : 0;
   }
 }
 
-// Emission: pair e of record r (e in [offsets[r], offsets[r] + tiles_touched[r]),
-// the record's tiles in row-major order) gets key (tile << 32 | depth bits),
-// value e, and owner[e] = r.
-__global__ __launch_bounds__(kScanThreads) void emit_keys(const float4* __restrict__ splats,
-                                                          const uint32_t* __restrict__ tt, int64_t nrec, int64_t n,
-                                                          const uint32_t* __restrict__ block_offsets,
-                                                          const int32_t* __restrict__ status, ViewTable vt,
-                                                          float inv_tw, float inv_th, uint64_t* __restrict__ keys,
-                                                          uint32_t* __restrict__ vals, uint32_t* __restrict__ owner,
-                                                          uint32_t* __restrict__ offsets) {
+// Canonical emission offsets of every record (pairs of record r occupy
+// [offsets[r], offsets[r] + tiles_touched[r]), records in index order), and
+// the visible records packed in record order as (depth bits, compact index)
+// with their emission descriptors; drec[r] = depth bits for the keys.
+__global__ __launch_bounds__(kScanThreads) void compact_visible(const float4* __restrict__ splats,
+                                                                const uint32_t* __restrict__ tt, int64_t nrec,
+                                                                int64_t n, ViewTable vt, float inv_tw, float inv_th,
+                                                                const uint32_t* __restrict__ block_offsets,
+                                                                const uint32_t* __restrict__ vis_offsets,
+                                                                const int32_t* __restrict__ status,
+                                                                uint32_t* __restrict__ offsets,
+                                                                uint32_t* __restrict__ dkey,
+                                                                uint32_t* __restrict__ dval, uint4* __restrict__ desc,
+                                                                uint32_t* __restrict__ drec) {
+  __shared__ uint32_t s_wave[kScanThreads / kWave];
+  if (*status != 0) return;  // overflow: no lists this step
+  const int64_t blk = (int64_t)blockIdx.x * kScanTile;
+  const int li0 = threadIdx.x * kScanItems;
+  uint32_t c[kScanItems];
+  uint32_t s = 0, v = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t r = blk + li0 + k;
+    c[k] = r < nrec ? tt[r] : 0u;
+    s += c[k];
+    v += c[k] != 0u;
+  }
+  uint32_t tot;
+  uint32_t ex = block_exclusive_scan_256(s, &tot, s_wave) + block_offsets[blockIdx.x];
+  uint32_t vx = block_exclusive_scan_256(v, &tot, s_wave) + vis_offsets[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t r = blk + li0 + k;
+    if (r < nrec) offsets[r] = ex;
+    if (c[k]) {
+      const float4 p0 = splats[r * 3 + 0];
+      const float4 p1 = splats[r * 3 + 1];
+      const ViewArgs& va = vt.v[(int)(r / n)];
+      int x0, y0, x1, y1;
+      tile_rect(p0.x, p0.y, p1.z, inv_tw, inv_th, va.TX, va.TY, &x0, &y0, &x1, &y1);
+      const uint32_t dbits = __float_as_uint(p1.w);  // depth > near plane > 0: bits order as values
+      dkey[vx] = dbits;
+      dval[vx] = vx;
+      desc[vx] = make_uint4((uint32_t)(va.tile_off + y0 * va.TX + x0),
+                            (uint32_t)(x1 - x0 + 1) | ((uint32_t)(y1 - y0 + 1) << 16), ex, (uint32_t)r);
+      if (drec) drec[r] = dbits;
+      ++vx;
+    }
+    ex += c[k];
+  }
+}
+
+// Per block of 1024 depth-sorted records: their number of pairs.
+__global__ __launch_bounds__(kScanThreads) void gather_reduce(const uint4* __restrict__ desc,
+                                                              const uint32_t* __restrict__ dval,
+                                                              const uint32_t* __restrict__ nvis,
+                                                              const int32_t* __restrict__ status,
+                                                              uint32_t* __restrict__ block_sums) {
+  __shared__ uint32_t s_wave[kScanThreads / kWave];
+  const uint32_t N = effective_count(nvis, status);
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k)
+    if (base + k < N) {
+      const uint32_t wh = desc[dval[base + k]].y;
+      s += (wh & 0xffffu) * (wh >> 16);
+    }
+  uint32_t tot;
+  block_exclusive_scan_256(s, &tot, s_wave);
+  if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
+}
+
+// Emission in depth order: sorted record m emits, at depth-ordered positions
+// [eoff(m), eoff(m) + w h), its tiles in row-major order of its tile
+// rectangle: tile id, the pair's canonical index offsets[r] + j, and r.
+__global__ __launch_bounds__(kScanThreads) void emit_pairs(const uint4* __restrict__ desc,
+                                                           const uint32_t* __restrict__ dval,
+                                                           const uint32_t* __restrict__ nvis, int64_t n,
+                                                           const uint32_t* __restrict__ eblock_offsets,
+                                                           const int32_t* __restrict__ status, ViewTable vt,
+                                                           uint32_t* __restrict__ tkey, uint32_t* __restrict__ tval,
+                                                           uint32_t* __restrict__ trec) {
   __shared__ uint32_t s_wave[kScanThreads / kWave];
   __shared__ uint32_t s_pref[kScanTile];
   __shared__ uint32_t s_base[kScanTile];
   __shared__ uint32_t s_w[kScanTile];
   __shared__ uint32_t s_tx[kScanTile];
-  __shared__ uint32_t s_depth[kScanTile];
-  if (*status != 0) return;
+  __shared__ uint32_t s_rec[kScanTile];
+  __shared__ uint32_t s_off[kScanTile];
+  const uint32_t N = effective_count(nvis, status);
   const int64_t blk = (int64_t)blockIdx.x * kScanTile;
+  if (blk >= N) return;  // uniform
   const int li0 = threadIdx.x * kScanItems;
   uint32_t c[kScanItems];
   uint32_t s = 0;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    const int64_t r = blk + li0 + k;
-    c[k] = r < nrec ? tt[r] : 0u;
+    const int64_t m = blk + li0 + k;
+    const int li = li0 + k;
+    c[k] = 0u;
+    if (m < N) {
+      const uint4 d = desc[dval[m]];
+      const uint32_t w = d.y & 0xffffu;
+      c[k] = w * (d.y >> 16);
+      s_base[li] = d.x;
+      s_w[li] = w;
+      s_off[li] = d.z;
+      s_rec[li] = d.w;
+      s_tx[li] = (uint32_t)vt.v[(int)((int64_t)d.w / n)].TX;
+    }
     s += c[k];
   }
   uint32_t total;
   uint32_t ex = block_exclusive_scan_256(s, &total, s_wave);
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    const int li = li0 + k;
-    s_pref[li] = ex;
-    if (c[k]) {
-      const int64_t r = blk + li;
-      const int v = (int)(r / n);
-      const ViewArgs& va = vt.v[v];
-      const float4 p0 = splats[r * 3 + 0];
-      const float4 p1 = splats[r * 3 + 1];
-      int x0, y0, x1, y1;
-      tile_rect(p0.x, p0.y, p1.z, inv_tw, inv_th, va.TX, va.TY, &x0, &y0, &x1, &y1);
-      s_base[li] = (uint32_t)(va.tile_off + y0 * va.TX + x0);
-      s_w[li] = (uint32_t)(x1 - x0 + 1);
-      s_tx[li] = (uint32_t)va.TX;
-      s_depth[li] = __float_as_uint(p1.w);
-    }
+    s_pref[li0 + k] = ex;
     ex += c[k];
   }
   __syncthreads();
-  const uint32_t out0 = block_offsets[blockIdx.x];
-#pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    const int64_t r = blk + li0 + k;
-    if (r < nrec) offsets[r] = out0 + s_pref[li0 + k];
-  }
+  const uint32_t out0 = eblock_offsets[blockIdx.x];
   for (uint32_t slot = threadIdx.x; slot < total; slot += kScanThreads) {
     // last record whose exclusive prefix is <= slot
     int lo = 0, hi = kScanTile;  // invariant: s_pref[lo] <= slot < s_pref[hi] (virtual s_pref[kScanTile] = total)
@@ -170,15 +259,14 @@ __global__ __launch_bounds__(kScanThreads) void emit_keys(const float4* __restri
     const uint32_t j = slot - s_pref[lo];
     const uint32_t w = s_w[lo];
     const uint32_t ty = j / w, tx = j - ty * w;
-    const uint32_t gt = s_base[lo] + ty * s_tx[lo] + tx;
-    const uint32_t e = out0 + slot;
-    keys[e] = ((uint64_t)gt << 32) | s_depth[lo];
-    vals[e] = e;
-    owner[e] = (uint32_t)(blk + lo);
+    tkey[out0 + slot] = s_base[lo] + ty * s_tx[lo] + tx;
+    tval[out0 + slot] = s_off[lo] + j;  // canonical pair index
+    trec[out0 + slot] = s_rec[lo];
   }
 }
 
-__global__ __launch_bounds__(kSortThreads) void radix_hist(const uint64_t* __restrict__ keys,
+template <typename KT>
+__global__ __launch_bounds__(kSortThreads) void radix_hist(const KT* __restrict__ keys,
                                                            const uint32_t* __restrict__ count,
                                                            const int32_t* __restrict__ status, int shift, int64_t nblk,
                                                            uint32_t* __restrict__ hist) {
@@ -233,9 +321,12 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
   return m;
 }
 
-__global__ __launch_bounds__(kSortThreads) void radix_scatter(const uint64_t* __restrict__ kin,
+// NV value arrays travel with the keys (NV = 1 or 2; the second may be null when NV = 1).
+template <typename KT, int NV>
+__global__ __launch_bounds__(kSortThreads) void radix_scatter(const KT* __restrict__ kin,
                                                               const uint32_t* __restrict__ vin,
-                                                              uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                              const uint32_t* __restrict__ vin2, KT* __restrict__ kout,
+                                                              uint32_t* __restrict__ vout, uint32_t* __restrict__ vout2,
                                                               const uint32_t* __restrict__ count,
                                                               const int32_t* __restrict__ status, int shift,
                                                               int64_t nblk, const uint32_t* __restrict__ hist,
@@ -255,14 +346,15 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter(const uint64_t* __
   s_run[t] = dbase + hist[(int64_t)t * nblk + blockIdx.x];
 #pragma unroll
   for (int w = 0; w < kWaves; ++w) s_cnt[w][t] = 0;
-  uint64_t key[kSortItems];
-  uint32_t val[kSortItems];
+  KT key[kSortItems];
+  uint32_t val[kSortItems], val2[NV == 2 ? kSortItems : 1];
 #pragma unroll
   for (int k = 0; k < kSortItems; ++k) {
     const int64_t i = base + k * kSortThreads + t;
     if (i < K) {
       key[k] = kin[i];
       val[k] = vin[i];
+      if (NV == 2) val2[k] = vin2[i];
     }
   }
   __syncthreads();
@@ -291,22 +383,73 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter(const uint64_t* __
       const uint32_t pos = s_pre[wave][d] + rank;
       kout[pos] = key[k];
       vout[pos] = val[k];
+      if (NV == 2) vout2[pos] = val2[k];
     }
   }
 }
 
-// Per sorted pair: record id from its emission position, and the tile's run boundaries.
-__global__ void tile_ranges(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ pair_index,
-                            const uint32_t* __restrict__ owner, const uint32_t* __restrict__ count,
-                            const int32_t* __restrict__ status, uint32_t* __restrict__ ids,
+// Per sorted pair: [start, end) of its tile's run and, if asked for, the 64-bit key.
+__global__ void tile_ranges(const uint32_t* __restrict__ tkey, const uint32_t* __restrict__ ids,
+                            const uint32_t* __restrict__ drec, const uint32_t* __restrict__ count,
+                            const int32_t* __restrict__ status, uint64_t* __restrict__ keys,
                             uint32_t* __restrict__ ranges) {
   const uint32_t K = effective_count(count, status);
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= K) return;
-  ids[i] = owner[pair_index[i]];
-  const uint32_t t = (uint32_t)(keys[i] >> 32);
-  if (i == 0 || (uint32_t)(keys[i - 1] >> 32) != t) ranges[2 * (int64_t)t] = (uint32_t)i;
-  if (i == (int64_t)K - 1 || (uint32_t)(keys[i + 1] >> 32) != t) ranges[2 * (int64_t)t + 1] = (uint32_t)(i + 1);
+  const uint32_t t = tkey[i];
+  if (keys) keys[i] = ((uint64_t)t << 32) | drec[ids[i]];
+  if (i == 0 || tkey[i - 1] != t) ranges[2 * (int64_t)t] = (uint32_t)i;
+  if (i == (int64_t)K - 1 || tkey[i + 1] != t) ranges[2 * (int64_t)t + 1] = (uint32_t)(i + 1);
+}
+
+// Heaviest-first tile schedule: tiles grouped by the bit length of their list
+// length (33 groups), groups in decreasing order.  hist[0..63] counts the
+// groups, hist[64..127] becomes each group's running write position.
+__device__ __forceinline__ int length_group(uint32_t len) { return len ? 32 - __clz(len) : 0; }
+
+__device__ __forceinline__ uint32_t tile_len(const uint32_t* ranges, const int32_t* status, int64_t t) {
+  return *status == 0 ? ranges[2 * t + 1] - ranges[2 * t] : 0u;
+}
+
+__global__ __launch_bounds__(256) void tile_order_count(const uint32_t* __restrict__ ranges,
+                                                        const int32_t* __restrict__ status, int64_t tiles,
+                                                        uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[64];
+  if (threadIdx.x < 64) h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < tiles) atomicAdd(&h[length_group(tile_len(ranges, status, t))], 1u);
+  __syncthreads();
+  if (threadIdx.x < 64 && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+}
+
+__global__ void tile_order_scan(uint32_t* __restrict__ hist) {
+  if (threadIdx.x != 0) return;
+  uint32_t run = 0;
+  for (int g = 63; g >= 0; --g) {
+    hist[64 + g] = run;
+    run += hist[g];
+  }
+}
+
+__global__ __launch_bounds__(256) void tile_order_scatter(const uint32_t* __restrict__ ranges,
+                                                          const int32_t* __restrict__ status, int64_t tiles,
+                                                          uint32_t* __restrict__ hist, uint32_t* __restrict__ order) {
+  // ranks within the block per group (LDS), one global reservation per group and block
+  __shared__ uint32_t h[64], base[64];
+  if (threadIdx.x < 64) h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int g = 0;
+  uint32_t rank = 0;
+  if (t < tiles) {
+    g = length_group(tile_len(ranges, status, t));
+    rank = atomicAdd(&h[g], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < 64 && h[threadIdx.x]) base[threadIdx.x] = atomicAdd(&hist[64 + threadIdx.x], h[threadIdx.x]);
+  __syncthreads();
+  if (t < tiles) order[base[g] + rank] = (uint32_t)t;
 }
 
 __global__ void fill_u32(uint32_t* p, int64_t count, uint32_t value) {
@@ -323,13 +466,26 @@ hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t value, hipStream
 static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct SortWs {
-  uint32_t* block_sums;
-  uint32_t* block_offsets;
-  uint64_t* keys_alt;
-  uint32_t* vals_alt;
-  uint32_t* owner;
-  uint32_t* hist;
-  uint32_t* digit_total;
+  uint32_t* block_sums;     // [scan blocks] pairs per block of records
+  uint32_t* vis_sums;       // [scan blocks] visible records per block
+  uint32_t* block_offsets;  // canonical emission offset of each block
+  uint32_t* vis_offsets;    // compaction offset of each block
+  uint32_t* eblock_sums;    // pairs per block of depth-sorted records
+  uint32_t* eblock_offsets;
+  uint32_t* nvis;           // [1] number of visible records
+  uint32_t* dkey;           // [nrec] depth bits of the visible records
+  uint32_t* dval;           // [nrec] their compact indices
+  uint32_t* dkey_alt;
+  uint32_t* dval_alt;
+  uint4* desc;              // [nrec] emission descriptors of the visible records (compact index)
+  uint32_t* drec;           // [nrec] depth bits by record (for the keys)
+  uint32_t* tkey;           // [capacity] tile id of each pair
+  uint32_t* tkey_alt;
+  uint32_t* tval_alt;       // [capacity] canonical pair index (second buffer)
+  uint32_t* trec_alt;       // [capacity] record id (second buffer)
+  uint32_t* hist;           // [256][sort blocks]
+  uint32_t* digit_total;    // [256]
+  uint32_t* tile_hist;      // [128] tile schedule counters
   size_t bytes;
 };
 
@@ -337,58 +493,110 @@ static SortWs carve(const SortPlan& p, uint64_t capacity, void* ws) {
   SortWs w{};
   char* b = (char*)ws;
   size_t o = 0;
-  w.block_sums = (uint32_t*)(b + o), o += align256(sizeof(uint32_t) * (size_t)p.scan_blocks);
-  w.block_offsets = (uint32_t*)(b + o), o += align256(sizeof(uint32_t) * (size_t)p.scan_blocks);
-  w.keys_alt = (uint64_t*)(b + o), o += align256(sizeof(uint64_t) * (size_t)capacity);
-  w.vals_alt = (uint32_t*)(b + o), o += align256(sizeof(uint32_t) * (size_t)capacity);
-  w.owner = (uint32_t*)(b + o), o += align256(sizeof(uint32_t) * (size_t)capacity);
-  w.hist = (uint32_t*)(b + o), o += align256(sizeof(uint32_t) * kRadix * (size_t)p.sort_blocks);
-  w.digit_total = (uint32_t*)(b + o), o += align256(sizeof(uint32_t) * kRadix);
+  auto take = [&](size_t bytes) {
+    uint32_t* q = (uint32_t*)(b + o);
+    o += align256(bytes);
+    return q;
+  };
+  const size_t nb = (size_t)p.scan_blocks, nrec = (size_t)p.nrec;
+  w.block_sums = take(4 * nb);
+  w.vis_sums = take(4 * nb);
+  w.block_offsets = take(4 * nb);
+  w.vis_offsets = take(4 * nb);
+  w.eblock_sums = take(4 * nb);
+  w.eblock_offsets = take(4 * nb);
+  w.nvis = take(8);  // [0] visible records, [1] their pairs (unused)
+  w.dkey = take(4 * nrec);
+  w.dval = take(4 * nrec);
+  w.dkey_alt = take(4 * nrec);
+  w.dval_alt = take(4 * nrec);
+  w.desc = (uint4*)take(16 * nrec);
+  w.drec = take(4 * nrec);
+  w.tkey = take(4 * (size_t)capacity);
+  w.tkey_alt = take(4 * (size_t)capacity);
+  w.tval_alt = take(4 * (size_t)capacity);
+  w.trec_alt = take(4 * (size_t)capacity);
+  w.hist = take(4 * (size_t)kRadix * (size_t)(p.sort_blocks > p.rec_sort_blocks ? p.sort_blocks : p.rec_sort_blocks));
+  w.digit_total = take(4 * (size_t)kRadix);
+  w.tile_hist = take(4 * 128);
   w.bytes = o;
   return w;
 }
 
-size_t bin_sort_ws_bytes(const SortPlan& p) {
-  return carve(p, (uint64_t)p.sort_blocks * kSortTile, nullptr).bytes;
+size_t bin_sort_ws_bytes(const SortPlan& p) { return carve(p, p.capacity, nullptr).bytes; }
+
+// One stable LSD pass per 8 key bits; the result lands back in (k0, v0, u0)
+// when the number of passes is even and in (k1, v1, u1) when it is odd.
+template <typename KT, int NV>
+static void radix_sort(KT* k0, uint32_t* v0, uint32_t* u0, KT* k1, uint32_t* v1, uint32_t* u1, int passes,
+                       const uint32_t* count, const int32_t* status, int64_t nblk, const SortWs& w, hipStream_t s) {
+  KT* kb[2] = {k0, k1};
+  uint32_t* vb[2] = {v0, v1};
+  uint32_t* ub[2] = {u0, u1};
+  int cur = 0;
+  for (int p = 0; p < passes && nblk > 0; ++p) {
+    const int shift = 8 * p;
+    hipLaunchKernelGGL((radix_hist<KT>), dim3((unsigned)nblk), dim3(kSortThreads), 0, s, kb[cur], count, status,
+                       shift, nblk, w.hist);
+    hipLaunchKernelGGL(radix_digit_scan, dim3(kRadix), dim3(256), 0, s, w.hist, nblk, w.digit_total);
+    hipLaunchKernelGGL((radix_scatter<KT, NV>), dim3((unsigned)nblk), dim3(kSortThreads), 0, s, kb[cur], vb[cur],
+                       ub[cur], kb[cur ^ 1], vb[cur ^ 1], ub[cur ^ 1], count, status, shift, nblk, w.hist,
+                       w.digit_total);
+    cur ^= 1;
+  }
 }
 
 hipError_t launch_bin_sort(const SortPlan& plan, const float4* splats, const uint32_t* tiles_touched, int64_t n,
                            const ViewTable& vt, float inv_tw, float inv_th, const BinOut& out, uint64_t capacity,
                            void* ws, hipStream_t s) {
-  const SortWs w = carve(plan, (uint64_t)plan.sort_blocks * kSortTile, ws);
+  const SortWs w = carve(plan, capacity, ws);
   hipError_t e;
   if ((e = launch_fill_u32(out.ranges, 2 * (int64_t)vt.total_tiles, 0u, s)) != hipSuccess) return e;
   const int64_t nb = plan.scan_blocks;
-  if (nb > 0) {
-    hipLaunchKernelGGL(count_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, tiles_touched, plan.nrec,
-                       w.block_sums);
-  }
-  hipLaunchKernelGGL(scan_top, dim3(1), dim3(1024), 0, s, w.block_sums, nb, w.block_offsets, capacity, out.count,
-                     out.status);
-  // ping-pong so that the last pass lands in (keys, pair_index)
-  uint64_t* kbuf[2] = {out.keys, w.keys_alt};
-  uint32_t* vbuf[2] = {out.pair_index, w.vals_alt};
-  int cur = (plan.passes % 2 == 0) ? 0 : 1;
   uint32_t* count = out.count;
   int32_t* status = out.status;
+  if (nb > 0)
+    hipLaunchKernelGGL(count_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, tiles_touched, plan.nrec,
+                       w.block_sums, w.vis_sums);
+  // K and the capacity status, then the number of visible records
+  hipLaunchKernelGGL(scan_top, dim3(1), dim3(1024), 0, s, w.block_sums, nb, w.block_offsets, capacity, count, status);
+  hipLaunchKernelGGL(scan_top, dim3(1), dim3(1024), 0, s, w.vis_sums, nb, w.vis_offsets, (uint64_t)0, w.nvis,
+                     (int32_t*)nullptr);
   if (nb > 0) {
-    hipLaunchKernelGGL(emit_keys, dim3((unsigned)nb), dim3(kScanThreads), 0, s, splats, tiles_touched, plan.nrec, n,
-                       w.block_offsets, status, vt, inv_tw, inv_th, kbuf[cur], vbuf[cur], w.owner, out.offsets);
-  }
-  const int64_t sb = plan.sort_blocks;
-  for (int p = 0; p < plan.passes && sb > 0; ++p) {
-    const int shift = 8 * p;
-    hipLaunchKernelGGL(radix_hist, dim3((unsigned)sb), dim3(kSortThreads), 0, s, kbuf[cur], count, status, shift, sb,
-                       w.hist);
-    hipLaunchKernelGGL(radix_digit_scan, dim3(kRadix), dim3(256), 0, s, w.hist, sb, w.digit_total);
-    hipLaunchKernelGGL(radix_scatter, dim3((unsigned)sb), dim3(kSortThreads), 0, s, kbuf[cur], vbuf[cur],
-                       kbuf[cur ^ 1], vbuf[cur ^ 1], count, status, shift, sb, w.hist, w.digit_total);
-    cur ^= 1;
+    hipLaunchKernelGGL(compact_visible, dim3((unsigned)nb), dim3(kScanThreads), 0, s, splats, tiles_touched,
+                       plan.nrec, n, vt, inv_tw, inv_th, w.block_offsets, w.vis_offsets, status, out.offsets, w.dkey,
+                       w.dval, w.desc, out.keys ? w.drec : (uint32_t*)nullptr);
+    // depth order of the visible records (four passes: the result is back in dkey/dval)
+    radix_sort<uint32_t, 1>(w.dkey, w.dval, nullptr, w.dkey_alt, w.dval_alt, nullptr, 4, w.nvis, status,
+                            plan.rec_sort_blocks, w, s);
+    hipLaunchKernelGGL(gather_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, w.desc, w.dval, w.nvis, status,
+                       w.eblock_sums);
+    hipLaunchKernelGGL(scan_top, dim3(1), dim3(1024), 0, s, w.eblock_sums, nb, w.eblock_offsets, (uint64_t)0,
+                       w.nvis + 1, (int32_t*)nullptr);  // total unused (equals K)
+    // emit so that the tile sort ends in (tkey, pair_index, ids)
+    const bool even = plan.tile_passes % 2 == 0;
+    hipLaunchKernelGGL(emit_pairs, dim3((unsigned)nb), dim3(kScanThreads), 0, s, w.desc, w.dval, w.nvis, n,
+                       w.eblock_offsets, status, vt, even ? w.tkey : w.tkey_alt, even ? out.pair_index : w.tval_alt,
+                       even ? out.ids : w.trec_alt);
+    if (even)
+      radix_sort<uint32_t, 2>(w.tkey, out.pair_index, out.ids, w.tkey_alt, w.tval_alt, w.trec_alt, plan.tile_passes,
+                              count, status, plan.sort_blocks, w, s);
+    else
+      radix_sort<uint32_t, 2>(w.tkey_alt, w.tval_alt, w.trec_alt, w.tkey, out.pair_index, out.ids, plan.tile_passes,
+                              count, status, plan.sort_blocks, w, s);
   }
   const int64_t cap_blocks = ((int64_t)capacity + 255) / 256;
-  if (cap_blocks > 0)
-    hipLaunchKernelGGL(tile_ranges, dim3((unsigned)cap_blocks), dim3(256), 0, s, out.keys, out.pair_index, w.owner,
-                       count, status, out.ids, out.ranges);
+  if (cap_blocks > 0 && nb > 0)
+    hipLaunchKernelGGL(tile_ranges, dim3((unsigned)cap_blocks), dim3(256), 0, s, w.tkey, out.ids, w.drec, count,
+                       status, out.keys, out.ranges);
+  if (out.order && vt.total_tiles > 0) {
+    const int64_t T = vt.total_tiles;
+    const unsigned tb = (unsigned)((T + 255) / 256);
+    if ((e = launch_fill_u32(w.tile_hist, 128, 0u, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(tile_order_count, dim3(tb), dim3(256), 0, s, out.ranges, status, T, w.tile_hist);
+    hipLaunchKernelGGL(tile_order_scan, dim3(1), dim3(64), 0, s, w.tile_hist);
+    hipLaunchKernelGGL(tile_order_scatter, dim3(tb), dim3(256), 0, s, out.ranges, status, T, w.tile_hist, out.order);
+  }
   return hipGetLastError();
 }
 

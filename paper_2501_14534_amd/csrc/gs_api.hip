@@ -52,8 +52,9 @@ bool opts_ok(const gs_opts* o) {
   if (px / o->pixels_per_thread > 256) return false;  // render kernels run <= 256 threads per tile
   if (o->batch_depth < 1 || o->batch_depth > GS_MAX_BATCH) return false;
   if (o->subtile_cull != 0 && o->subtile_cull != 1) return false;
+  if (o->bwd_chunk != 0 && (!pow2(o->bwd_chunk) || o->bwd_chunk < 16 || o->bwd_chunk > (1 << 20))) return false;
   if (!std::isfinite(o->lowpass) || o->lowpass < 0.0f) return false;
-  if (!std::isfinite(o->near_plane)) return false;
+  if (!std::isfinite(o->near_plane) || !(o->near_plane > 0.0f)) return false;  // depths > 0 order as bits
   if (!(o->tan_clamp > 0.0f)) return false;
   for (int c = 0; c < 3; ++c)
     if (!std::isfinite(o->bg[c])) return false;
@@ -82,6 +83,7 @@ bool view_table(const gs_camera* cams, int32_t V, const gs_opts* o, ViewTable* v
     a.W = c.width, a.H = c.height;
     a.TX = (c.width + o->tile_w - 1) / o->tile_w;
     a.TY = (c.height + o->tile_h - 1) / o->tile_h;
+    if (a.TX > 65535 || a.TY > 65535) return false;  // tile rectangles are packed as 16-bit sizes
     a.tile_off = (int32_t)to;
     a.pix_off = (int32_t)po;
     to += (int64_t)a.TX * a.TY;
@@ -115,14 +117,29 @@ bool gaussians_ok(const gs_gaussians* g, ProjectArgs* a) {
 SortPlan sort_plan(int64_t n, int32_t V, int32_t total_tiles, uint64_t capacity) {
   SortPlan p;
   p.nrec = (int64_t)V * n;
+  p.capacity = capacity;
   p.scan_blocks = (p.nrec + 1023) / 1024;
+  p.rec_sort_blocks = (p.nrec + 4095) / 4096;
   p.sort_blocks = (int64_t)((capacity + 4095) / 4096);
-  p.bits = 32 + (total_tiles > 1 ? ilog2(total_tiles) : 0);
-  p.passes = (p.bits + 7) / 8;
+  p.tile_passes = ((total_tiles > 1 ? ilog2(total_tiles) : 0) + 7) / 8;
   return p;
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Chunk length of the backward work items (2^31: one item per tile).
+int log2_chunk(const gs_opts* o) { return o->bwd_chunk ? ilog2(o->bwd_chunk) : 31; }
+int64_t chunk_slots(uint64_t capacity, const gs_opts* o) { return (int64_t)(capacity >> log2_chunk(o)) + 1; }
+
+// Per-chunk pixel states, after the backward's own regions in the workspace:
+// slot owners [slots] u32, then states [slots][tile pixels] float4.
+size_t state_owner_bytes(uint64_t capacity, const gs_opts* o) {
+  return align256(sizeof(uint32_t) * (size_t)chunk_slots(capacity, o));
+}
+size_t render_state_bytes(uint64_t capacity, const gs_opts* o) {
+  return state_owner_bytes(capacity, o) +
+         align256(16 * (size_t)chunk_slots(capacity, o) * (size_t)(o->tile_w * o->tile_h));
+}
 
 RenderArgs render_args(const gs_projected* p, const gs_binning* b, const gs_opts* o) {
   RenderArgs a;
@@ -130,6 +147,7 @@ RenderArgs render_args(const gs_projected* p, const gs_binning* b, const gs_opts
   a.ids = b->ids;
   a.pair_index = b->pair_index;
   a.ranges = b->ranges;
+  a.order = b->order;
   a.status = b->status;
   a.log2_tw = ilog2(o->tile_w);
   a.log2_th = ilog2(o->tile_h);
@@ -151,6 +169,10 @@ RenderArgs render_args(const gs_projected* p, const gs_binning* b, const gs_opts
   a.ppt = o->pixels_per_thread;
   a.cull = o->subtile_cull;
   for (int c = 0; c < 3; ++c) a.bg[c] = o->bg[c];
+  a.log2_chunk = log2_chunk(o);
+  a.nslots = chunk_slots(b->capacity, o);
+  a.slot_owner = nullptr;
+  a.state = nullptr;
   return a;
 }
 
@@ -158,7 +180,7 @@ int launched(hipError_t e) { return e == hipSuccess ? GS_OK : GS_E_HIP; }
 
 bool binning_ok(const gs_binning* b, int64_t nrec) {
   if (!b || !b->ranges || !b->count || !b->status || b->capacity >= (1ull << 32)) return false;
-  if (b->capacity > 0 && (!b->keys || !b->ids || !b->pair_index)) return false;
+  if (b->capacity > 0 && (!b->ids || !b->pair_index)) return false;
   if (nrec > 0 && !b->offsets) return false;
   return true;
 }
@@ -170,6 +192,17 @@ size_t rec_geo_bytes(int64_t nrec) { return align256(sizeof(double) * 6 * (size_
 size_t rec_mu_bytes(int64_t nrec) { return align256(sizeof(float) * 4 * (size_t)nrec); }
 size_t bwd_ws_bytes(uint64_t capacity, int64_t nrec) {
   return grad_pair_bytes(capacity) + rec_geo_bytes(nrec) + rec_mu_bytes(nrec);
+}
+
+// Bytes the forward and backward need: the backward's regions, then the chunk states.
+size_t render_ws_bytes(uint64_t capacity, int64_t nrec, const gs_opts* o) {
+  return bwd_ws_bytes(capacity, nrec) + render_state_bytes(capacity, o);
+}
+
+void attach_state(RenderArgs* a, uint64_t capacity, int64_t nrec, const gs_opts* o, const void* ws) {
+  char* base = (char*)ws + bwd_ws_bytes(capacity, nrec);
+  a->slot_owner = (uint32_t*)base;
+  a->state = (float4*)(base + state_owner_bytes(capacity, o));
 }
 
 ProjectBwdArgs project_bwd_args(ProjectArgs pa, const gs_opts* opts, const gs_projected* proj, const gs_binning* bins,
@@ -228,8 +261,8 @@ size_t gs_workspace_size(int64_t n, int32_t V, const gs_camera* cams, const gs_o
   if (n < 0 || capacity >= (1ull << 32) || !view_table(cams, V, opts, &vt, nullptr)) return 0;
   const SortPlan p = sort_plan(n, V, vt.total_tiles, capacity);
   const size_t sort_bytes = bin_sort_ws_bytes(p);
-  const size_t bwd_bytes = bwd_ws_bytes(capacity, (int64_t)V * n);
-  return sort_bytes > bwd_bytes ? sort_bytes : bwd_bytes;
+  const size_t render_bytes = render_ws_bytes(capacity, (int64_t)V * n, opts);
+  return sort_bytes > render_bytes ? sort_bytes : render_bytes;
 }
 
 int gs_project(const gs_gaussians* g, const gs_camera* cams, int32_t V, const gs_opts* opts, gs_projected* out,
@@ -267,6 +300,7 @@ int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int32_t V, int6
   bo.pair_index = out->pair_index;
   bo.offsets = out->offsets;
   bo.ranges = out->ranges;
+  bo.order = out->order;
   bo.count = out->count;
   bo.status = out->status;
   return launched(launch_bin_sort(p, (const float4*)proj->splats, proj->tiles_touched, n, vt,
@@ -275,14 +309,17 @@ int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int32_t V, int6
 }
 
 int gs_render_fwd(const gs_projected* proj, const gs_binning* bins, const gs_camera* cams, int32_t V, int64_t n,
-                  const gs_opts* opts, float* image, float* T_final, int32_t* last_contrib, gs_stream_t stream) {
+                  const gs_opts* opts, float* image, float* T_final, int32_t* last_contrib, void* ws,
+                  size_t ws_bytes, gs_stream_t stream) {
   ViewTable vt;
   if (!proj || n < 0 || !view_table(cams, V, opts, &vt, nullptr)) return GS_E_INVALID;
   if (!image || !T_final || !last_contrib || !binning_ok(bins, (int64_t)V * n)) return GS_E_INVALID;
   if (n > 0 && !proj->splats) return GS_E_INVALID;
+  if (!ws || ws_bytes < render_ws_bytes(bins->capacity, (int64_t)V * n, opts)) return GS_E_INVALID;
   const int d = device_ok();
   if (d != GS_OK) return d;
-  const RenderArgs a = render_args(proj, bins, opts);
+  RenderArgs a = render_args(proj, bins, opts);
+  attach_state(&a, bins->capacity, (int64_t)V * n, opts, ws);
   return launched(launch_render_fwd(a, vt, image, T_final, last_contrib, (hipStream_t)stream));
 }
 
@@ -297,13 +334,13 @@ int gs_render_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t V, const
   if (!binning_ok(bins, (int64_t)V * g->n)) return GS_E_INVALID;
   if (g->n > 0 && (!proj->splats || !proj->tiles_touched)) return GS_E_INVALID;
   const int64_t nrec = (int64_t)V * g->n;
-  const size_t need = bwd_ws_bytes(bins->capacity, nrec);
-  if (ws_bytes < need || (!ws && need > 0)) return GS_E_INVALID;
+  if (!ws || ws_bytes < render_ws_bytes(bins->capacity, nrec, opts)) return GS_E_INVALID;
   const int d = device_ok();
   if (d != GS_OK) return d;
   hipStream_t s = (hipStream_t)stream;
   float* grad_pair = (float*)ws;
-  const RenderArgs ra = render_args(proj, bins, opts);
+  RenderArgs ra = render_args(proj, bins, opts);
+  attach_state(&ra, bins->capacity, nrec, opts, ws);
   hipError_t e = launch_render_bwd(ra, vt, T_final, last_contrib, dL_dimage, grad_pair, s);
   if (e != hipSuccess) return GS_E_HIP;
   return launched(launch_project_bwd(project_bwd_args(pa, opts, proj, bins, grad_pair, grads, g->sh_degree, ws, nrec),
@@ -312,14 +349,16 @@ int gs_render_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t V, const
 
 int gs_blend_bwd(const gs_camera* cams, int32_t V, int64_t n, const gs_opts* opts, const gs_projected* proj,
                  const gs_binning* bins, const float* T_final, const int32_t* last_contrib, const float* dL_dimage,
-                 float* grad_pair, gs_stream_t stream) {
+                 float* grad_pair, const void* ws, size_t ws_bytes, gs_stream_t stream) {
   ViewTable vt;
   if (n < 0 || !view_table(cams, V, opts, &vt, nullptr)) return GS_E_INVALID;
   if (!proj || !T_final || !last_contrib || !dL_dimage || !binning_ok(bins, (int64_t)V * n)) return GS_E_INVALID;
   if (n > 0 && (!proj->splats || !grad_pair)) return GS_E_INVALID;
+  if (!ws || ws_bytes < render_ws_bytes(bins->capacity, (int64_t)V * n, opts)) return GS_E_INVALID;
   const int d = device_ok();
   if (d != GS_OK) return d;
-  const RenderArgs ra = render_args(proj, bins, opts);
+  RenderArgs ra = render_args(proj, bins, opts);
+  attach_state(&ra, bins->capacity, (int64_t)V * n, opts, ws);
   return launched(launch_render_bwd(ra, vt, T_final, last_contrib, dL_dimage, grad_pair, (hipStream_t)stream));
 }
 

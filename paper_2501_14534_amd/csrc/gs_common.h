@@ -73,6 +73,24 @@ struct Eval {
   float dx, dy, G, raw, alpha;
 };
 
+// eval_splat_all computes the same values without branching and returns the
+// square test's outcome; eval_splat skips the falloff outside the square.
+__device__ __forceinline__ bool eval_splat_all(float px, float py, float u, float v, float A, float B, float C,
+                                               float o, float rad, Eval* e) {
+#pragma clang fp contract(off)
+  const float dx = px - u;
+  const float dy = py - v;
+  const float q = A * dx * dx + 2.0f * B * dx * dy + C * dy * dy;
+  const float G = __builtin_amdgcn_exp2f(q * (-0.5f * kLog2e));
+  const float raw = o * G;
+  e->dx = dx;
+  e->dy = dy;
+  e->G = G;
+  e->raw = raw;
+  e->alpha = fminf(kAlphaMax, raw);
+  return fabsf(dx) <= rad && fabsf(dy) <= rad;
+}
+
 __device__ __forceinline__ bool eval_splat(float px, float py, float u, float v, float A, float B, float C, float o,
                                            float rad, Eval* e) {
 #pragma clang fp contract(off)
@@ -117,6 +135,10 @@ constexpr float kC3d = 0.37317633259011540f;  // 1/4 sqrt(7/pi)
 constexpr float kC3e = 1.44530572132027737f;  // 1/4 sqrt(105/pi)
 
 // Basis functions k = 1..15 (band 0 is the diffuse colour) at unit (x, y, z).
+// Coefficients of SH degree 3 and the band of coefficient k (band l holds k in [l^2, (l+1)^2)).
+constexpr int kShCoeffs = 16;
+__host__ __device__ constexpr int sh_band(int k) { return k < 1 ? 0 : k < 4 ? 1 : k < 9 ? 2 : 3; }
+
 __device__ __forceinline__ void sh_basis15(float x, float y, float z, float Y[15]) {
   const float xx = x * x, yy = y * y, zz = z * z;
   Y[0] = -kC1 * y;

@@ -32,6 +32,7 @@ struct RenderArgs {
   const uint32_t* ids;
   const uint32_t* pair_index;
   const uint32_t* ranges;
+  const uint32_t* order;  // tile schedule (NULL: tile-id order)
   const int32_t* status;
   int32_t log2_tw, log2_th;
   int32_t log2_sw, log2_sh;  // sub-tile (one per wave) width and height
@@ -40,6 +41,14 @@ struct RenderArgs {
   int32_t ppt;
   int32_t cull;
   float bg[3];
+  // per-chunk pixel states written by the forward, read by the backward:
+  // boundary position q = start + k * 2^log2_chunk (k >= 1) of a tile's list
+  // owns slot q >> log2_chunk; slot_owner[slot] = global tile, state[slot][pixel]
+  // = (T, colour composited after q)
+  int32_t log2_chunk;
+  int64_t nslots;
+  uint32_t* slot_owner;
+  float4* state;
 };
 
 struct BinOut {
@@ -48,6 +57,7 @@ struct BinOut {
   uint32_t* pair_index;
   uint32_t* offsets;
   uint32_t* ranges;
+  uint32_t* order;
   uint32_t* count;
   int32_t* status;
 };
@@ -73,11 +83,12 @@ struct ProjectBwdArgs {
 
 // Workspace carve-up of gs_bin_sort / gs_render_bwd.
 struct SortPlan {
-  int64_t nrec;         // V * n
-  int64_t scan_blocks;  // records / 1024
-  int64_t sort_blocks;  // capacity / 4096
-  int passes;
-  int bits;
+  int64_t nrec;             // V * n
+  uint64_t capacity;        // pair capacity
+  int64_t scan_blocks;      // records / 1024
+  int64_t rec_sort_blocks;  // records / 4096 (depth sort of the visible records)
+  int64_t sort_blocks;      // capacity / 4096 (tile sort of the pairs)
+  int tile_passes;          // 8-bit passes over ceil(log2 #tiles) tile bits
 };
 
 hipError_t launch_project(const ProjectArgs& a, const ViewTable& vt, int deg, hipStream_t s);

@@ -54,19 +54,20 @@ __global__ __launch_bounds__(256) void project_kernel(ProjectArgs a, ViewTable v
         band_on[l] = m > a.sh_mask_thr;
       }
     }
+    // flat loops with constant trip counts, so the coefficients stay in registers
 #pragma unroll
-    for (int l = 1; l <= DEG; ++l) {
+    for (int k = 1; k < kShCoeffs; ++k) {
+      const int l = sh_band(k);
+      if (l > DEG) continue;
 #pragma unroll
-      for (int k = l * l; k < (l + 1) * (l + 1); ++k)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          float x = 0.f;
-          if (band_on[l]) {
-            x = a.sh_rest[((k - 1) * 3 + c) * n + i];
-            ok = ok && finitef(x);
-          }
-          rest[k - 1][c] = x;
+      for (int c = 0; c < 3; ++c) {
+        float x = 0.f;
+        if (band_on[l]) {
+          x = a.sh_rest[((k - 1) * 3 + c) * n + i];
+          ok = ok && finitef(x);
         }
+        rest[k - 1][c] = x;
+      }
     }
   }
 
@@ -141,12 +142,11 @@ __global__ __launch_bounds__(256) void project_kernel(ProjectArgs a, ViewTable v
           float Y[15];
           sh_basis15(d0, d1, d2, Y);
 #pragma unroll
-          for (int l = 1; l <= DEG; ++l) {
-            if (!band_on[l]) continue;
+          for (int k = 1; k < kShCoeffs; ++k) {
+            const int l = sh_band(k);
+            if (l > DEG || !band_on[l]) continue;
 #pragma unroll
-            for (int k = l * l; k < (l + 1) * (l + 1); ++k)
-#pragma unroll
-              for (int ch = 0; ch < 3; ++ch) rgb[ch] += Y[k - 1] * rest[k - 1][ch];
+            for (int ch = 0; ch < 3; ++ch) rgb[ch] += Y[k - 1] * rest[k - 1][ch];
           }
         }
         o0 = make_float4(u, vv, cc * idet, -cb * idet);

@@ -157,13 +157,13 @@ __global__ __launch_bounds__(256) void project_bwd_color_kernel(ProjectBwdArgs b
       il = 1.0f / sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
       dx = d0 * il, dy = d1 * il, dz = d2 * il;
       sh_basis15(dx, dy, dz, Y);
+      // flat loops with constant trip counts keep rest/Y/trest in registers
 #pragma unroll
-      for (int l = 1; l <= DEG; ++l) {
-        if (!band_on[l]) continue;
+      for (int k = 1; k < kShCoeffs; ++k) {
+        const int l = sh_band(k);
+        if (l > DEG || !band_on[l]) continue;
 #pragma unroll
-        for (int k = l * l; k < (l + 1) * (l + 1); ++k)
-#pragma unroll
-          for (int ch = 0; ch < 3; ++ch) pre[ch] += Y[k - 1] * rest[k - 1][ch];
+        for (int ch = 0; ch < 3; ++ch) pre[ch] += Y[k - 1] * rest[k - 1][ch];
       }
     }
     float gpre[3];
@@ -177,21 +177,23 @@ __global__ __launch_bounds__(256) void project_bwd_color_kernel(ProjectBwdArgs b
       float wY[15];
 #pragma unroll
       for (int k = 0; k < 15; ++k) wY[k] = 0.f;
+      float band[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+      for (int k = 1; k < kShCoeffs; ++k) {
+        const int l = sh_band(k);
+        if (l > DEG) continue;
+        const float cg = rest[k - 1][0] * gpre[0] + rest[k - 1][1] * gpre[1] + rest[k - 1][2] * gpre[2];
+        band[l - 1] += Y[k - 1] * cg;
+        if (band_on[l]) {
+          wY[k - 1] = cg;
+#pragma unroll
+          for (int ch = 0; ch < 3; ++ch) trest[k - 1][ch] = acc_mul_add(trest[k - 1][ch], Y[k - 1], gpre[ch]);
+        }
+      }
 #pragma unroll
       for (int l = 1; l <= DEG; ++l) {
-        float band = 0.f;
-#pragma unroll
-        for (int k = l * l; k < (l + 1) * (l + 1); ++k) {
-          const float cg = rest[k - 1][0] * gpre[0] + rest[k - 1][1] * gpre[1] + rest[k - 1][2] * gpre[2];
-          band += Y[k - 1] * cg;
-          if (band_on[l]) {
-            wY[k - 1] = cg;
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) trest[k - 1][ch] = acc_mul_add(trest[k - 1][ch], Y[k - 1], gpre[ch]);
-          }
-        }
         const float sb = sigmoidf(bm[l - 1]);
-        tbm[l - 1] = acc_mul_add(tbm[l - 1], band, sb * (1.f - sb));
+        tbm[l - 1] = acc_mul_add(tbm[l - 1], band[l - 1], sb * (1.f - sb));
       }
       float gdx, gdy, gdz;
       sh_grad15(dx, dy, dz, wY, &gdx, &gdy, &gdz);

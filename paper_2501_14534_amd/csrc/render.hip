@@ -1,29 +1,33 @@
 // Per-tile front-to-back compositing (Eq. 2) and its backward.
 //
-// One workgroup per tile (global tile ids span all views of the call).  The
-// tile's sorted list is walked in batches of up to 256 splat records that the
-// workgroup gathers into LDS; every lane then walks the batch for its
-// pixel(s), reading each record as a wave-uniform LDS broadcast.  No MFMA:
-// the work per (pixel, splat) pair is ~20 VALU operations and one exp.
+// One workgroup per tile (global tile ids span all views of the call),
+// launched in the heaviest-first order gs_bin_sort writes when the caller
+// asks for it.  The tile's sorted list is walked in batches of up to 256
+// splat records that the workgroup gathers into LDS; every lane then walks
+// the batch for its pixel(s), reading each record as a wave-uniform LDS
+// broadcast, the next record loaded while the current one is blended.  No
+// MFMA: the work per (pixel, splat) pair is ~20 VALU operations and one exp.
 //
 // Sub-tile culling (CULL): while staging a batch, each record's conservative
 // alpha >= 1/255 footprint (the ellipse q <= 2 ln(255 o') bounded by its
 // square, widened by rounding margins) is tested against the pixel box of
-// every wave; wave 0 then builds one ordered list of batch indices per wave,
-// and each wave walks only its own list.  Culled records fail a per-pixel
-// test for every pixel of that wave, so the result is unchanged.
+// every wave; each wave then walks only the records whose bit it holds, taken
+// from a ballot in scalar registers.  Culled records fail a per-pixel test
+// for every pixel of that wave, so the result is unchanged.
 //
 // Forward: lanes whose pixels have terminated drop out of the walk through
-// the exec mask; before each batch the waves vote and the whole workgroup
-// leaves once every pixel is done.
+// the exec mask; a wave stops walking once all its pixels are done, and
+// before each batch the waves vote and the workgroup leaves once every pixel
+// is done.
 //
 // Backward: the list is re-walked back to front from the tile's largest
 // last_contrib; each pixel recovers the transmittance in front of a splat by
 // dividing by (1 - alpha) and carries the dL/dC-weighted colour behind it, so
 // no per-pixel list is stored.  Per-pair partials (9 floats) are summed over
-// the lane's pixels, over the wave (DPP), then over the workgroup's waves in a
-// fixed order (LDS), and stored once per (tile, splat) at the pair's emission
-// position: no atomics, so the result is bitwise reproducible.
+// the lane's pixels, over the wave (a butterfly reduce-scatter over cross-lane
+// swaps: about 30 instructions for all 9 sums), then over the workgroup's
+// waves in a fixed order (LDS), and stored once per (tile, splat) at the
+// pair's emission position: no atomics, so the result is bitwise reproducible.
 #include "gs_common.h"
 #include "kernels.h"
 
@@ -106,49 +110,31 @@ __device__ __forceinline__ uint32_t footprint_mask(const RenderArgs& a, float4 r
   return m;
 }
 
-// Wave 0 turns the per-record wave masks of a batch into one ordered index
-// list per wave (lane l handles batch entries 4l .. 4l+3).
-__device__ __forceinline__ void build_wave_lists(const uint8_t* s_mask, int cnt, int nwaves, int stride,
-                                                 uint8_t* s_list, int* s_len) {
-  const int l = threadIdx.x;  // called by wave 0 only
-  uint32_t m[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int i = 4 * l + q;
-    m[q] = i < cnt ? s_mask[i] : 0u;
-  }
-  for (int w = 0; w < nwaves; ++w) {
-    uint32_t c = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) c += (m[q] >> w) & 1u;
-    uint32_t incl = c;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-      const uint32_t t = __shfl_up(incl, o, kWave);
-      if (l >= o) incl += t;
-    }
-    uint32_t pos = incl - c;
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if ((m[q] >> w) & 1u) s_list[w * stride + pos++] = (uint8_t)(4 * l + q);
-    if (l == kWave - 1) s_len[w] = (int)incl;
-  }
+// Entry selection.  Once a batch is staged, lane l of wave w reads the
+// footprint mask of entry 64c + l; the ballot is the set of entries of chunk c
+// that wave w walks.  The walk takes the set bits in order from scalar
+// registers, so no per-wave index list is built, stored or read.
+template <bool CULL>
+__device__ __forceinline__ uint64_t chunk_bits(const uint8_t* s_mask, int c, int cnt, int wave, int lane) {
+  const int i = c * kWave + lane;
+  bool bit = i < cnt;
+  if (CULL && bit) bit = ((s_mask[i] >> wave) & 1u) != 0u;
+  return __ballot(bit);
 }
 
 // Dynamic LDS of the blend kernels, sized by the batch depth B and the wave count W:
-//   records 3 x B float4 | [bwd] B pair indices | [bwd] W x B x 9 partial sums | B masks | 4 x B lists
+//   records 3 x B float4 | [bwd] B pair indices | [bwd] W x B x 9 partial sums | B masks
 struct Lds {
   float4 *a, *b, *c;
   uint32_t* e;
   float* part;
   uint8_t* mask;
-  uint8_t* list;  // [4][B]
 };
 
 __host__ __device__ inline size_t lds_bytes(int batch, int nwaves, bool bwd) {
   size_t o = 3 * 16 * (size_t)batch;
   if (bwd) o += 4 * (size_t)batch + 4 * (size_t)GS_GRAD_FLOATS * nwaves * batch;
-  o += (size_t)batch + 4 * (size_t)batch;
+  o += (size_t)batch;
   return (o + 15) & ~(size_t)15;
 }
 
@@ -164,8 +150,7 @@ __device__ inline Lds lds_carve(unsigned char* base, int batch, int nwaves, bool
     l.e = (uint32_t*)(base + o), o += 4 * (size_t)batch;
     l.part = (float*)(base + o), o += 4 * (size_t)GS_GRAD_FLOATS * nwaves * batch;
   }
-  l.mask = base + o, o += batch;
-  l.list = base + o;
+  l.mask = base + o;
   return l;
 }
 
@@ -175,13 +160,78 @@ __host__ __device__ inline int bwd_batch(int batch, int nwaves) {
   return batch < cap ? batch : cap;
 }
 
+__device__ __forceinline__ int tile_of_block(const RenderArgs& a) {
+  return a.order ? (int)a.order[blockIdx.x] : (int)blockIdx.x;
+}
+
+// Cross-lane moves of the backward's reduce-scatter.  permlane32_swap
+// exchanges the upper 32 lanes of its first operand with the lower 32 lanes
+// of its second, permlane16_swap the odd 16-lane rows of the first with the
+// even rows of the second (both new on gfx950).  The pair result is read
+// through a 64-bit cast.
+__device__ __forceinline__ void swap_halves(float& a, float& b) {
+  const uint64_t r = __builtin_bit_cast(
+      uint64_t, __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(uint32_t, a), __builtin_bit_cast(uint32_t, b),
+                                                 false, false));
+  a = __builtin_bit_cast(float, (uint32_t)r);
+  b = __builtin_bit_cast(float, (uint32_t)(r >> 32));
+}
+
+__device__ __forceinline__ void swap_rows(float& a, float& b) {
+  const uint64_t r = __builtin_bit_cast(
+      uint64_t, __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(uint32_t, a), __builtin_bit_cast(uint32_t, b),
+                                                 false, false));
+  a = __builtin_bit_cast(float, (uint32_t)r);
+  b = __builtin_bit_cast(float, (uint32_t)(r >> 32));
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+}
+
+// Sums each of the 9 per-lane values over the 64 lanes of the wave
+// (butterfly reduce-scatter: every step halves the values a lane carries).
+// Element e ends in the four lanes l with (l >> 2) bits giving
+// k2 = 2 b3 + b2 <= 2, k1 = k2 + 3 b4 <= 4, e = k1 + 5 b5 <= 8; the tree is
+// fixed, so the sum is reproducible.  Needs every lane of the wave active.
+__device__ __forceinline__ float reduce_scatter9(const float (&x)[GS_GRAD_FLOATS], bool b2, bool b3) {
+  float y[5];  // lane bit 5: elements 0-4 stay in lanes 0-31, 5-8 go to lanes 32-63
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    float lo = x[k], hi = k + 5 < GS_GRAD_FLOATS ? x[k + 5] : 0.0f;
+    swap_halves(lo, hi);
+    y[k] = lo + hi;
+  }
+  float z[3];  // lane bit 4: y0-y2 stay in even rows, y3-y4 go to odd rows
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    float lo = y[k], hi = k + 3 < 5 ? y[k + 3] : 0.0f;
+    swap_rows(lo, hi);
+    z[k] = lo + hi;
+  }
+  // lane bit 3: row_mirror pairs lane i of a row with lane 15 - i
+  const float t0 = z[0] + dpp_f<0x140>(z[0]);
+  const float t1 = z[1] + dpp_f<0x140>(z[1]);
+  const float t2 = z[2] + dpp_f<0x140>(z[2]);
+  const float w0 = b3 ? t2 : t0;
+  const float w1 = b3 ? 0.0f : t1;
+  // lane bit 2: row_half_mirror pairs lane i of an 8-lane half row with lane 7 - i
+  const float u0 = w0 + dpp_f<0x141>(w0);
+  const float u1 = w1 + dpp_f<0x141>(w1);
+  float v = b2 ? u1 : u0;
+  // lane bits 1 and 0: quad permutations [2,3,0,1] and [1,0,3,2]
+  v += dpp_f<0x4E>(v);
+  v += dpp_f<0xB1>(v);
+  return v;
+}
+
 template <int PPT, bool CULL>
 __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable vt, float* __restrict__ image,
                                                          float* __restrict__ T_final, int32_t* __restrict__ last_out) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ int s_len[4];
-  __shared__ int s_alive[16];
-  const int gtile = blockIdx.x;
+  __shared__ int s_alive[4];
+  const int gtile = tile_of_block(a);
   const TileCtx tc = tile_ctx(vt, a, gtile);
   const ViewArgs& va = vt.v[tc.view];
   const int nthreads = blockDim.x;
@@ -191,9 +241,11 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable
   float4* s_b = L.b;
   float4* s_c = L.c;
   uint8_t* s_mask = L.mask;
-  uint8_t* s_list = L.list;
 
-  float px[PPT], py[PPT], T[PPT], C0[PPT], C1[PPT], C2[PPT];
+  // C: colour composited so far (the image); S: colour composited since the
+  // last chunk boundary (kept apart so that the colour after a boundary is a
+  // sum of non-negative segments, accurate relative to itself)
+  float px[PPT], py[PPT], T[PPT], C0[PPT], C1[PPT], C2[PPT], S0[PPT], S1[PPT], S2[PPT];
   int last[PPT];
   bool done[PPT];
 #pragma unroll
@@ -204,21 +256,42 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable
     py[p] = (float)y + 0.5f;
     T[p] = 1.0f;
     C0[p] = C1[p] = C2[p] = 0.0f;
+    S0[p] = S1[p] = S2[p] = 0.0f;
     last[p] = 0;
     done[p] = !(x < va.W && y < va.H);
   }
 
-  for (uint32_t bs = tc.start; bs < tc.end; bs += a.batch) {
+  const int tpx = 1 << (a.log2_tw + a.log2_th);
+  const int lc = a.log2_chunk;
+  int nbnd = 0;  // chunk boundaries recorded (uniform)
+  for (uint32_t bs = tc.start; bs < tc.end;) {
     bool alive = false;
 #pragma unroll
     for (int p = 0; p < PPT; ++p) alive |= !done[p];
     const uint64_t vote = __ballot(alive);
     if (lane == 0) s_alive[wave] = vote != 0;
-    __syncthreads();
+    __syncthreads();  // also: every wave has finished walking the previous batch
     int any = 0;
     for (int w = 0; w < nwaves; ++w) any |= s_alive[w];
     if (!any) break;
-    const int cnt = (int)min((uint32_t)a.batch, tc.end - bs);
+    const uint64_t rel = bs - tc.start;
+    if (rel != 0 && (rel & ((1ull << lc) - 1)) == 0) {
+      // a chunk boundary of the backward: record each pixel's transmittance
+      // here and the colour of the chunk that ends here, then start a new chunk
+      const int64_t slot = (int64_t)(bs >> lc);
+      float4* st = a.state + slot * tpx;
+#pragma unroll
+      for (int p = 0; p < PPT; ++p) {
+        st[threadIdx.x * PPT + p] = make_float4(T[p], S0[p], S1[p], S2[p]);
+        S0[p] = S1[p] = S2[p] = 0.0f;
+      }
+      if (threadIdx.x == 0) a.slot_owner[slot] = (uint32_t)gtile;
+      ++nbnd;
+    }
+    // batches never straddle a chunk boundary
+    const uint64_t next = (uint64_t)tc.start + (((rel >> lc) + 1) << lc);
+    const uint32_t be = (uint32_t)min(min((uint64_t)tc.end, (uint64_t)bs + (uint64_t)a.batch), next);
+    const int cnt = (int)(be - bs);
     for (int i = threadIdx.x; i < cnt; i += nthreads) {
       const uint32_t rec = a.ids[bs + i];
       const float4 ra = a.splats[(size_t)rec * 3 + 0];
@@ -229,34 +302,76 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable
       if (CULL) s_mask[i] = (uint8_t)footprint_mask(a, ra, rb, nwaves, tc.tx, tc.ty);
     }
     __syncthreads();
-    int len = cnt;
-    if (CULL) {
-      if (wave == 0) build_wave_lists(s_mask, cnt, nwaves, a.batch, s_list, s_len);
-      __syncthreads();
-      len = s_len[wave];
-    }
-    for (int jj = 0; jj < len; ++jj) {
-      const int j = CULL ? (int)s_list[wave * a.batch + jj] : jj;
-      const float4 ra = s_a[j], rb = s_b[j];
+    const int nchunks = (cnt + kWave - 1) / kWave;
+    for (int c = 0; c < nchunks; ++c) {
+      bool live = false;
 #pragma unroll
-      for (int p = 0; p < PPT; ++p) {
-        if (done[p]) continue;
-        Eval e;
-        if (!eval_splat(px[p], py[p], ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, &e)) continue;
-        if (e.alpha < kAlphaMin) continue;
-        const float Tn = T[p] * (1.0f - e.alpha);
-        if (Tn < kTMin) {
-          done[p] = true;
-          continue;
+      for (int p = 0; p < PPT; ++p) live |= !done[p];
+      if (__ballot(live) == 0) break;  // every pixel of this wave has stopped
+      uint64_t m = chunk_bits<CULL>(s_mask, c, cnt, wave, lane);
+      if (m == 0) continue;
+      // blend one staged record into this lane's pixel(s); branch-free: a lane
+      // that skips the splat adds exact zeros
+      auto blend = [&](int j, const float4& ra, const float4& rb, const float4& rc) {
+        const int idx = (int)(bs + j - tc.start) + 1;
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+          Eval e;
+          const bool inside = eval_splat_all(px[p], py[p], ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, &e);
+          const bool use = !done[p] && inside && !(e.alpha < kAlphaMin);
+          const float Tn = T[p] * (1.0f - e.alpha);
+          const bool stop = use && Tn < kTMin;  // stop before this splat
+          done[p] = done[p] || stop;
+          const bool take = use && !stop;
+          const float w = take ? e.alpha * T[p] : 0.0f;
+          C0[p] += rc.x * w;
+          C1[p] += rc.y * w;
+          C2[p] += rc.z * w;
+          S0[p] += rc.x * w;
+          S1[p] += rc.y * w;
+          S2[p] += rc.z * w;
+          T[p] = take ? Tn : T[p];
+          last[p] = take ? idx : last[p];
         }
-        const float4 rc = s_c[j];
-        const float w = e.alpha * T[p];
-        C0[p] += rc.x * w;
-        C1[p] += rc.y * w;
-        C2[p] += rc.z * w;
-        T[p] = Tn;
-        last[p] = (int)(bs + j - tc.start) + 1;
+      };
+      // two register sets in turn: the next record loads while this one blends
+      int j0 = c * kWave + __builtin_ctzll(m);
+      m &= m - 1;
+      float4 a0 = s_a[j0], b0 = s_b[j0], c0 = s_c[j0];
+      for (;;) {
+        const bool more1 = m != 0;
+        const int j1 = more1 ? c * kWave + __builtin_ctzll(m) : j0;
+        m &= m - 1;
+        const float4 a1 = s_a[j1], b1 = s_b[j1], c1 = s_c[j1];
+        blend(j0, a0, b0, c0);
+        if (!more1) break;
+        const bool more2 = m != 0;
+        j0 = more2 ? c * kWave + __builtin_ctzll(m) : j1;
+        m &= m - 1;
+        a0 = s_a[j0], b0 = s_b[j0], c0 = s_c[j0];
+        blend(j1, a1, b1, c1);
+        if (!more2) break;
       }
+    }
+    bs = be;
+  }
+
+  // Each recorded state becomes (T there, colour composited after it): the
+  // suffix sums of the chunks' colours, last chunk first.
+  for (int k = nbnd; k >= 1; --k) {
+    const int64_t slot = (int64_t)(((uint64_t)tc.start + ((uint64_t)k << lc)) >> lc);
+    float4* st = a.state + slot * tpx;
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+      float4 v = st[threadIdx.x * PPT + p];
+      const float e0 = v.y, e1 = v.z, e2 = v.w;  // colour of the chunk before boundary k
+      v.y = S0[p];
+      v.z = S1[p];
+      v.w = S2[p];
+      st[threadIdx.x * PPT + p] = v;
+      S0[p] = e0 + S0[p];
+      S1[p] = e1 + S1[p];
+      S2[p] = e2 + S2[p];
     }
   }
 
@@ -282,10 +397,29 @@ __global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs a, ViewTable
                                                          const float* __restrict__ dL_dimage,
                                                          float* __restrict__ grad_pair) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ int s_len[4];
-  __shared__ int s_max[16];
-  const int gtile = blockIdx.x;
+  __shared__ int s_max[4];
+  // Work items: workgroups [0, nslots) take the chunks that start at a recorded
+  // boundary (slot order, so the long lists' chunks start first); the rest take
+  // each tile's first chunk, in the tile schedule.
+  const int lg = a.log2_chunk;
+  int gtile;
+  bool first;
+  if ((int64_t)blockIdx.x < a.nslots) {
+    const uint32_t owner = a.slot_owner[blockIdx.x];
+    if (owner >= (uint32_t)vt.total_tiles) return;  // no boundary here (uniform)
+    gtile = (int)owner;
+    first = false;
+  } else {
+    const int b = (int)((int64_t)blockIdx.x - a.nslots);
+    gtile = a.order ? (int)a.order[b] : b;
+    first = true;
+  }
   const TileCtx tc = tile_ctx(vt, a, gtile);
+  const uint64_t cmask = (1ull << lg) - 1;
+  // chunk [cs, ce) of the tile's list [start, end)
+  const uint64_t cs = first ? (uint64_t)tc.start : (((uint64_t)blockIdx.x << lg) | ((uint64_t)tc.start & cmask));
+  const uint64_t ce = min(cs + (1ull << lg), (uint64_t)tc.end);
+  if (!first && !(cs > (uint64_t)tc.start && cs < (uint64_t)tc.end)) return;  // a record not of this list
   const ViewArgs& va = vt.v[tc.view];
   const int nthreads = blockDim.x;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave, nwaves = nthreads / kWave;
@@ -298,7 +432,11 @@ __global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs a, ViewTable
   uint32_t* s_e = L.e;
   float* s_part = L.part;  // per-wave partial sums of one batch: [nwaves][batch][9]
   uint8_t* s_mask = L.mask;
-  uint8_t* s_list = L.list;
+
+  // this lane's element of the reduce-scatter (see reduce_scatter9)
+  const bool b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1;
+  const int k2 = 2 * (int)b3 + (int)b2, k1 = k2 + 3 * ((lane >> 4) & 1), my_e = k1 + 5 * ((lane >> 5) & 1);
+  const bool writer = (lane & 3) == 0 && k2 <= 2 && k1 <= 4 && my_e < GS_GRAD_FLOATS;
 
   float px[PPT], py[PPT], T[PPT], g0[PPT], g1[PPT], g2[PPT], RdL[PPT];
   int lc[PPT];
@@ -332,17 +470,42 @@ __global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs a, ViewTable
   int maxlast = 0;
   for (int w = 0; w < nwaves; ++w) maxlast = max(maxlast, s_max[w]);
   maxlast = min(maxlast, (int)(tc.end - tc.start));  // never walk past the tile's list
+  const uint64_t wlim = (uint64_t)tc.start + (uint64_t)maxlast;
 
-  // pairs behind every pixel's last contributor receive no gradient
-  for (uint32_t i = tc.start + (uint32_t)maxlast + threadIdx.x; i < tc.end; i += nthreads) {
-    float* gp = grad_pair + (size_t)a.pair_index[i] * GS_GRAD_FLOATS;
+  // Pairs behind every pixel's last contributor receive no gradient: each item
+  // clears its own chunk's share; the first item also clears the chunks that
+  // have no item because the forward stopped before reaching them.
+  auto clear = [&](uint64_t lo, uint64_t hi) {
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += nthreads) {
+      float* gp = grad_pair + (size_t)a.pair_index[i] * GS_GRAD_FLOATS;
 #pragma unroll
-    for (int k = 0; k < GS_GRAD_FLOATS; ++k) gp[k] = 0.0f;
+      for (int k = 0; k < GS_GRAD_FLOATS; ++k) gp[k] = 0.0f;
+    }
+  };
+  clear(max(cs, wlim), ce);
+  if (first) {
+    for (uint64_t q = cs + (1ull << lg); q < tc.end; q += (1ull << lg))
+      if (a.slot_owner[q >> lg] != (uint32_t)gtile) clear(max(q, wlim), min(q + (1ull << lg), (uint64_t)tc.end));
   }
 
-  const uint32_t wend = tc.start + (uint32_t)maxlast;
-  for (uint32_t be = wend; be > tc.start;) {
-    const uint32_t bs = (be - tc.start > (uint32_t)batch) ? be - batch : tc.start;
+  // Starting state at the chunk's end: the final one when the walk ends in
+  // this chunk, else the forward's record at ce (transmittance there, and the
+  // colour composited after it, which gives the dL/dC-weighted colour behind).
+  if (ce < wlim) {
+    const int tpx = 1 << (a.log2_tw + a.log2_th);
+    const float4* st = a.state + (int64_t)(ce >> lg) * tpx;
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+      const float4 v = st[threadIdx.x * PPT + p];
+      T[p] = v.x;
+      RdL[p] = RdL[p] + (v.y * g0[p] + v.z * g1[p] + v.w * g2[p]);
+    }
+  }
+
+  const uint32_t cstart = (uint32_t)cs;
+  const uint32_t wend = (uint32_t)min(ce, wlim);
+  for (uint32_t be = wend; be > cstart;) {
+    const uint32_t bs = (be - cstart > (uint32_t)batch) ? be - batch : cstart;
     const int cnt = (int)(be - bs);
     for (int i = threadIdx.x; i < cnt; i += nthreads) {
       const uint32_t rec = a.ids[bs + i];
@@ -356,66 +519,57 @@ __global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs a, ViewTable
     }
     for (int i = threadIdx.x; i < nwaves * batch * GS_GRAD_FLOATS; i += nthreads) s_part[i] = 0.0f;
     __syncthreads();
-    int len = cnt;
-    if (CULL) {
-      if (wave == 0) build_wave_lists(s_mask, cnt, nwaves, batch, s_list, s_len);
-      __syncthreads();
-      len = s_len[wave];
-    }
-    for (int jj = len - 1; jj >= 0; --jj) {
-      const int j = CULL ? (int)s_list[wave * batch + jj] : jj;
-      const int jr = (int)(bs - tc.start) + j;  // index within the tile's list
-      const float4 ra = s_a[j], rb = s_b[j], rc = s_c[j];
-      float gu = 0.f, gv = 0.f, gA = 0.f, gB = 0.f, gC = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gb = 0.f;
-      bool any = false;
+    const int nchunks = (cnt + kWave - 1) / kWave;
+    for (int c = nchunks - 1; c >= 0; --c) {
+      uint64_t m = chunk_bits<CULL>(s_mask, c, cnt, wave, lane);
+      if (m == 0) continue;
+      int bit = 63 - __builtin_clzll(m);  // back to front
+      m &= ~(1ull << bit);
+      int j = c * kWave + bit;
+      float4 ra = s_a[j], rb = s_b[j], rc = s_c[j];
+      for (;;) {
+        const bool more = m != 0;
+        const int nbit = more ? 63 - __builtin_clzll(m) : bit;
+        const int jn = c * kWave + nbit;
+        const float4 ran = s_a[jn], rbn = s_b[jn], rcn = s_c[jn];  // next entry, loaded ahead
+        const int jr = (int)(bs - tc.start) + j;                   // index within the tile's list
+        float x[GS_GRAD_FLOATS] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // u v A B C o' r g b
+        bool any = false;
 #pragma unroll
-      for (int p = 0; p < PPT; ++p) {
-        if (jr >= lc[p]) continue;
-        Eval e;
-        if (!eval_splat(px[p], py[p], ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, &e)) continue;
-        if (e.alpha < kAlphaMin) continue;
-        any = true;
-        const float inv = __builtin_amdgcn_rcpf(1.0f - e.alpha);
-        T[p] *= inv;  // transmittance in front of this splat
-        const float wgt = e.alpha * T[p];
-        gr += wgt * g0[p];
-        gg += wgt * g1[p];
-        gb += wgt * g2[p];
-        const float cd = rc.x * g0[p] + rc.y * g1[p] + rc.z * g2[p];
-        const float dLda = T[p] * cd - RdL[p] * inv;
-        RdL[p] += cd * wgt;
-        if (!(e.raw > kAlphaMax)) {
-          go += e.G * dLda;
+        for (int p = 0; p < PPT; ++p) {
+          // branch-free: lanes that do not composite this splat add exact zeros
+          Eval e;
+          const bool inside = eval_splat_all(px[p], py[p], ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, &e);
+          const bool use = jr < lc[p] && inside && !(e.alpha < kAlphaMin);
+          any |= use;
+          const float inv = __builtin_amdgcn_rcpf(1.0f - e.alpha);
+          T[p] = use ? T[p] * inv : T[p];  // transmittance in front of this splat
+          const float wgt = use ? e.alpha * T[p] : 0.0f;
+          x[6] += wgt * g0[p];
+          x[7] += wgt * g1[p];
+          x[8] += wgt * g2[p];
+          const float cd = rc.x * g0[p] + rc.y * g1[p] + rc.z * g2[p];
+          const float dLda = use && !(e.raw > kAlphaMax) ? T[p] * cd - RdL[p] * inv : 0.0f;
+          RdL[p] += cd * wgt;
+          x[5] += e.G * dLda;
           const float dLdq = -0.5f * e.alpha * dLda;
-          gA += dLdq * e.dx * e.dx;
-          gB += dLdq * 2.0f * e.dx * e.dy;
-          gC += dLdq * e.dy * e.dy;
-          gu += -2.0f * dLdq * (ra.z * e.dx + ra.w * e.dy);
-          gv += -2.0f * dLdq * (ra.w * e.dx + rb.x * e.dy);
+          x[2] += dLdq * e.dx * e.dx;
+          x[3] += dLdq * 2.0f * e.dx * e.dy;
+          x[4] += dLdq * e.dy * e.dy;
+          x[0] += -2.0f * dLdq * (ra.z * e.dx + ra.w * e.dy);
+          x[1] += -2.0f * dLdq * (ra.w * e.dx + rb.x * e.dy);
         }
-      }
-      if (__ballot(any) != 0) {  // wave-uniform
-        gu = wave_sum_lane63(gu);
-        gv = wave_sum_lane63(gv);
-        gA = wave_sum_lane63(gA);
-        gB = wave_sum_lane63(gB);
-        gC = wave_sum_lane63(gC);
-        go = wave_sum_lane63(go);
-        gr = wave_sum_lane63(gr);
-        gg = wave_sum_lane63(gg);
-        gb = wave_sum_lane63(gb);
-        if (lane == kWave - 1) {
-          float* part = &s_part[(wave * batch + j) * GS_GRAD_FLOATS];
-          part[0] = gu;
-          part[1] = gv;
-          part[2] = gA;
-          part[3] = gB;
-          part[4] = gC;
-          part[5] = go;
-          part[6] = gr;
-          part[7] = gg;
-          part[8] = gb;
+        if (__ballot(any) != 0) {  // wave-uniform: the whole wave takes part
+          const float v = reduce_scatter9(x, b2, b3);
+          if (writer) s_part[(wave * batch + j) * GS_GRAD_FLOATS + my_e] = v;
         }
+        if (!more) break;
+        m &= ~(1ull << nbit);
+        bit = nbit;
+        j = jn;
+        ra = ran;
+        rb = rbn;
+        rc = rcn;
       }
     }
     __syncthreads();
@@ -449,7 +603,8 @@ template <int PPT>
 static void bwd_ppt(const RenderArgs& a, const ViewTable& vt, const float* T_final, const int32_t* last,
                     const float* dL, float* grad_pair, hipStream_t s) {
   const int nt = tile_threads(a);
-  const dim3 grid((unsigned)vt.total_tiles), block((unsigned)nt);
+  // chunk items first, then one item per tile
+  const dim3 grid((unsigned)(a.nslots + vt.total_tiles)), block((unsigned)nt);
   const size_t sh = lds_bytes(bwd_batch(a.batch, nt / kWave), nt / kWave, true);
   if (a.cull)
     hipLaunchKernelGGL((render_bwd_kernel<PPT, true>), grid, block, sh, s, a, vt, T_final, last, dL, grad_pair);
@@ -460,6 +615,8 @@ static void bwd_ppt(const RenderArgs& a, const ViewTable& vt, const float* T_fin
 hipError_t launch_render_fwd(const RenderArgs& a, const ViewTable& vt, float* image, float* T_final,
                              int32_t* last_contrib, hipStream_t s) {
   if (vt.total_tiles == 0) return hipSuccess;
+  const hipError_t e = launch_fill_u32(a.slot_owner, a.nslots, 0xffffffffu, s);  // no boundary recorded yet
+  if (e != hipSuccess) return e;
   switch (a.ppt) {
     case 1: fwd_ppt<1>(a, vt, image, T_final, last_contrib, s); break;
     case 2: fwd_ppt<2>(a, vt, image, T_final, last_contrib, s); break;

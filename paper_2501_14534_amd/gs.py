@@ -39,7 +39,8 @@ class GsCamera(C.Structure):
 class GsOpts(C.Structure):
     _fields_ = [("near_plane", C.c_float), ("tan_clamp", C.c_float), ("lowpass", C.c_float),
                 ("bg", C.c_float * 3), ("tile_w", C.c_int32), ("tile_h", C.c_int32),
-                ("batch_depth", C.c_int32), ("pixels_per_thread", C.c_int32), ("subtile_cull", C.c_int32)]
+                ("batch_depth", C.c_int32), ("pixels_per_thread", C.c_int32), ("subtile_cull", C.c_int32),
+                ("bwd_chunk", C.c_int32)]
 
 
 class GsProjected(C.Structure):
@@ -47,7 +48,7 @@ class GsProjected(C.Structure):
 
 
 class GsBinning(C.Structure):
-    _fields_ = [("keys", vp), ("ids", vp), ("pair_index", vp), ("offsets", vp), ("ranges", vp),
+    _fields_ = [("keys", vp), ("ids", vp), ("pair_index", vp), ("offsets", vp), ("ranges", vp), ("order", vp),
                 ("capacity", C.c_uint64), ("count", vp), ("status", vp)]
 
 
@@ -82,13 +83,13 @@ def load():
                               C.c_size_t, vp]
     L.gs_bin_sort.restype = C.c_int
     L.gs_render_fwd.argtypes = [P(GsProjected), P(GsBinning), P(GsCamera), C.c_int32, C.c_int64, P(GsOpts), vp, vp,
-                                vp, vp]
+                                vp, vp, C.c_size_t, vp]
     L.gs_render_fwd.restype = C.c_int
     L.gs_render_bwd.argtypes = [P(GsGaussians), P(GsCamera), C.c_int32, P(GsOpts), P(GsProjected), P(GsBinning),
                                 vp, vp, vp, P(GsGrads), vp, C.c_size_t, vp]
     L.gs_render_bwd.restype = C.c_int
     L.gs_blend_bwd.argtypes = [P(GsCamera), C.c_int32, C.c_int64, P(GsOpts), P(GsProjected), P(GsBinning), vp, vp,
-                               vp, vp, vp]
+                               vp, vp, vp, C.c_size_t, vp]
     L.gs_blend_bwd.restype = C.c_int
     L.gs_project_bwd.argtypes = [P(GsGaussians), P(GsCamera), C.c_int32, P(GsOpts), P(GsProjected), P(GsBinning),
                                  vp, P(GsGrads), vp, C.c_size_t, vp]
@@ -132,6 +133,7 @@ def options(o) -> GsOpts:
     s.tile_w, s.tile_h = int(o.tile_w), int(o.tile_h)
     s.batch_depth, s.pixels_per_thread = int(o.batch_depth), int(o.pixels_per_thread)
     s.subtile_cull = int(getattr(o, "subtile_cull", 1))
+    s.bwd_chunk = int(getattr(o, "bwd_chunk", 1024))
     return s
 
 
@@ -161,9 +163,9 @@ def bin_sort(proj, cams_arr, V, n, opts_s, bins, ws, ws_bytes, stream) -> int:
     return load().gs_bin_sort(C.byref(proj), cams_arr, V, int(n), C.byref(opts_s), C.byref(bins), ws, ws_bytes, stream)
 
 
-def render_fwd(proj, bins, cams_arr, V, n, opts_s, image, T_final, last, stream) -> int:
+def render_fwd(proj, bins, cams_arr, V, n, opts_s, image, T_final, last, ws, ws_bytes, stream) -> int:
     return load().gs_render_fwd(C.byref(proj), C.byref(bins), cams_arr, V, int(n), C.byref(opts_s), image, T_final,
-                                last, stream)
+                                last, ws, ws_bytes, stream)
 
 
 def render_bwd(g, cams_arr, V, opts_s, proj, bins, T_final, last, dL_dimage, grads, ws, ws_bytes, stream) -> int:
@@ -171,9 +173,9 @@ def render_bwd(g, cams_arr, V, opts_s, proj, bins, T_final, last, dL_dimage, gra
                                 dL_dimage, C.byref(grads), ws, ws_bytes, stream)
 
 
-def blend_bwd(cams_arr, V, n, opts_s, proj, bins, T_final, last, dL_dimage, grad_pair, stream) -> int:
+def blend_bwd(cams_arr, V, n, opts_s, proj, bins, T_final, last, dL_dimage, grad_pair, ws, ws_bytes, stream) -> int:
     return load().gs_blend_bwd(cams_arr, V, int(n), C.byref(opts_s), C.byref(proj), C.byref(bins), T_final, last,
-                               dL_dimage, grad_pair, stream)
+                               dL_dimage, grad_pair, ws, ws_bytes, stream)
 
 
 def project_bwd(g, cams_arr, V, opts_s, proj, bins, grad_pair, grads, ws, ws_bytes, stream) -> int:

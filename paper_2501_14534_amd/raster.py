@@ -38,7 +38,8 @@ class Rasterizer:
     """
 
     def __init__(self, n: int, sh_degree: int, cams: Sequence, opts, *, mask_eps: float = 0.5,
-                 sh_mask_eps: float = 0.5, capacity: Optional[int] = None, device: str = "cuda"):
+                 sh_mask_eps: float = 0.5, capacity: Optional[int] = None, device: str = "cuda",
+                 schedule: bool = True, keep_keys: bool = False):
         gs.load()
         if len(cams) < 1 or len(cams) > gs.MAX_VIEWS:
             raise ValueError(f"1..{gs.MAX_VIEWS} views per call")
@@ -46,6 +47,7 @@ class Rasterizer:
         self.cams = list(cams)
         self.opts = opts
         self.mask_eps, self.sh_mask_eps = mask_eps, sh_mask_eps
+        self.keep_keys = keep_keys  # the 64-bit sort keys are written only when asked for (tests)
         dev = torch.device(device)
         if dev.type == "cuda" and dev.index is None:
             dev = torch.device("cuda", torch.cuda.current_device())
@@ -59,6 +61,8 @@ class Rasterizer:
         self.tiles_touched = torch.zeros(max(nrec, 1), dtype=torch.int32, device=dev)
         self.offsets = torch.zeros(max(nrec, 1), dtype=torch.int32, device=dev)
         self.ranges = torch.zeros(max(self.total_tiles, 1) * 2, dtype=torch.int32, device=dev)
+        # heaviest-first tile schedule written by gs_bin_sort (None: tile-id order)
+        self.order = torch.zeros(max(self.total_tiles, 1), dtype=torch.int32, device=dev) if schedule else None
         self.count = torch.zeros(1, dtype=torch.int32, device=dev)
         self.status = torch.zeros(1, dtype=torch.int32, device=dev)
         self.image = torch.zeros(3 * self.total_pixels, dtype=torch.float32, device=dev)
@@ -72,7 +76,7 @@ class Rasterizer:
     def set_capacity(self, capacity: int) -> None:
         capacity = int(min(max(capacity, 1), (1 << 32) - 1))
         self.capacity = capacity
-        self.keys = torch.zeros(capacity, dtype=torch.int64, device=self.device)
+        self.keys = torch.zeros(capacity, dtype=torch.int64, device=self.device) if self.keep_keys else None
         self.ids = torch.zeros(capacity, dtype=torch.int32, device=self.device)
         self.pair_index = torch.zeros(capacity, dtype=torch.int32, device=self.device)
         self.ws_bytes = gs.workspace_size(self.n, self.cams_arr, self.V, self.opts_s, capacity)
@@ -80,7 +84,8 @@ class Rasterizer:
             raise gs.GsError("invalid configuration for gs_workspace_size")
         self.ws = torch.zeros(self.ws_bytes, dtype=torch.uint8, device=self.device)
         self.bins = gs.GsBinning(gs.ptr(self.keys), gs.ptr(self.ids), gs.ptr(self.pair_index), gs.ptr(self.offsets),
-                                 gs.ptr(self.ranges), capacity, gs.ptr(self.count), gs.ptr(self.status))
+                                 gs.ptr(self.ranges), gs.ptr(self.order), capacity, gs.ptr(self.count),
+                                 gs.ptr(self.status))
 
     def gaussians(self, params: Dict[str, torch.Tensor]) -> gs.GsGaussians:
         for k, t in params.items():
@@ -101,7 +106,8 @@ class Rasterizer:
 
     def render_fwd(self) -> None:
         gs.check(gs.render_fwd(self.proj, self.bins, self.cams_arr, self.V, self.n, self.opts_s, gs.ptr(self.image),
-                               gs.ptr(self.T_final), gs.ptr(self.last), _stream()), "gs_render_fwd")
+                               gs.ptr(self.T_final), gs.ptr(self.last), gs.ptr(self.ws), self.ws_bytes, _stream()),
+                 "gs_render_fwd")
 
     def render_bwd(self, params, dL_dimage: torch.Tensor, grads: Dict[str, torch.Tensor],
                    mean2d: Optional[torch.Tensor] = None) -> None:
@@ -118,7 +124,8 @@ class Rasterizer:
         if grad_pair.numel() < self.capacity * gs.GRAD_FLOATS:
             raise ValueError("grad_pair must hold capacity x 9 floats")
         gs.check(gs.blend_bwd(self.cams_arr, self.V, self.n, self.opts_s, self.proj, self.bins, gs.ptr(self.T_final),
-                              gs.ptr(self.last), gs.ptr(dL_dimage), gs.ptr(grad_pair), _stream()), "gs_blend_bwd")
+                              gs.ptr(self.last), gs.ptr(dL_dimage), gs.ptr(grad_pair), gs.ptr(self.ws),
+                              self.ws_bytes, _stream()), "gs_blend_bwd")
 
     def project_bwd(self, params, grad_pair: torch.Tensor, grads: Dict[str, torch.Tensor], mean2d=None) -> None:
         g = self.gaussians(params)

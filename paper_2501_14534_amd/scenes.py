@@ -108,6 +108,7 @@ class Opts:
     batch_depth: int = 256
     pixels_per_thread: int = 1
     subtile_cull: int = 1
+    bwd_chunk: int = 1024  # list entries per backward work item (0: one per tile)
 
 
 @dataclasses.dataclass

@@ -33,15 +33,15 @@ GRAD_RTOL = 1e-3
 GRAD_FLOOR = 1e-2
 
 
-def make_rasterizer(wl, opts=None, capacity=None):
+def make_rasterizer(wl, opts=None, capacity=None, schedule=True):
     opts = opts or wl.opts
     sc = wl.scene
     return raster.Rasterizer(sc.n, sc.sh_degree, wl.cams, opts, mask_eps=sc.mask_eps, sh_mask_eps=sc.sh_mask_eps,
-                             capacity=capacity)
+                             capacity=capacity, schedule=schedule, keep_keys=True)
 
 
-def gpu_forward(wl, opts=None, capacity=None, params=None):
-    r = make_rasterizer(wl, opts, capacity)
+def gpu_forward(wl, opts=None, capacity=None, params=None, schedule=True):
+    r = make_rasterizer(wl, opts, capacity, schedule)
     params = params if params is not None else raster.to_device(wl.scene)
     r.forward(params)
     torch.cuda.synchronize()

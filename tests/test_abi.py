@@ -60,6 +60,9 @@ def test_workspace_size(lib):
     bad = gs.options(dataclasses.replace(wl.opts, tile_w=12))
     assert gs.workspace_size(100, cams, 1, bad, 1000) == 0
     assert gs.workspace_size(100, cams, 1, o, 1 << 33) == 0
+    # smaller backward chunks need more chunk-state slots
+    small = gs.options(dataclasses.replace(wl.opts, bwd_chunk=16))
+    assert gs.workspace_size(100, cams, 1, small, 100000) > b
 
 
 def _bad_opts(wl):
@@ -71,6 +74,8 @@ def _bad_opts(wl):
     yield dataclasses.replace(wl.opts, batch_depth=257)
     yield dataclasses.replace(wl.opts, lowpass=-1.0)
     yield dataclasses.replace(wl.opts, tan_clamp=0.0)
+    yield dataclasses.replace(wl.opts, bwd_chunk=100)                # not a power of two
+    yield dataclasses.replace(wl.opts, bwd_chunk=8)                  # below 16
 
 
 def test_project_rejects_invalid_arguments(lib):
@@ -118,19 +123,23 @@ def test_other_entry_points_reject_null_buffers(lib):
     cams = gs.cameras(wl.cams)
     o = gs.options(wl.opts)
     proj = gs.GsProjected(4096, 4096)
-    bins = gs.GsBinning(4096, 4096, 4096, 4096, None, 100, 4096, 4096)  # ranges missing
+    bins = gs.GsBinning(4096, 4096, 4096, 4096, None, None, 100, 4096, 4096)  # ranges missing
     assert lib.gs_bin_sort(C.byref(proj), cams, 1, 64, C.byref(o), C.byref(bins), 4096, 1 << 30, None) == \
         gs.GS_E_INVALID
-    bins = gs.GsBinning(4096, 4096, None, 4096, 4096, 100, 4096, 4096)  # pair_index missing
+    bins = gs.GsBinning(4096, 4096, None, 4096, 4096, None, 100, 4096, 4096)  # pair_index missing
     assert lib.gs_bin_sort(C.byref(proj), cams, 1, 64, C.byref(o), C.byref(bins), 4096, 1 << 30, None) == \
         gs.GS_E_INVALID
-    bins = gs.GsBinning(4096, 4096, 4096, None, 4096, 100, 4096, 4096)  # offsets missing
+    bins = gs.GsBinning(4096, 4096, 4096, None, 4096, None, 100, 4096, 4096)  # offsets missing
     assert lib.gs_bin_sort(C.byref(proj), cams, 1, 64, C.byref(o), C.byref(bins), 4096, 1 << 30, None) == \
         gs.GS_E_INVALID
-    bins = gs.GsBinning(4096, 4096, 4096, 4096, 4096, 100, 4096, 4096)
+    bins = gs.GsBinning(4096, 4096, 4096, 4096, 4096, None, 100, 4096, 4096)
     assert lib.gs_bin_sort(C.byref(proj), cams, 1, 64, C.byref(o), C.byref(bins), 4096, 16, None) == \
         gs.GS_E_INVALID  # workspace too small
-    assert lib.gs_render_fwd(C.byref(proj), C.byref(bins), cams, 1, 64, C.byref(o), None, 4096, 4096, None) == \
-        gs.GS_E_INVALID
+    assert lib.gs_render_fwd(C.byref(proj), C.byref(bins), cams, 1, 64, C.byref(o), None, 4096, 4096, 4096,
+                             1 << 30, None) == gs.GS_E_INVALID  # image missing
+    assert lib.gs_render_fwd(C.byref(proj), C.byref(bins), cams, 1, 64, C.byref(o), 4096, 4096, 4096, 4096,
+                             16, None) == gs.GS_E_INVALID  # workspace too small for the chunk states
     assert lib.gs_blend_bwd(cams, 1, 64, C.byref(o), C.byref(proj), C.byref(bins), 4096, 4096, 4096, None,
-                            None) == gs.GS_E_INVALID
+                            4096, 1 << 30, None) == gs.GS_E_INVALID
+    assert lib.gs_blend_bwd(cams, 1, 64, C.byref(o), C.byref(proj), C.byref(bins), 4096, 4096, 4096, 4096,
+                            None, 1 << 30, None) == gs.GS_E_INVALID  # workspace missing

@@ -66,10 +66,14 @@ def test_render_fwd_parity(P, case):
     assert res["flagged_frac"] <= 1e-3
 
 
+@pytest.mark.parametrize("chunk", [1024, 16])
 @pytest.mark.parametrize("case", list(CASES))
-def test_render_bwd_parity(P, case):
+def test_render_bwd_parity(P, case, chunk):
+    """Backward vs the oracle.  With chunk 16 every list longer than 16 is walked by several
+    work items in parallel, each starting from the state the forward recorded at its end."""
     wl = CASES[case]()
-    print(f"[render_bwd] {case}", flush=True)
+    wl = dataclasses.replace(wl, opts=dataclasses.replace(wl.opts, bwd_chunk=chunk))
+    print(f"[render_bwd] {case} chunk {chunk}", flush=True)
     r, params = P.gpu_forward(wl)
     fwd = P.check_forward(wl, wl.opts, r)
     res = P.check_backward(wl, wl.opts, r, params, fwd["flagged"], seed=3)
