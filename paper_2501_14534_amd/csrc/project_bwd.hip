@@ -3,12 +3,15 @@
 // call and added (+=) to the caller's gradient arrays.  Straight-through
 // estimator for the hard masks (Eq. 3, Eq. 5): d(mask)/d(logit) = sigmoid'.
 //
-// Two kernels, one thread per Gaussian each (no atomics):
-//   colour:   sums each record's pairs in emission order (double), keeps the
-//             geometry sums for the second kernel, and runs the SH chain
-//             (diffuse colour, bands 1..3, band-mask logits, and the
-//             view-direction term of the mean) in single precision;
-//   geometry: the EWA chain in double precision (this half is bound by
+// Three kernels (no atomics):
+//   sums:     one thread per (view, Gaussian) record: its pairs' gradients
+//             summed in emission order (double); geometry sums kept in double,
+//             colour sums rounded to float (adjacent records' pairs are
+//             adjacent, so a wave reads one contiguous stretch);
+//   colour:   one thread per Gaussian: the SH chain (diffuse colour, bands
+//             1..3, band-mask logits, and the view-direction term of the
+//             mean) in single precision;
+//   geometry: one thread per Gaussian: the EWA chain in double precision (this half is bound by
 //             memory traffic, and the 2x2 inverse amplifies rounding by the
 //             condition number of Sigma'):
 //     dL/dSigma'  = -Q G_Q Q              (G_Q = [[gA, gB/2], [gB/2, gC]], Q = conic)
@@ -83,6 +86,34 @@ __device__ __forceinline__ float acc_mul_add(float t, float a, float b) {
   return t + p;
 }
 
+// Per record: sums of its pairs' 9 gradients in emission order.  rec_geo gets
+// (u, v, A, B, C, o') in double, rec_mu[0..2] the colour sums in float (the
+// colour kernel replaces them with the colour term of the mean gradient).
+__global__ __launch_bounds__(256) void record_sum_kernel(ProjectBwdArgs b, int64_t nrec) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrec) return;
+  if (*b.status != 0) return;  // binning overflowed: no lists, no gradients
+  const uint32_t cntp = b.tiles_touched[r];
+  if (cntp == 0) return;
+  double gsum[GS_GRAD_FLOATS] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  const float* gp = b.grad_pair + (size_t)b.offsets[r] * GS_GRAD_FLOATS;
+  for (uint32_t k = 0; k < cntp; ++k)
+#pragma unroll
+    for (int c = 0; c < GS_GRAD_FLOATS; ++c) gsum[c] += (double)gp[(size_t)k * GS_GRAD_FLOATS + c];
+  double* geo = b.rec_geo + r * 6;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) geo[c] = gsum[c];
+  if (b.g_mean2d) {
+    const int64_t n = b.p.n, v = r / n, i = r - v * n;
+    b.g_mean2d[(v * 2 + 0) * n + i] += (float)gsum[0];
+    b.g_mean2d[(v * 2 + 1) * n + i] += (float)gsum[1];
+  }
+  float* cmu = b.rec_mu + r * 4;
+  cmu[0] = (float)gsum[6];
+  cmu[1] = (float)gsum[7];
+  cmu[2] = (float)gsum[8];
+}
+
 template <int DEG>
 __global__ __launch_bounds__(256) void project_bwd_color_kernel(ProjectBwdArgs b, ViewTable vt) {
   const ProjectArgs& a = b.p;
@@ -127,23 +158,9 @@ __global__ __launch_bounds__(256) void project_bwd_color_kernel(ProjectBwdArgs b
 
   for (int v = 0; v < V; ++v) {
     const size_t r = (size_t)v * n + i;
-    const uint32_t cntp = b.tiles_touched[r];
-    if (cntp == 0) continue;
-    // this record's pairs, in emission order
-    double gsum[GS_GRAD_FLOATS] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    const float* gp = b.grad_pair + (size_t)b.offsets[r] * GS_GRAD_FLOATS;
-    for (uint32_t k = 0; k < cntp; ++k)
-#pragma unroll
-      for (int c = 0; c < GS_GRAD_FLOATS; ++c) gsum[c] += (double)gp[(size_t)k * GS_GRAD_FLOATS + c];
-    double* geo = b.rec_geo + r * 6;
-#pragma unroll
-    for (int c = 0; c < 6; ++c) geo[c] = gsum[c];
-    if (b.g_mean2d) {
-      b.g_mean2d[((size_t)v * 2 + 0) * n + i] += (float)gsum[0];
-      b.g_mean2d[((size_t)v * 2 + 1) * n + i] += (float)gsum[1];
-    }
-    float* cmu = b.rec_mu + r * 4;
-    const float grgb[3] = {(float)gsum[6], (float)gsum[7], (float)gsum[8]};
+    if (b.tiles_touched[r] == 0) continue;
+    float* cmu = b.rec_mu + r * 4;  // colour sums of this record's pairs (record_sum_kernel)
+    const float grgb[3] = {cmu[0], cmu[1], cmu[2]};
     if (grgb[0] == 0.f && grgb[1] == 0.f && grgb[2] == 0.f) {
       cmu[0] = cmu[1] = cmu[2] = 0.f;
       continue;
@@ -405,6 +422,8 @@ __global__ __launch_bounds__(256) void project_bwd_geom_kernel(ProjectBwdArgs b,
 hipError_t launch_project_bwd(const ProjectBwdArgs& a, const ViewTable& vt, int deg, hipStream_t s) {
   if (a.p.n == 0) return hipSuccess;
   const dim3 block(256), grid((unsigned)((a.p.n + 255) / 256));
+  const int64_t nrec = (int64_t)vt.nviews * a.p.n;
+  hipLaunchKernelGGL(record_sum_kernel, dim3((unsigned)((nrec + 255) / 256)), block, 0, s, a, nrec);
   switch (deg) {
     case 0: hipLaunchKernelGGL(project_bwd_color_kernel<0>, grid, block, 0, s, a, vt); break;
     case 1: hipLaunchKernelGGL(project_bwd_color_kernel<1>, grid, block, 0, s, a, vt); break;

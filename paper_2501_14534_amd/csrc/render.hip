@@ -66,25 +66,39 @@ __device__ __forceinline__ void pixel_of(const RenderArgs& a, int ppt, int t, in
   *y = (ty << a.log2_th) + (syi << a.log2_sh) + (li >> a.log2_sw);
 }
 
-// Pixel-centre box of wave w's sub-tile.
+// Box of pixel centres [x0, x1] x [y0, y1]; empty when x0 > x1.
 struct Box {
   float x0, x1, y0, y1;
 };
 
-__device__ __forceinline__ Box wave_box(const RenderArgs& a, int w, int tx, int ty) {
-  const int sxi = w & ((1 << a.log2_sx) - 1), syi = w >> a.log2_sx;
-  const int x0 = (tx << a.log2_tw) + (sxi << a.log2_sw), y0 = (ty << a.log2_th) + (syi << a.log2_sh);
-  Box b;
-  b.x0 = (float)x0 + 0.5f;
-  b.x1 = (float)(x0 + (1 << a.log2_sw) - 1) + 0.5f;
-  b.y0 = (float)y0 + 0.5f;
-  b.y1 = (float)(y0 + (1 << a.log2_sh) - 1) + 0.5f;
+// Box of the pixel centres of this wave's lanes whose pixel is still live
+// (may still composite or receive gradient), the same value in every lane.
+// Culling against it instead of the wave's whole sub-tile drops the records
+// that can only reach pixels that have already stopped.
+template <int PPT>
+__device__ __forceinline__ Box live_box(const float (&px)[PPT], const float (&py)[PPT], const bool (&live)[PPT]) {
+  Box b{__builtin_inff(), -__builtin_inff(), __builtin_inff(), -__builtin_inff()};
+#pragma unroll
+  for (int p = 0; p < PPT; ++p)
+    if (live[p]) {
+      b.x0 = fminf(b.x0, px[p]);
+      b.x1 = fmaxf(b.x1, px[p]);
+      b.y0 = fminf(b.y0, py[p]);
+      b.y1 = fmaxf(b.y1, py[p]);
+    }
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    b.x0 = fminf(b.x0, __shfl_xor(b.x0, o, kWave));
+    b.x1 = fmaxf(b.x1, __shfl_xor(b.x1, o, kWave));
+    b.y0 = fminf(b.y0, __shfl_xor(b.y0, o, kWave));
+    b.y1 = fmaxf(b.y1, __shfl_xor(b.y1, o, kWave));
+  }
   return b;
 }
 
-// Bit w set when record (u, v, conic, o', radius) may composite some pixel of wave w.
-__device__ __forceinline__ uint32_t footprint_mask(const RenderArgs& a, float4 ra, float4 rb, int nwaves, int tx,
-                                                   int ty) {
+// Bit w set when record (u, v, conic, o', radius) may composite some pixel in
+// wave w's live box.
+__device__ __forceinline__ uint32_t footprint_mask(float4 ra, float4 rb, int nwaves, const Box* boxes) {
   const float u = ra.x, v = ra.y, A = ra.z, B = ra.w, C = rb.x, o = rb.y, r = rb.z;
   if (!(o >= kAlphaMin * 0.999f)) return 0u;  // alpha <= o' < 1/255 at every pixel
   float ex = r, ey = r;
@@ -103,7 +117,7 @@ __device__ __forceinline__ uint32_t footprint_mask(const RenderArgs& a, float4 r
   ey += 0.5f;
   uint32_t m = 0u;
   for (int w = 0; w < nwaves; ++w) {
-    const Box b = wave_box(a, w, tx, ty);
+    const Box b = boxes[w];
     const bool hit = (u + ex >= b.x0) && (u - ex <= b.x1) && (v + ey >= b.y0) && (v - ey <= b.y1);
     m |= hit ? (1u << w) : 0u;
   }
@@ -231,6 +245,7 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable
                                                          float* __restrict__ T_final, int32_t* __restrict__ last_out) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_alive[4];
+  __shared__ Box s_box[4];
   const int gtile = tile_of_block(a);
   const TileCtx tc = tile_ctx(vt, a, gtile);
   const ViewArgs& va = vt.v[tc.view];
@@ -264,11 +279,40 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable
   const int tpx = 1 << (a.log2_tw + a.log2_th);
   const int lc = a.log2_chunk;
   int nbnd = 0;  // chunk boundaries recorded (uniform)
-  for (uint32_t bs = tc.start; bs < tc.end;) {
-    bool alive = false;
+  // batches never straddle a chunk boundary
+  auto batch_end = [&](uint32_t b0) -> uint32_t {
+    const uint64_t rel = b0 - tc.start;
+    const uint64_t next = (uint64_t)tc.start + (((rel >> lc) + 1) << lc);
+    return (uint32_t)min(min((uint64_t)tc.end, (uint64_t)b0 + (uint64_t)a.batch), next);
+  };
+  // Software-pipelined gather: while a batch is walked, thread t holds the
+  // record of entry t of the next batch (loads in flight) and the id of entry
+  // t of the batch after it.
+  const int t = threadIdx.x;
+  uint32_t bs = tc.start;
+  uint32_t be = bs < tc.end ? batch_end(bs) : bs;
+  uint32_t be2 = be < tc.end ? batch_end(be) : be;
+  float4 pa = make_float4(0.f, 0.f, 0.f, 0.f), pb = pa, pc = pa;
+  uint32_t nid = 0;
+  if (bs + t < be) {
+    const uint32_t rec = a.ids[bs + t];
+    pa = a.splats[(size_t)rec * 3 + 0];
+    pb = a.splats[(size_t)rec * 3 + 1];
+    pc = a.splats[(size_t)rec * 3 + 2];
+  }
+  if (be + t < be2) nid = a.ids[be + t];
+  while (bs < tc.end) {
+    bool alive = false, live[PPT];
 #pragma unroll
-    for (int p = 0; p < PPT; ++p) alive |= !done[p];
+    for (int p = 0; p < PPT; ++p) {
+      live[p] = !done[p];
+      alive |= live[p];
+    }
     const uint64_t vote = __ballot(alive);
+    if (CULL) {
+      const Box b = live_box<PPT>(px, py, live);
+      if (lane == 0) s_box[wave] = b;
+    }
     if (lane == 0) s_alive[wave] = vote != 0;
     __syncthreads();  // also: every wave has finished walking the previous batch
     int any = 0;
@@ -288,19 +332,30 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable
       if (threadIdx.x == 0) a.slot_owner[slot] = (uint32_t)gtile;
       ++nbnd;
     }
-    // batches never straddle a chunk boundary
-    const uint64_t next = (uint64_t)tc.start + (((rel >> lc) + 1) << lc);
-    const uint32_t be = (uint32_t)min(min((uint64_t)tc.end, (uint64_t)bs + (uint64_t)a.batch), next);
     const int cnt = (int)(be - bs);
-    for (int i = threadIdx.x; i < cnt; i += nthreads) {
+    if (t < cnt) {  // entry t from the registers
+      s_a[t] = pa;
+      s_b[t] = pb;
+      s_c[t] = pc;
+      if (CULL) s_mask[t] = (uint8_t)footprint_mask(pa, pb, nwaves, s_box);
+    }
+    for (int i = t + nthreads; i < cnt; i += nthreads) {  // batches deeper than the workgroup
       const uint32_t rec = a.ids[bs + i];
       const float4 ra = a.splats[(size_t)rec * 3 + 0];
       const float4 rb = a.splats[(size_t)rec * 3 + 1];
       s_a[i] = ra;
       s_b[i] = rb;
       s_c[i] = a.splats[(size_t)rec * 3 + 2];
-      if (CULL) s_mask[i] = (uint8_t)footprint_mask(a, ra, rb, nwaves, tc.tx, tc.ty);
+      if (CULL) s_mask[i] = (uint8_t)footprint_mask(ra, rb, nwaves, s_box);
     }
+    // issue the next batch's record loads and the following batch's id loads
+    const uint32_t be3 = be2 < tc.end ? batch_end(be2) : be2;
+    if (be + t < be2) {
+      pa = a.splats[(size_t)nid * 3 + 0];
+      pb = a.splats[(size_t)nid * 3 + 1];
+      pc = a.splats[(size_t)nid * 3 + 2];
+    }
+    nid = be2 + t < be3 ? a.ids[be2 + t] : 0u;
     __syncthreads();
     const int nchunks = (cnt + kWave - 1) / kWave;
     for (int c = 0; c < nchunks; ++c) {
@@ -354,6 +409,8 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable
       }
     }
     bs = be;
+    be = be2;
+    be2 = be3;
   }
 
   // Each recorded state becomes (T there, colour composited after it): the
@@ -398,6 +455,7 @@ __global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs a, ViewTable
                                                          float* __restrict__ grad_pair) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_max[4];
+  __shared__ Box s_box[4];
   // Work items: workgroups [0, nslots) take the chunks that start at a recorded
   // boundary (slot order, so the long lists' chunks start first); the rest take
   // each tile's first chunk, in the tile schedule.
@@ -507,6 +565,15 @@ __global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs a, ViewTable
   for (uint32_t be = wend; be > cstart;) {
     const uint32_t bs = (be - cstart > (uint32_t)batch) ? be - batch : cstart;
     const int cnt = (int)(be - bs);
+    if (CULL) {
+      // live pixels: those with an entry of this batch before their last contributor
+      bool live[PPT];
+#pragma unroll
+      for (int p = 0; p < PPT; ++p) live[p] = lc[p] > (int)(bs - tc.start);
+      const Box b = live_box<PPT>(px, py, live);
+      if (lane == 0) s_box[wave] = b;
+      __syncthreads();
+    }
     for (int i = threadIdx.x; i < cnt; i += nthreads) {
       const uint32_t rec = a.ids[bs + i];
       const float4 ra = a.splats[(size_t)rec * 3 + 0];
@@ -515,7 +582,7 @@ __global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs a, ViewTable
       s_a[i] = ra;
       s_b[i] = rb;
       s_c[i] = a.splats[(size_t)rec * 3 + 2];
-      if (CULL) s_mask[i] = (uint8_t)footprint_mask(a, ra, rb, nwaves, tc.tx, tc.ty);
+      if (CULL) s_mask[i] = (uint8_t)footprint_mask(ra, rb, nwaves, s_box);
     }
     for (int i = threadIdx.x; i < nwaves * batch * GS_GRAD_FLOATS; i += nthreads) s_part[i] = 0.0f;
     __syncthreads();
