@@ -321,49 +321,65 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
   return m;
 }
 
-// NV value arrays travel with the keys (NV = 1 or 2; the second may be null when NV = 1).
-template <typename KT, int NV>
-__global__ __launch_bounds__(kSortThreads) void radix_scatter(const KT* __restrict__ kin,
+// One stable scatter pass for 32-bit keys; NV value arrays travel with the
+// keys (NV = 1 or 2; the second may be null when NV = 1).  The block's 4096
+// elements are first ranked into LDS in (digit, index) order, then written
+// out run by run, so consecutive threads write consecutive addresses.
+template <int NV>
+__global__ __launch_bounds__(kSortThreads) void radix_scatter(const uint32_t* __restrict__ kin,
                                                               const uint32_t* __restrict__ vin,
-                                                              const uint32_t* __restrict__ vin2, KT* __restrict__ kout,
-                                                              uint32_t* __restrict__ vout, uint32_t* __restrict__ vout2,
+                                                              const uint32_t* __restrict__ vin2,
+                                                              uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                              uint32_t* __restrict__ vout2,
                                                               const uint32_t* __restrict__ count,
                                                               const int32_t* __restrict__ status, int shift,
                                                               int64_t nblk, const uint32_t* __restrict__ hist,
                                                               const uint32_t* __restrict__ digit_total) {
   constexpr int kWaves = kSortThreads / kWave;
+  __shared__ uint32_t s_gbase[kRadix];  // global position of this block's first element of each digit
+  __shared__ uint32_t s_lbase[kRadix];  // its position within the block's digit-ordered elements
   __shared__ uint32_t s_run[kRadix];
   __shared__ uint32_t s_cnt[kWaves][kRadix];
   __shared__ uint32_t s_pre[kWaves][kRadix];
   __shared__ uint32_t s_wave[kWaves];
+  __shared__ uint32_t s_k[kSortTile];
+  __shared__ uint32_t s_v[kSortTile];
+  __shared__ uint32_t s_v2[NV == 2 ? kSortTile : 1];
   const uint32_t K = effective_count(count, status);
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
   if (base >= K) return;  // uniform across the block
+  const int nvalid = (int)min((int64_t)kSortTile, (int64_t)K - base);
   const int t = threadIdx.x, lane = t & (kWave - 1), wave = t / kWave;
-  // digit bases: exclusive scan of the digit totals
-  uint32_t tot;
-  const uint32_t dbase = block_exclusive_scan_256(digit_total[t], &tot, s_wave);
-  s_run[t] = dbase + hist[(int64_t)t * nblk + blockIdx.x];
+  uint32_t key[kSortItems];
+  uint32_t val[kSortItems], val2[NV == 2 ? kSortItems : 1];
+  s_run[t] = 0;
 #pragma unroll
   for (int w = 0; w < kWaves; ++w) s_cnt[w][t] = 0;
-  KT key[kSortItems];
-  uint32_t val[kSortItems], val2[NV == 2 ? kSortItems : 1];
+  __syncthreads();
 #pragma unroll
   for (int k = 0; k < kSortItems; ++k) {
-    const int64_t i = base + k * kSortThreads + t;
-    if (i < K) {
-      key[k] = kin[i];
-      val[k] = vin[i];
-      if (NV == 2) val2[k] = vin2[i];
+    const int li = k * kSortThreads + t;
+    if (li < nvalid) {
+      key[k] = kin[base + li];
+      val[k] = vin[base + li];
+      if (NV == 2) val2[k] = vin2[base + li];
+      atomicAdd(&s_run[(key[k] >> shift) & (kRadix - 1)], 1u);  // the block's digit counts
     }
   }
+  __syncthreads();
+  uint32_t tot;
+  const uint32_t lb = block_exclusive_scan_256(s_run[t], &tot, s_wave);
+  const uint32_t dbase = block_exclusive_scan_256(digit_total[t], &tot, s_wave);
+  s_lbase[t] = lb;
+  s_gbase[t] = dbase + hist[(int64_t)t * nblk + blockIdx.x];
+  s_run[t] = lb;
   __syncthreads();
   const uint64_t lt_mask = (1ull << lane) - 1ull;
 #pragma unroll
   for (int k = 0; k < kSortItems; ++k) {
-    const int64_t i = base + k * kSortThreads + t;
-    const bool valid = i < K;
-    const uint32_t d = valid ? (uint32_t)(key[k] >> shift) & (kRadix - 1) : 0u;
+    const int li = k * kSortThreads + t;
+    const bool valid = li < nvalid;
+    const uint32_t d = valid ? (key[k] >> shift) & (kRadix - 1) : 0u;
     const uint64_t peers = match_digit(d, valid);
     const uint32_t rank = __popcll(peers & lt_mask);
     if (valid && rank == 0) s_cnt[wave][d] = __popcll(peers);
@@ -380,11 +396,20 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter(const KT* __restri
     }
     __syncthreads();
     if (valid) {
-      const uint32_t pos = s_pre[wave][d] + rank;
-      kout[pos] = key[k];
-      vout[pos] = val[k];
-      if (NV == 2) vout2[pos] = val2[k];
+      const uint32_t pos = s_pre[wave][d] + rank;  // within the block
+      s_k[pos] = key[k];
+      s_v[pos] = val[k];
+      if (NV == 2) s_v2[pos] = val2[k];
     }
+  }
+  __syncthreads();
+  for (int i = t; i < nvalid; i += kSortThreads) {
+    const uint32_t kk = s_k[i];
+    const uint32_t d = (kk >> shift) & (kRadix - 1);
+    const uint32_t pos = s_gbase[d] + ((uint32_t)i - s_lbase[d]);
+    kout[pos] = kk;
+    vout[pos] = s_v[i];
+    if (NV == 2) vout2[pos] = s_v2[i];
   }
 }
 
@@ -539,7 +564,7 @@ static void radix_sort(KT* k0, uint32_t* v0, uint32_t* u0, KT* k1, uint32_t* v1,
     hipLaunchKernelGGL((radix_hist<KT>), dim3((unsigned)nblk), dim3(kSortThreads), 0, s, kb[cur], count, status,
                        shift, nblk, w.hist);
     hipLaunchKernelGGL(radix_digit_scan, dim3(kRadix), dim3(256), 0, s, w.hist, nblk, w.digit_total);
-    hipLaunchKernelGGL((radix_scatter<KT, NV>), dim3((unsigned)nblk), dim3(kSortThreads), 0, s, kb[cur], vb[cur],
+    hipLaunchKernelGGL((radix_scatter<NV>), dim3((unsigned)nblk), dim3(kSortThreads), 0, s, kb[cur], vb[cur],
                        ub[cur], kb[cur ^ 1], vb[cur ^ 1], ub[cur ^ 1], count, status, shift, nblk, w.hist,
                        w.digit_total);
     cur ^= 1;

@@ -68,7 +68,7 @@ struct ProjectBwdArgs {
   const uint32_t* tiles_touched;   // [V*n]
   const uint32_t* offsets;         // [V*n] first emission position of each record
   const int32_t* status;
-  double* rec_geo;                 // [V*n][6] per-record sums of (u, v, A, B, C, o') gradients
+  float* rec_geo;                  // [V*n][6] per-record sums of (u, v, A, B, C, o') gradients
   float* rec_mu;                   // [V*n][4] per-record colour term of the mean gradient
   float* g_means;
   float* g_log_scales;

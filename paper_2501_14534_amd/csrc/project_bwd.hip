@@ -5,8 +5,7 @@
 //
 // Three kernels (no atomics):
 //   sums:     one thread per (view, Gaussian) record: its pairs' gradients
-//             summed in emission order (double); geometry sums kept in double,
-//             colour sums rounded to float (adjacent records' pairs are
+//             summed in emission order (double), rounded once to float (adjacent records' pairs are
 //             adjacent, so a wave reads one contiguous stretch);
 //   colour:   one thread per Gaussian: the SH chain (diffuse colour, bands
 //             1..3, band-mask logits, and the view-direction term of the
@@ -86,9 +85,10 @@ __device__ __forceinline__ float acc_mul_add(float t, float a, float b) {
   return t + p;
 }
 
-// Per record: sums of its pairs' 9 gradients in emission order.  rec_geo gets
-// (u, v, A, B, C, o') in double, rec_mu[0..2] the colour sums in float (the
-// colour kernel replaces them with the colour term of the mean gradient).
+// Per record: sums of its pairs' 9 gradients in emission order, accumulated in
+// double and rounded once to float: rec_geo gets (u, v, A, B, C, o'),
+// rec_mu[0..2] the colour sums (the colour kernel replaces them with the
+// colour term of the mean gradient).
 __global__ __launch_bounds__(256) void record_sum_kernel(ProjectBwdArgs b, int64_t nrec) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nrec) return;
@@ -100,9 +100,9 @@ __global__ __launch_bounds__(256) void record_sum_kernel(ProjectBwdArgs b, int64
   for (uint32_t k = 0; k < cntp; ++k)
 #pragma unroll
     for (int c = 0; c < GS_GRAD_FLOATS; ++c) gsum[c] += (double)gp[(size_t)k * GS_GRAD_FLOATS + c];
-  double* geo = b.rec_geo + r * 6;
+  float* geo = b.rec_geo + r * 6;
 #pragma unroll
-  for (int c = 0; c < 6; ++c) geo[c] = gsum[c];
+  for (int c = 0; c < 6; ++c) geo[c] = (float)gsum[c];
   if (b.g_mean2d) {
     const int64_t n = b.p.n, v = r / n, i = r - v * n;
     b.g_mean2d[(v * 2 + 0) * n + i] += (float)gsum[0];
@@ -294,7 +294,7 @@ __global__ __launch_bounds__(256) void project_bwd_geom_kernel(ProjectBwdArgs b,
   for (int v = 0; v < V; ++v) {
     const size_t r = (size_t)v * n + i;
     if (b.tiles_touched[r] == 0) continue;
-    const double* geo = b.rec_geo + r * 6;
+    const float* geo = b.rec_geo + r * 6;
     const float* cmu = b.rec_mu + r * 4;
     const double gu = geo[0], gv = geo[1], gA = geo[2], gB = geo[3], gC = geo[4], go = geo[5];
     const float cm0 = cmu[0], cm1 = cmu[1], cm2 = cmu[2];
