@@ -47,7 +47,7 @@ enum {
 #define GS_MAX_VIEWS 16       /* views per call */
 #define GS_SPLAT_FLOATS 12    /* floats per projected record */
 #define GS_GRAD_FLOATS 9      /* floats per record gradient */
-#define GS_MAX_BATCH 256      /* largest per-tile staging batch */
+#define GS_MAX_BATCH 1024     /* largest per-tile staging batch (the backward stages at most 512 / waves) */
 
 /* Gaussian parameters, raw (before activations).  Sec. 3.1: mean, scale,
  * rotation quaternion, opacity, diffuse colour and SH coefficients; Sec. 3.2.5:

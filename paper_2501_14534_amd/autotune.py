@@ -19,7 +19,7 @@ CACHE = os.path.join(HERE, "autotune_cache.json")
 
 # (tile_w, tile_h, batch_depth, pixels_per_thread, subtile_cull)
 CANDIDATES: List[Tuple[int, int, int, int, int]] = [
-    (16, 16, 256, 1, 0), (16, 16, 256, 1, 1), (16, 16, 128, 1, 1), (16, 16, 64, 1, 1),
+    (16, 16, 256, 1, 0), (16, 16, 256, 1, 1), (16, 16, 512, 1, 1), (16, 16, 1024, 1, 1), (16, 16, 128, 1, 1), (16, 16, 64, 1, 1),
     (16, 16, 256, 2, 1), (16, 16, 128, 2, 1), (16, 16, 64, 2, 1),
     (16, 16, 256, 4, 1), (16, 16, 128, 4, 1), (16, 16, 64, 4, 1), (16, 16, 32, 4, 1),
     (8, 8, 64, 1, 1), (8, 8, 32, 1, 1), (16, 8, 128, 1, 1), (16, 8, 64, 2, 1), (32, 8, 256, 1, 1),

@@ -75,6 +75,25 @@ struct Box {
 // (may still composite or receive gradient), the same value in every lane.
 // Culling against it instead of the wave's whole sub-tile drops the records
 // that can only reach pixels that have already stopped.
+// Min (or max) over the 64 lanes, returned in every lane: row shifts by 1, 2,
+// 4, 8 leave each 16-lane row's result in its lane 15, row broadcasts 15 and
+// 31 fold the rows into lane 63 (lanes without a source see the identity).
+template <bool MAX>
+__device__ __forceinline__ float wave_minmax(float v) {
+  const int id = __builtin_bit_cast(int, MAX ? -__builtin_inff() : __builtin_inff());
+  auto step = [&](float x, float y) { return MAX ? fmaxf(x, y) : fminf(x, y); };
+#define GS_DPP_STEP(ctrl, rmask) \
+  v = step(v, __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(id, __builtin_bit_cast(int, v), ctrl, rmask, 0xf, false)))
+  GS_DPP_STEP(0x111, 0xf);
+  GS_DPP_STEP(0x112, 0xf);
+  GS_DPP_STEP(0x114, 0xf);
+  GS_DPP_STEP(0x118, 0xf);
+  GS_DPP_STEP(0x142, 0xa);
+  GS_DPP_STEP(0x143, 0xc);
+#undef GS_DPP_STEP
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), kWave - 1));
+}
+
 template <int PPT>
 __device__ __forceinline__ Box live_box(const float (&px)[PPT], const float (&py)[PPT], const bool (&live)[PPT]) {
   Box b{__builtin_inff(), -__builtin_inff(), __builtin_inff(), -__builtin_inff()};
@@ -86,13 +105,10 @@ __device__ __forceinline__ Box live_box(const float (&px)[PPT], const float (&py
       b.y0 = fminf(b.y0, py[p]);
       b.y1 = fmaxf(b.y1, py[p]);
     }
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    b.x0 = fminf(b.x0, __shfl_xor(b.x0, o, kWave));
-    b.x1 = fmaxf(b.x1, __shfl_xor(b.x1, o, kWave));
-    b.y0 = fminf(b.y0, __shfl_xor(b.y0, o, kWave));
-    b.y1 = fmaxf(b.y1, __shfl_xor(b.y1, o, kWave));
-  }
+  b.x0 = wave_minmax<false>(b.x0);
+  b.x1 = wave_minmax<true>(b.x1);
+  b.y0 = wave_minmax<false>(b.y0);
+  b.y1 = wave_minmax<true>(b.y1);
   return b;
 }
 
@@ -590,15 +606,8 @@ __global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs a, ViewTable
     for (int c = nchunks - 1; c >= 0; --c) {
       uint64_t m = chunk_bits<CULL>(s_mask, c, cnt, wave, lane);
       if (m == 0) continue;
-      int bit = 63 - __builtin_clzll(m);  // back to front
-      m &= ~(1ull << bit);
-      int j = c * kWave + bit;
-      float4 ra = s_a[j], rb = s_b[j], rc = s_c[j];
-      for (;;) {
-        const bool more = m != 0;
-        const int nbit = more ? 63 - __builtin_clzll(m) : bit;
-        const int jn = c * kWave + nbit;
-        const float4 ran = s_a[jn], rbn = s_b[jn], rcn = s_c[jn];  // next entry, loaded ahead
+      // one staged record: per-pixel partials, then the wave's sums into LDS
+      auto grad = [&](int j, const float4& ra, const float4& rb, const float4& rc) {
         const int jr = (int)(bs - tc.start) + j;                   // index within the tile's list
         float x[GS_GRAD_FLOATS] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // u v A B C o' r g b
         bool any = false;
@@ -630,13 +639,24 @@ __global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs a, ViewTable
           const float v = reduce_scatter9(x, b2, b3);
           if (writer) s_part[(wave * batch + j) * GS_GRAD_FLOATS + my_e] = v;
         }
-        if (!more) break;
-        m &= ~(1ull << nbit);
-        bit = nbit;
-        j = jn;
-        ra = ran;
-        rb = rbn;
-        rc = rcn;
+      };
+      // two register sets in turn: the next record loads while this one is reduced
+      int j0 = c * kWave + (63 - __builtin_clzll(m));  // back to front
+      m &= ~(1ull << (j0 - c * kWave));
+      float4 a0 = s_a[j0], b0 = s_b[j0], c0 = s_c[j0];
+      for (;;) {
+        const bool more1 = m != 0;
+        const int j1 = more1 ? c * kWave + (63 - __builtin_clzll(m)) : j0;
+        m &= ~(1ull << (j1 - c * kWave));
+        const float4 a1 = s_a[j1], b1 = s_b[j1], c1 = s_c[j1];
+        grad(j0, a0, b0, c0);
+        if (!more1) break;
+        const bool more2 = m != 0;
+        j0 = more2 ? c * kWave + (63 - __builtin_clzll(m)) : j1;
+        m &= ~(1ull << (j0 - c * kWave));
+        a0 = s_a[j0], b0 = s_b[j0], c0 = s_c[j0];
+        grad(j1, a1, b1, c1);
+        if (!more2) break;
       }
     }
     __syncthreads();

@@ -17,7 +17,7 @@ GS_OK, GS_E_INVALID, GS_E_CAPACITY, GS_E_HIP, GS_E_UNSUPPORTED = 0, -1, -2, -3, 
 MAX_VIEWS = 16
 SPLAT_FLOATS = 12
 GRAD_FLOATS = 9
-MAX_BATCH = 256
+MAX_BATCH = 1024
 
 EXPORTS = ("gs_view_sizes", "gs_workspace_size", "gs_project", "gs_bin_sort", "gs_render_fwd", "gs_render_bwd",
            "gs_blend_bwd", "gs_project_bwd", "gs_strerror")

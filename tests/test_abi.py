@@ -71,7 +71,7 @@ def _bad_opts(wl):
     yield dataclasses.replace(wl.opts, pixels_per_thread=3)
     yield dataclasses.replace(wl.opts, tile_w=32, tile_h=32, pixels_per_thread=1)  # 1024 threads
     yield dataclasses.replace(wl.opts, batch_depth=0)
-    yield dataclasses.replace(wl.opts, batch_depth=257)
+    yield dataclasses.replace(wl.opts, batch_depth=1025)
     yield dataclasses.replace(wl.opts, lowpass=-1.0)
     yield dataclasses.replace(wl.opts, tan_clamp=0.0)
     yield dataclasses.replace(wl.opts, bwd_chunk=100)                # not a power of two
