@@ -231,6 +231,28 @@ def main():
     roof["ms_per_launch"] = round(stage_ms[dom], 4)
     roof["traffic"] = load_traffic(single[dom], workload, src_hash)
 
+    # ---------------- L1 + D-SSIM loss (Eq. 7) on the rendered views ----------------
+    from paper_2501_14534_amd.photometric import PhotometricLoss
+    pl = PhotometricLoss(wl.cams)
+    dl_buf = torch.empty_like(r.image)
+    for _ in range(3):
+        pl(r.image, target, out=dl_buf)
+    lev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    nl = max(5, args.steps)
+    lev[0].record(stream)
+    for _ in range(nl):
+        pl(r.image, target, out=dl_buf)
+    lev[1].record(stream)
+    torch.cuda.synchronize()
+    loss_ms = lev[0].elapsed_time(lev[1]) / nl
+    elems = 3 * pixels
+    loss_bytes = 44.0 * elems  # fwd: x, y in, 3 partial maps out; bwd: maps, x, y in, gradient out
+    l1_dssim = dict(ms_per_call=round(loss_ms, 4), loss=round(float(pl.loss[-1]), 6),
+                    roofline=dict(bound="hbm", achieved=round(loss_bytes / (loss_ms * 1e-3) / 1e9, 1),
+                                  peak=PEAK_HBM_GBS, unit="GB/s",
+                                  frac=round(loss_bytes / (loss_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 5)),
+                    kernels="ssim_fwd_kernel + ssim_bwd_kernel + loss_reduce_kernel + loss_mean_kernel")
+
     # ---------------- FP64 oracle on the host cores (bounded sample) ----------------
     cpu = None
     if not args.no_cpu_baseline:
@@ -262,6 +284,7 @@ def main():
         "useful_pairs": useful_pairs,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "l1_dssim": l1_dssim,
         "kernel_source": src_hash,
     }
     print(json.dumps(out), flush=True)

@@ -239,6 +239,22 @@ int gs_project_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t V, cons
                    void* ws, size_t ws_bytes, gs_stream_t stream);
 
 /* Static description of a return code. */
+/* Photometric loss of Eq. 7, its L1 and D-SSIM terms, over the V views of a
+ * rendered image (layout of gs_render_fwd's image), and its gradient:
+ *   L_v = (1 - lambda) mean|x - y| + lambda (1 - mean SSIM),  L = mean_v L_v
+ * SSIM per colour plane with the 11 x 11 Gaussian window of standard
+ * deviation 1.5 applied as two 1-D passes (Sec. 3.2.5), zero padding,
+ * C1 = 0.01^2, C2 = 0.03^2; d|t|/dt = sign(t) (0 at 0).
+ * image, target: device, [sum_v 3 H_v W_v] planar per view, views concatenated.
+ * loss: device [V + 1] or NULL: the V per-view losses, then their mean.
+ * dL_dimage: device, image layout, or NULL: WRITES dL/dimage of the mean.
+ * Only the cameras' width and height are read.  lambda_ssim in [0, 1].
+ * ws_bytes >= gs_loss_workspace_size(cams, V).  Deterministic (no atomics). */
+size_t gs_loss_workspace_size(const gs_camera* cams, int32_t V);
+int gs_loss_l1_dssim(const float* image, const float* target, const gs_camera* cams, int32_t V,
+                     float lambda_ssim, float* loss, float* dL_dimage, void* ws, size_t ws_bytes,
+                     gs_stream_t stream);
+
 const char* gs_strerror(int code);
 
 #ifdef __cplusplus

@@ -379,4 +379,73 @@ int gs_project_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t V, cons
                                      vt, g->sh_degree, (hipStream_t)stream));
 }
 
+// ---------------------------------------------------------------------------
+// Photometric loss (Eq. 7, L1 and D-SSIM terms)
+
+static bool loss_views(const gs_camera* cams, int32_t V, LossViews* lv, int64_t* total_px) {
+  if (!cams || V < 1 || V > GS_MAX_VIEWS) return false;
+  std::memset(lv, 0, sizeof(*lv));
+  int64_t po = 0, bo = 0;
+  for (int v = 0; v < V; ++v) {
+    const int W = cams[v].width, H = cams[v].height;
+    if (W <= 0 || H <= 0) return false;
+    LossView& q = lv->v[v];
+    q.W = W, q.H = H;
+    q.TX = (W + 15) / 16, q.TY = (H + 15) / 16;
+    q.pix_off = po;
+    q.block_off = (int32_t)bo;
+    po += (int64_t)W * H;
+    bo += 3ll * q.TX * q.TY;
+    if (bo >= (1ll << 31)) return false;
+  }
+  lv->nviews = V;
+  lv->total_blocks = (int32_t)bo;
+  // the window's 1-D factor: exp(-k^2 / (2 * 1.5^2)), k = -5..5, normalised
+  double g[11], sum = 0.0;
+  for (int k = 0; k < 11; ++k) sum += (g[k] = std::exp(-(double)((k - 5) * (k - 5)) / (2.0 * 1.5 * 1.5)));
+  for (int k = 0; k < 11; ++k) lv->g[k] = (float)(g[k] / sum);
+  if (total_px) *total_px = po;
+  return true;
+}
+
+struct LossWs {
+  float* dmap;
+  float* bsum;
+  double* per_view;
+  size_t bytes;
+};
+
+static LossWs loss_ws(const LossViews& lv, int64_t total_px, void* ws) {
+  LossWs w{};
+  char* b = (char*)ws;
+  size_t o = 0;
+  w.dmap = (float*)(b + o), o += align256(sizeof(float) * 9 * (size_t)total_px);
+  w.bsum = (float*)(b + o), o += align256(sizeof(float) * 2 * (size_t)lv.total_blocks);
+  w.per_view = (double*)(b + o), o += align256(sizeof(double) * GS_MAX_VIEWS);
+  w.bytes = o;
+  return w;
+}
+
+size_t gs_loss_workspace_size(const gs_camera* cams, int32_t V) {
+  LossViews lv;
+  int64_t px = 0;
+  if (!loss_views(cams, V, &lv, &px)) return 0;
+  return loss_ws(lv, px, nullptr).bytes;
+}
+
+int gs_loss_l1_dssim(const float* image, const float* target, const gs_camera* cams, int32_t V, float lambda_ssim,
+                     float* loss, float* dL_dimage, void* ws, size_t ws_bytes, gs_stream_t stream) {
+  LossViews lv;
+  int64_t px = 0;
+  if (!loss_views(cams, V, &lv, &px)) return GS_E_INVALID;
+  if (!image || !target || !std::isfinite(lambda_ssim) || lambda_ssim < 0.0f || lambda_ssim > 1.0f)
+    return GS_E_INVALID;
+  const LossWs w = loss_ws(lv, px, ws);
+  if (!ws || ws_bytes < w.bytes) return GS_E_INVALID;
+  const int d = device_ok();
+  if (d != GS_OK) return d;
+  return launched(launch_loss(lv, image, target, lambda_ssim, loss, dL_dimage, w.dmap, w.bsum, w.per_view,
+                              (hipStream_t)stream));
+}
+
 }  // extern "C"

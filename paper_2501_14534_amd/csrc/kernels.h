@@ -81,6 +81,23 @@ struct ProjectBwdArgs {
   float* g_mean2d;
 };
 
+// Views of a loss call: per view its size, 16 x 16 tile grid, pixel offset
+// (views concatenated, each [3][H][W]) and first workgroup; the window taps.
+struct LossView {
+  int32_t W, H, TX, TY;
+  int64_t pix_off;
+  int32_t block_off;
+};
+struct LossViews {
+  LossView v[GS_MAX_VIEWS];
+  int32_t nviews;
+  int32_t total_blocks;
+  float g[11];  // normalised Gaussian taps of the 11 x 11 window's 1-D factor
+};
+
+hipError_t launch_loss(const LossViews& lv, const float* image, const float* target, float lambda, float* loss,
+                       float* dL, float* dmap, float* bsum, double* per_view, hipStream_t s);
+
 // Workspace carve-up of gs_bin_sort / gs_render_bwd.
 struct SortPlan {
   int64_t nrec;             // V * n

@@ -20,7 +20,7 @@ GRAD_FLOATS = 9
 MAX_BATCH = 1024
 
 EXPORTS = ("gs_view_sizes", "gs_workspace_size", "gs_project", "gs_bin_sort", "gs_render_fwd", "gs_render_bwd",
-           "gs_blend_bwd", "gs_project_bwd", "gs_strerror")
+           "gs_blend_bwd", "gs_project_bwd", "gs_loss_workspace_size", "gs_loss_l1_dssim", "gs_strerror")
 
 vp = C.c_void_p
 
@@ -94,6 +94,10 @@ def load():
     L.gs_project_bwd.argtypes = [P(GsGaussians), P(GsCamera), C.c_int32, P(GsOpts), P(GsProjected), P(GsBinning),
                                  vp, P(GsGrads), vp, C.c_size_t, vp]
     L.gs_project_bwd.restype = C.c_int
+    L.gs_loss_workspace_size.argtypes = [P(GsCamera), C.c_int32]
+    L.gs_loss_workspace_size.restype = C.c_size_t
+    L.gs_loss_l1_dssim.argtypes = [vp, vp, P(GsCamera), C.c_int32, C.c_float, vp, vp, vp, C.c_size_t, vp]
+    L.gs_loss_l1_dssim.restype = C.c_int
     L.gs_strerror.argtypes = [C.c_int]
     L.gs_strerror.restype = C.c_char_p
     _lib = L
@@ -181,3 +185,12 @@ def blend_bwd(cams_arr, V, n, opts_s, proj, bins, T_final, last, dL_dimage, grad
 def project_bwd(g, cams_arr, V, opts_s, proj, bins, grad_pair, grads, ws, ws_bytes, stream) -> int:
     return load().gs_project_bwd(C.byref(g), cams_arr, V, C.byref(opts_s), C.byref(proj), C.byref(bins), grad_pair,
                                  C.byref(grads), ws, ws_bytes, stream)
+
+
+def loss_workspace_size(cams_arr, V) -> int:
+    return int(load().gs_loss_workspace_size(cams_arr, V))
+
+
+def loss_l1_dssim(image, target, cams_arr, V, lambda_ssim, loss, dL_dimage, ws, ws_bytes, stream) -> int:
+    return load().gs_loss_l1_dssim(image, target, cams_arr, V, float(lambda_ssim), loss, dL_dimage, ws, ws_bytes,
+                                   stream)

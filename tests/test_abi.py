@@ -143,3 +143,22 @@ def test_other_entry_points_reject_null_buffers(lib):
                             4096, 1 << 30, None) == gs.GS_E_INVALID
     assert lib.gs_blend_bwd(cams, 1, 64, C.byref(o), C.byref(proj), C.byref(bins), 4096, 4096, 4096, 4096,
                             None, 1 << 30, None) == gs.GS_E_INVALID  # workspace missing
+
+
+def test_loss_entry_points_validate_on_the_host(lib):
+    wl = scenes.config(4, n=10)
+    cams = gs.cameras(wl.cams)
+    V = len(wl.cams)
+    need = gs.loss_workspace_size(cams, V)
+    assert need >= 9 * 4 * wl.pixels  # three partial-derivative maps per colour plane
+    assert gs.loss_workspace_size(cams, 0) == 0
+    bad = gs.cameras(wl.cams[:1])
+    bad[0].width = 0
+    assert gs.loss_workspace_size(bad, 1) == 0
+    f = lib.gs_loss_l1_dssim
+    assert f(4096, 4096, cams, V, C.c_float(1.5), 4096, 4096, 4096, need, None) == gs.GS_E_INVALID  # lambda > 1
+    assert f(4096, 4096, cams, V, C.c_float(-0.1), 4096, 4096, 4096, need, None) == gs.GS_E_INVALID
+    assert f(None, 4096, cams, V, C.c_float(0.2), 4096, 4096, 4096, need, None) == gs.GS_E_INVALID
+    assert f(4096, None, cams, V, C.c_float(0.2), 4096, 4096, 4096, need, None) == gs.GS_E_INVALID
+    assert f(4096, 4096, cams, V, C.c_float(0.2), 4096, 4096, 4096, need - 1, None) == gs.GS_E_INVALID
+    assert f(4096, 4096, cams, V, C.c_float(0.2), 4096, 4096, None, need, None) == gs.GS_E_INVALID
