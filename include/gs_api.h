@@ -255,6 +255,18 @@ int gs_loss_l1_dssim(const float* image, const float* target, const gs_camera* c
                      float lambda_ssim, float* loss, float* dL_dimage, void* ws, size_t ws_bytes,
                      gs_stream_t stream);
 
+/* Mask terms of Eq. 7: lambda_m L_m + lambda_sh L_sh with
+ *   L_m  = mean over the n Gaussians of sigmoid(mask_logit)        (soft volume mask, Eq. 3)
+ *   L_sh = mean over the Gaussians of sum_l w_l sigmoid(sh_mask_logit_l), l = 1..sh_degree,
+ *          w_l = (2l + 1) / sum_l' (2l' + 1)                       (coefficient-weighted, Sec. 3.2.3)
+ * A NULL mask array contributes nothing.  loss: device [1] or NULL (written).
+ * grads->mask_logits / sh_mask_logits (if grads and they are non-NULL) are
+ * ACCUMULATED (+=).  Only g's mask arrays, n and sh_degree are read.
+ * ws_bytes >= gs_mask_loss_workspace_size(n).  Deterministic (no atomics). */
+size_t gs_mask_loss_workspace_size(int64_t n);
+int gs_mask_loss(const gs_gaussians* g, float lambda_m, float lambda_sh, float* loss, gs_grads* grads, void* ws,
+                 size_t ws_bytes, gs_stream_t stream);
+
 const char* gs_strerror(int code);
 
 #ifdef __cplusplus

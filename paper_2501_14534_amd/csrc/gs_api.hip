@@ -448,4 +448,22 @@ int gs_loss_l1_dssim(const float* image, const float* target, const gs_camera* c
                               (hipStream_t)stream));
 }
 
+size_t gs_mask_loss_workspace_size(int64_t n) {
+  if (n < 0) return 0;
+  return align256(sizeof(float) * 2 * (size_t)((n + 255) / 256)) + 256;
+}
+
+int gs_mask_loss(const gs_gaussians* g, float lambda_m, float lambda_sh, float* loss, gs_grads* grads, void* ws,
+                 size_t ws_bytes, gs_stream_t stream) {
+  if (!g || g->n < 0 || g->sh_degree < 0 || g->sh_degree > 3) return GS_E_INVALID;
+  if (!std::isfinite(lambda_m) || !std::isfinite(lambda_sh)) return GS_E_INVALID;
+  if (g->n > 0 && (!ws || ws_bytes < gs_mask_loss_workspace_size(g->n))) return GS_E_INVALID;
+  const int d = device_ok();
+  if (d != GS_OK) return d;
+  float* gm = grads ? grads->mask_logits : nullptr;
+  float* gsh = grads ? grads->sh_mask_logits : nullptr;
+  return launched(launch_mask_loss(g->mask_logits, g->sh_mask_logits, g->n, g->sh_degree, lambda_m, lambda_sh, gm,
+                                   gsh, loss, (float*)ws, (hipStream_t)stream));
+}
+
 }  // extern "C"

@@ -98,6 +98,9 @@ struct LossViews {
 hipError_t launch_loss(const LossViews& lv, const float* image, const float* target, float lambda, float* loss,
                        float* dL, float* dmap, float* bsum, double* per_view, hipStream_t s);
 
+hipError_t launch_mask_loss(const float* m, const float* msh, int64_t n, int deg, float lam_m, float lam_sh,
+                            float* gm, float* gsh, float* loss, float* bsum, hipStream_t s);
+
 // Workspace carve-up of gs_bin_sort / gs_render_bwd.
 struct SortPlan {
   int64_t nrec;             // V * n

@@ -259,3 +259,82 @@ hipError_t launch_loss(const LossViews& lv, const float* image, const float* tar
 }
 
 }  // namespace gs
+
+namespace gs {
+
+// Mask terms of Eq. 7: lambda_m mean sigmoid(m) + lambda_sh mean sum_l w_l
+// sigmoid(m^l), w_l = (2l + 1) / sum (2l' + 1) over bands 1..deg (each band
+// weighted by its coefficient count, Sec. 3.2.3).  One thread per Gaussian:
+// gradients accumulated (+=) into the mask-logit gradients; per-workgroup sums
+// in a fixed order; a one-workgroup kernel adds them in double.
+__global__ __launch_bounds__(256) void mask_loss_kernel(const float* __restrict__ m, const float* __restrict__ msh,
+                                                        int64_t n, int deg, float lam_m, float lam_sh,
+                                                        float* __restrict__ gm, float* __restrict__ gsh,
+                                                        float* __restrict__ bsum) {
+  __shared__ float s_red[2][4];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  float a = 0.f, b = 0.f;
+  if (i < n) {
+    const float inv_n = 1.0f / (float)n;
+    if (m) {
+      const float s = 1.0f / (1.0f + __expf(-m[i]));
+      a = s;
+      if (gm) gm[i] += lam_m * s * (1.0f - s) * inv_n;
+    }
+    if (msh && deg > 0) {
+      const float wsum = (float)(deg * (deg + 2));  // sum_{l=1..deg} (2l + 1)
+      for (int l = 1; l <= deg; ++l) {
+        const float w = (float)(2 * l + 1) / wsum;
+        const float s = 1.0f / (1.0f + __expf(-msh[(int64_t)(l - 1) * n + i]));
+        b += w * s;
+        if (gsh) gsh[(int64_t)(l - 1) * n + i] += lam_sh * w * s * (1.0f - s) * inv_n;
+      }
+    }
+  }
+  a = wave_sum_lane63(a);
+  b = wave_sum_lane63(b);
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  if (lane == kWave - 1) {
+    s_red[0][wave] = a;
+    s_red[1][wave] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    bsum[2 * blockIdx.x + 0] = ((s_red[0][0] + s_red[0][1]) + s_red[0][2]) + s_red[0][3];
+    bsum[2 * blockIdx.x + 1] = ((s_red[1][0] + s_red[1][1]) + s_red[1][2]) + s_red[1][3];
+  }
+}
+
+__global__ __launch_bounds__(256) void mask_loss_reduce_kernel(const float* __restrict__ bsum, int nb, int64_t n,
+                                                               float lam_m, float lam_sh, float* __restrict__ loss) {
+  __shared__ double s_a[256], s_b[256];
+  const int t = threadIdx.x;
+  double a = 0.0, b = 0.0;
+  for (int k = t; k < nb; k += 256) {
+    a += (double)bsum[2 * k + 0];
+    b += (double)bsum[2 * k + 1];
+  }
+  s_a[t] = a;
+  s_b[t] = b;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) {
+      s_a[t] += s_a[t + o];
+      s_b[t] += s_b[t + o];
+    }
+    __syncthreads();
+  }
+  if (t == 0) loss[0] = (float)((double)lam_m * s_a[0] / (double)n + (double)lam_sh * s_b[0] / (double)n);
+}
+
+hipError_t launch_mask_loss(const float* m, const float* msh, int64_t n, int deg, float lam_m, float lam_sh,
+                            float* gm, float* gsh, float* loss, float* bsum, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int nb = (int)((n + 255) / 256);
+  hipLaunchKernelGGL(mask_loss_kernel, dim3((unsigned)nb), dim3(256), 0, s, m, msh, n, deg, lam_m, lam_sh, gm, gsh,
+                     bsum);
+  if (loss) hipLaunchKernelGGL(mask_loss_reduce_kernel, dim3(1), dim3(256), 0, s, bsum, nb, n, lam_m, lam_sh, loss);
+  return hipGetLastError();
+}
+
+}  // namespace gs

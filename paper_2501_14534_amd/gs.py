@@ -20,7 +20,8 @@ GRAD_FLOATS = 9
 MAX_BATCH = 1024
 
 EXPORTS = ("gs_view_sizes", "gs_workspace_size", "gs_project", "gs_bin_sort", "gs_render_fwd", "gs_render_bwd",
-           "gs_blend_bwd", "gs_project_bwd", "gs_loss_workspace_size", "gs_loss_l1_dssim", "gs_strerror")
+           "gs_blend_bwd", "gs_project_bwd", "gs_loss_workspace_size", "gs_loss_l1_dssim", "gs_mask_loss_workspace_size", "gs_mask_loss",
+           "gs_strerror")
 
 vp = C.c_void_p
 
@@ -98,6 +99,10 @@ def load():
     L.gs_loss_workspace_size.restype = C.c_size_t
     L.gs_loss_l1_dssim.argtypes = [vp, vp, P(GsCamera), C.c_int32, C.c_float, vp, vp, vp, C.c_size_t, vp]
     L.gs_loss_l1_dssim.restype = C.c_int
+    L.gs_mask_loss_workspace_size.argtypes = [C.c_int64]
+    L.gs_mask_loss_workspace_size.restype = C.c_size_t
+    L.gs_mask_loss.argtypes = [P(GsGaussians), C.c_float, C.c_float, vp, P(GsGrads), vp, C.c_size_t, vp]
+    L.gs_mask_loss.restype = C.c_int
     L.gs_strerror.argtypes = [C.c_int]
     L.gs_strerror.restype = C.c_char_p
     _lib = L
@@ -194,3 +199,12 @@ def loss_workspace_size(cams_arr, V) -> int:
 def loss_l1_dssim(image, target, cams_arr, V, lambda_ssim, loss, dL_dimage, ws, ws_bytes, stream) -> int:
     return load().gs_loss_l1_dssim(image, target, cams_arr, V, float(lambda_ssim), loss, dL_dimage, ws, ws_bytes,
                                    stream)
+
+
+def mask_loss_workspace_size(n) -> int:
+    return int(load().gs_mask_loss_workspace_size(int(n)))
+
+
+def mask_loss(g, lambda_m, lambda_sh, loss, grads, ws, ws_bytes, stream) -> int:
+    return load().gs_mask_loss(C.byref(g), float(lambda_m), float(lambda_sh), loss,
+                               C.byref(grads) if grads is not None else None, ws, ws_bytes, stream)

@@ -230,56 +230,105 @@ def l2_loss_grad(image: torch.Tensor, target: torch.Tensor, views: int, out: tor
 
 
 class Step:
-    """One fwd+bwd step of a Rasterizer (project, bin/sort, composite, L2 gradient,
-    backward), run eagerly or replayed from a captured HIP graph.
+    """One fwd+bwd step of a Rasterizer (project, bin/sort, composite, loss
+    gradient, backward), run eagerly or replayed from a captured HIP graph.
+
+    loss: "l2" (mean over views of the mean squared error; the benchmark's
+    loss) or "l1_dssim" (the photometric terms of Eq. 7, gs_loss_l1_dssim).
+    mask_loss: (lambda_m, lambda_sh) adds the mask terms of Eq. 7
+    (gs_mask_loss), or None.  sh_rest_every: k > 1 computes the SH bands 1..3
+    gradients only on every k-th step (the others skip writing them), the
+    sparse SH update the paper adopts (Sec. 3.2.5); two graphs are captured and
+    replayed in turn.
 
     The binning capacity is fixed while a graph exists; `run()` reads the
     device status after the step and, on overflow, grows the buffers,
     re-captures and runs again."""
 
     def __init__(self, rast: Rasterizer, params, target_flat: torch.Tensor, graph: bool = True,
-                 loss_views: Optional[int] = None):
+                 loss_views: Optional[int] = None, loss: str = "l2", mask_loss=None, sh_rest_every: int = 1):
         self.rast = rast
         self.params = params
         self.target = target_flat
         self.dL = torch.zeros_like(rast.image)
         self.grads = rast.zero_grads(params)
         self.graph_enabled = graph
-        self.graph = None
+        self.graphs = {}
         self.pix = [c.width * c.height for c in rast.cams]
         # number of views the loss averages over (a per-view step of a batch uses the batch's count)
         self.loss_views = rast.V if loss_views is None else int(loss_views)
+        if loss not in ("l2", "l1_dssim"):
+            raise ValueError(loss)
+        self.loss_kind = loss
+        self.ploss = None
+        if loss == "l1_dssim":
+            from .photometric import PhotometricLoss
+            if self.loss_views != rast.V:
+                raise ValueError("the L1 + D-SSIM step averages over the rasterizer's own views")
+            self.ploss = PhotometricLoss(rast.cams)
+        self.mask_loss = mask_loss
+        self.mask_value = torch.zeros(1, dtype=torch.float32, device=rast.device)
+        self.mask_ws = None
+        if mask_loss is not None:
+            b = gs.mask_loss_workspace_size(rast.n)
+            self.mask_ws = torch.zeros(max(b, 1), dtype=torch.uint8, device=rast.device)
+        self.sh_rest_every = max(1, int(sh_rest_every))
+        self.step_index = 0
 
-    def _body(self):
+    @property
+    def graph(self):
+        return self.graphs.get(True)
+
+    @graph.setter
+    def graph(self, g):
+        if g is None:
+            self.graphs = {}
+        else:
+            self.graphs[True] = g
+
+    def _body(self, with_sh_rest: bool = True):
         r = self.rast
         r.project(self.params)
         r.bin_sort()
         r.render_fwd()
-        l2_loss_grad(r.image, self.target, self.loss_views, self.dL, self.pix)
+        if self.ploss is not None:
+            self.ploss(r.image, self.target, out=self.dL)
+        else:
+            l2_loss_grad(r.image, self.target, self.loss_views, self.dL, self.pix)
         for g in self.grads.values():
             g.zero_()
-        r.render_bwd(self.params, self.dL, self.grads)
+        grads = self.grads
+        if not with_sh_rest:
+            grads = {k: v for k, v in self.grads.items() if k != "sh_rest"}
+        r.render_bwd(self.params, self.dL, grads)
+        if self.mask_loss is not None:
+            g = r.gaussians(self.params)
+            gr = gs.GsGrads(*[gs.ptr(grads.get(k)) for k in PARAM_NAMES], None)
+            gs.check(gs.mask_loss(g, self.mask_loss[0], self.mask_loss[1], gs.ptr(self.mask_value), gr,
+                                  gs.ptr(self.mask_ws), self.mask_ws.numel(), _stream()), "gs_mask_loss")
 
-    def capture(self):
+    def capture(self, with_sh_rest: bool = True):
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(s):
-            self._body()  # warm-up on the side stream before capture
+            self._body(with_sh_rest)  # warm-up on the side stream before capture
         torch.cuda.current_stream().wait_stream(s)
         torch.cuda.synchronize()
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
-            self._body()
-        self.graph = g
+            self._body(with_sh_rest)
+        self.graphs[with_sh_rest] = g
 
     def launch(self):
         """Enqueue one step (no host synchronisation)."""
+        with_sh_rest = self.step_index % self.sh_rest_every == 0
+        self.step_index += 1
         if self.graph_enabled:
-            if self.graph is None:
-                self.capture()
-            self.graph.replay()
+            if with_sh_rest not in self.graphs:
+                self.capture(with_sh_rest)
+            self.graphs[with_sh_rest].replay()
         else:
-            self._body()
+            self._body(with_sh_rest)
 
     def run(self, headroom: float = 1.25):
         """One step with the capacity check (synchronises): grows the binning
