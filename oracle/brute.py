@@ -137,7 +137,8 @@ def project(p, scene, cam, opts):
 
 
 def render_view(p, scene, cam, opts):
-    """Image [3,H,W], T_final [H,W] and the number of composited Gaussians per pixel."""
+    """Image [3,H,W], T_final [H,W], the number of composited Gaussians per pixel and the
+    number of pixels each Gaussian is composited at (its ray hits, Eq. 4)."""
     pr = project(p, scene, cam, opts)
     H, W = cam.height, cam.width
     ys, xs = torch.meshgrid(torch.arange(H, dtype=torch.float64) + 0.5,
@@ -150,6 +151,7 @@ def render_view(p, scene, cam, opts):
     Cimg = torch.zeros(3, P, dtype=torch.float64)
     alive = torch.ones(P, dtype=torch.bool)
     count = torch.zeros(P, dtype=torch.int64)
+    hits = np.zeros(n, np.int64)
     for j in order:
         if not bool(pr["keep"][j]):
             continue
@@ -167,23 +169,25 @@ def render_view(p, scene, cam, opts):
         Cimg = Cimg + pr["rgb"][:, j:j + 1] * (a * T)[None, :]
         T = T * (1 - a)
         count = count + use.long()
+        hits[j] = int(use.sum())
     bg = torch.tensor(opts.bg, dtype=torch.float64)[:, None]
     img = Cimg + T[None, :] * bg
-    return img.reshape(3, H, W), T.reshape(H, W), count.reshape(H, W)
+    return img.reshape(3, H, W), T.reshape(H, W), count.reshape(H, W), hits
 
 
 def render(scene, cams, opts, weights=None, grad=True):
     """Images for all views; with `weights` (list of [3,H,W]) also the gradient of
     sum_v sum(weights_v * image_v) w.r.t. every raw parameter (float64 numpy)."""
     p = params_of(scene, grad=grad and weights is not None)
-    imgs, Ts, counts = [], [], []
+    imgs, Ts, counts, hits = [], [], [], []
     for cam in cams:
-        im, T, c = render_view(p, scene, cam, opts)
+        im, T, c, h = render_view(p, scene, cam, opts)
         imgs.append(im)
         Ts.append(T)
         counts.append(c)
+        hits.append(h)
     out = dict(images=[i.detach().numpy() for i in imgs], T_final=[t.detach().numpy() for t in Ts],
-               counts=[c.numpy() for c in counts])
+               counts=[c.numpy() for c in counts], hits=hits)
     if weights is not None:
         loss = sum((im * _t(w)).sum() for im, w in zip(imgs, weights))
         loss.backward()

@@ -663,6 +663,51 @@ void orc_composite_fwd(int32_t V, int64_t n, const OrcCamera* cams, const OrcOpt
   }
 }
 
+// Number of pixels where each record is composited (the ray hits of the
+// significance score, Eq. 4): walks every pixel like orc_composite_fwd and
+// counts the records in its composited list.  hits: [V*n], zeroed here.
+// Pixels where a decision lies within eps of its threshold (the flags of
+// orc_composite_fwd) add one to `uncertain` of every record of their tile's
+// list: a single-precision walk may decide differently there.
+void orc_hits(int32_t V, int64_t n, const OrcCamera* cams, const OrcOpts* o, const double* uv, const double* conic,
+              const double* opacity, const double* rgb, const int32_t* radius, const uint32_t* ids,
+              const uint32_t* ranges, const double* eps, uint32_t* hits, uint32_t* uncertain) {
+  int64_t total_tiles = 0;
+  std::vector<ViewGeom> vt = view_table(V, cams, *o, &total_tiles, nullptr);
+  std::vector<int32_t> tile_view(total_tiles);
+  for (int v = 0; v < V; ++v)
+    for (int64_t t = 0; t < (int64_t)vt[v].TX * vt[v].TY; ++t) tile_view[vt[v].tile_off + t] = v;
+  for (int64_t r = 0; r < (int64_t)V * n; ++r) {
+    hits[r] = 0;
+    if (uncertain) uncertain[r] = 0;
+  }
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t gt = 0; gt < total_tiles; ++gt) {
+    const int vi = tile_view[gt];
+    const ViewGeom& g = vt[vi];
+    const int64_t lt = gt - g.tile_off;
+    const int tx = (int)(lt % g.TX), ty = (int)(lt / g.TX);
+    const int64_t start = ranges[2 * gt], end = ranges[2 * gt + 1];
+    std::vector<Contrib> list;
+    for (int yy = ty * o->tile_h; yy < std::min(g.H, (ty + 1) * o->tile_h); ++yy)
+      for (int xx = tx * o->tile_w; xx < std::min(g.W, (tx + 1) * o->tile_w); ++xx) {
+        list.clear();
+        WalkResult r = walk_pixel(xx + 0.5, yy + 0.5, start, end, ids, uv, conic, opacity, rgb, radius, eps, &list);
+        if (r.flags && uncertain) {
+          // a near-threshold pixel: a walk in other arithmetic may count any record of the tile
+          for (int64_t k = start; k < end; ++k) {
+#pragma omp atomic
+            uncertain[ids[k]] += 1u;
+          }
+        }
+        for (const Contrib& c : list) {
+#pragma omp atomic
+          hits[c.rec] += 1u;
+        }
+      }
+  }
+}
+
 // Gradient of sum(dL_dimage * image) with respect to the per-record splat
 // values, written to grad_rec [V*n][9] as (u, v, A, B, C, o', r, g, b).
 // Per pixel, with T_i the transmittance in front of composited Gaussian i and

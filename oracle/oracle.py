@@ -11,6 +11,7 @@ positions produced elsewhere) as well as run the whole chain.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 import threading
@@ -86,6 +87,8 @@ def lib():
                                         I32, U32, U32, D, D, U8]
         L.orc_project_bwd.argtypes = [C.POINTER(OrcGaussians), C.POINTER(OrcCamera), C.POINTER(OrcOpts), D,
                                       C.POINTER(OrcGrads)]
+        L.orc_hits.argtypes = [C.c_int32, C.c_int64, C.POINTER(OrcCamera), C.POINTER(OrcOpts), D, D, D, D, I32, U32,
+                               U32, D, U32, U32]
         _lib = L
     return _lib
 
@@ -256,6 +259,66 @@ def composite_fwd(cams, opts, n, splats, ids, ranges, eps=None, tile_mask=None) 
                             _p(flags, U8) if e is not None else None,
                             _p(hsh, U64) if e is not None else None, _p(tm, U8))
     return dict(image=img, T_final=T, last_contrib=last, flags=flags, hash=hsh)
+
+
+def hits(cams, opts, n, splats, ids, ranges, eps=None) -> dict:
+    """Per record, the number of pixels where it is composited (Eq. 4's ray hits) -> [V*n] uint32,
+    and, if eps is given, per record the number of near-threshold pixels whose tile lists it."""
+    V = len(cams)
+    uv, conic, op, rgb, rad = _splat_args(splats)
+    ids = np.ascontiguousarray(ids, np.uint32)
+    if ids.size == 0:
+        ids = np.zeros(1, np.uint32)
+    ranges = np.ascontiguousarray(ranges, np.uint32)
+    h = np.zeros(V * n, np.uint32)
+    u = np.zeros(V * n, np.uint32)
+    e = None if eps is None else np.asarray(eps, np.float64)
+    cs, o = _cams(cams), opts_struct(opts)
+    lib().orc_hits(V, n, cs, C.byref(o), _p(uv, D), _p(conic, D), _p(op, D), _p(rgb, D), _p(rad, I32), _p(ids, U32),
+                   _p(ranges, U32), _p(e, D), _p(h, U32), _p(u, U32) if e is not None else None)
+    return dict(hits=h, uncertain=u)
+
+
+def count_hits(scene, cams, opts, eps=None, splats=None, lists=None) -> dict:
+    """Whole chain for Eq. 4's ray hits: project, bin, walk; per record and per Gaussian."""
+    n = scene.n
+    if splats is None:
+        splats = project_views(scene, cams, opts)
+    if lists is None:
+        lists = bin(cams, opts, n, splats["uv"][:, 0].astype(np.float32), splats["uv"][:, 1].astype(np.float32),
+                    splats["depth"].astype(np.float32), splats["radius"], splats["valid"])
+    h = hits(cams, opts, n, splats, lists["ids"], lists["ranges"], eps=eps)
+    h["per_gaussian"] = hits_per_gaussian(h["hits"], len(cams), n)
+    h.update(splats=splats, lists=lists)
+    return h
+
+
+def hits_per_gaussian(hits_rec, V: int, n: int) -> np.ndarray:
+    """Sum over the V views of the per-record hit counts -> [n] (records are view-major)."""
+    return np.asarray(hits_rec, np.int64).reshape(V, n).sum(0)
+
+
+def volume_rank(q: float, n: int) -> int:
+    """Ascending rank (1-based) of the reference volume: ceil(q n) in double, clamped to [1, n]."""
+    return min(max(int(math.ceil(float(q) * float(n))), 1), n)
+
+
+def significance(scene, hits, q: float = 0.9) -> np.ndarray:
+    """Significance score of Eq. 4 per Gaussian j: hits_j x o'_j x gamma_j, in FP64.
+    hits_j = the number of (view, pixel) rays where Gaussian j is composited (summed over views);
+    o'_j = sigmoid(opacity logit) x the hard volume mask of Eq. 3; gamma_j = min(vol_j / v_q, 1),
+    vol_j = the product of its three scales, v_q the volume at ascending rank ceil(q n) (the
+    normalisation by the volume of the largest Gaussians that Sec. 3.2.2 describes)."""
+    n = scene.n
+    h = np.asarray(hits, np.float64)
+    op = 1.0 / (1.0 + np.exp(-scene.opacity_logits.astype(np.float64)))
+    if scene.mask_logits is not None:
+        op = op * (1.0 / (1.0 + np.exp(-scene.mask_logits.astype(np.float64))) > scene.mask_eps)
+    vol = np.exp(scene.log_scales.astype(np.float64).sum(0))
+    if n == 0:
+        return np.zeros(0)
+    vq = np.sort(vol)[volume_rank(q, n) - 1]
+    return h * op * np.minimum(vol / vq, 1.0)
 
 
 def composite_bwd(cams, opts, n, splats, ids, ranges, dL_dimage, tile_mask=None) -> np.ndarray:
