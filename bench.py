@@ -30,9 +30,14 @@ import numpy as np  # noqa: E402
 PEAK_FP32_TFLOPS = 157.3   # MI355X published fp32 vector peak
 PEAK_HBM_GBS = 8000.0      # MI355X HBM3E
 # Algorithmic work per composited (pixel, splat) pair, counted from the
-# operations the method needs (see the kernel notes in the design document):
+# operations the method needs.  Forward: 2 (offset) + 9 (quadratic form) + 1
+# (exponent scale) + 1 (exp) + 2 (opacity product, cap) + 2 (T (1 - alpha)) +
+# 7 (colour update).  Backward: 15 (recompute) + 2 (T recovery) + 6 (colour
+# gradient) + 8 (dL/dalpha) + 19 (conic and position gradient) + 2 (opacity) +
+# 8 (bookkeeping).
 FWD_FLOP_PER_PAIR = 24.0
 BWD_FLOP_PER_PAIR = 60.0
+COUNT_FLOP_PER_PAIR = 17.0  # the forward walk without the 7 FLOP of the colour update
 
 
 def parse():
@@ -253,6 +258,32 @@ def main():
                                   frac=round(loss_bytes / (loss_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 5)),
                     kernels="ssim_fwd_kernel + ssim_bwd_kernel + loss_reduce_kernel + loss_mean_kernel")
 
+    # ---------------- significance score (Eq. 4) over the step's views ----------------
+    hits = torch.zeros(sc.n, dtype=torch.int32, device=dev)
+    score = torch.empty(sc.n, dtype=torch.float32, device=dev)
+    for _ in range(2):
+        r.count_hits(hits)
+        raster.significance(params, hits, 0.9, sc.mask_eps, out=score)
+    hits.zero_()
+    sev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ns = max(5, args.steps)
+    sev[0].record(stream)
+    for _ in range(ns):
+        r.count_hits(hits)
+    sev[1].record(stream)
+    for _ in range(ns):
+        raster.significance(params, hits, 0.9, sc.mask_eps, out=score)
+    sev[2].record(stream)
+    torch.cuda.synchronize()
+    count_ms = sev[0].elapsed_time(sev[1]) / ns
+    score_ms = sev[1].elapsed_time(sev[2]) / ns
+    hit_total = int(hits.to(torch.int64).sum()) // ns
+    count_tflops = useful_pairs * COUNT_FLOP_PER_PAIR / (count_ms * 1e-3) / 1e12
+    significance = dict(count_hits_ms=round(count_ms, 4), score_ms=round(score_ms, 4), hits_per_call=hit_total,
+                        roofline=dict(bound="alu", achieved=round(count_tflops, 3), peak=PEAK_FP32_TFLOPS,
+                                      unit="TFLOP/s", frac=round(count_tflops / PEAK_FP32_TFLOPS, 5)),
+                        kernels="render_fwd_kernel<COUNT> + select_hist/pick (4 passes) + significance_kernel")
+
     # ---------------- FP64 oracle on the host cores (bounded sample) ----------------
     cpu = None
     if not args.no_cpu_baseline:
@@ -285,6 +316,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "l1_dssim": l1_dssim,
+        "significance": significance,
         "kernel_source": src_hash,
     }
     print(json.dumps(out), flush=True)

@@ -238,7 +238,6 @@ int gs_project_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t V, cons
                    const gs_projected* proj, const gs_binning* bins, const float* grad_pair, gs_grads* grads,
                    void* ws, size_t ws_bytes, gs_stream_t stream);
 
-/* Static description of a return code. */
 /* Photometric loss of Eq. 7, its L1 and D-SSIM terms, over the V views of a
  * rendered image (layout of gs_render_fwd's image), and its gradient:
  *   L_v = (1 - lambda) mean|x - y| + lambda (1 - mean SSIM),  L = mean_v L_v
@@ -267,6 +266,33 @@ size_t gs_mask_loss_workspace_size(int64_t n);
 int gs_mask_loss(const gs_gaussians* g, float lambda_m, float lambda_sh, float* loss, gs_grads* grads, void* ws,
                  size_t ws_bytes, gs_stream_t stream);
 
+/* Ray hits of the significance score (Eq. 4, Sec. 3.2.2): the walk of
+ * gs_render_fwd over the same lists and with the same per-pixel decisions,
+ * counting instead of blending.  For each Gaussian i, ADDS (+=) to hits[i]
+ * the number of pixels of the V views where it is composited (alpha >= 1/255,
+ * in front of the point where the transmittance would fall under 1e-4).
+ * Call once per batch of views into one caller-zeroed array to sum over a
+ * training set.  hits: device [n] uint32.  Writes nothing else; needs no
+ * workspace. */
+int gs_count_hits(const gs_projected* proj, const gs_binning* bins, const gs_camera* cams, int32_t V, int64_t n,
+                  const gs_opts* opts, uint32_t* hits, gs_stream_t stream);
+
+/* Significance score of Eq. 4 from the summed ray hits:
+ *   score_i = hits_i * o'_i * min(vol_i / v_q, 1)
+ * o'_i = sigmoid(opacity_logit) times the hard volume mask (Eq. 3, when
+ * g->mask_logits is given); vol_i = the product of the three scales; v_q the
+ * volume at ascending rank ceil(q n) (q = volume_quantile in (0, 1], 0.9 for
+ * the normalisation by the largest Gaussians' volume of Sec. 3.2.2; rank
+ * computed in double).  Volumes are compared as the float sums of the
+ * log-scales.  A Gaussian without hits scores 0.  Only g's log_scales,
+ * opacity_logits, mask_logits, mask_eps and n are read.  hits: device [n];
+ * score: device [n] (written).  ws_bytes >= gs_significance_workspace_size().
+ * Deterministic. */
+size_t gs_significance_workspace_size(void);
+int gs_significance(const gs_gaussians* g, const uint32_t* hits, float volume_quantile, float* score, void* ws,
+                    size_t ws_bytes, gs_stream_t stream);
+
+/* Static description of a return code. */
 const char* gs_strerror(int code);
 
 #ifdef __cplusplus

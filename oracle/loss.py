@@ -4,7 +4,7 @@ infrastructure only, never called by the product path.
     L = (1 - lambda) L1 + lambda (1 - SSIM)                      (Eq. 7, first two terms)
 
 per view, the batched loss being the mean over the views of a call.  The
-paper leaves L1 and SSIM to 3DGS; the readings (the DESIGN notes list them):
+paper leaves L1 and SSIM to 3DGS; the readings taken here:
   * L1 = mean over the view's 3 H W values of |x - y|;
   * SSIM = mean over the same values of the SSIM map of each colour plane,
     computed from Gaussian-weighted local moments: an 11 x 11 window, the

@@ -3,7 +3,7 @@ never called by the product path.
 
     lambda_m L_m + lambda_sh L_sh                                (Eq. 7, last two terms)
 
-The paper takes both terms from the works it cites.  Readings (listed in the DESIGN notes):
+The paper takes both terms from the works it cites.  The readings taken here:
   * L_m  = mean over the n Gaussians of sigmoid(m_i), the soft volume mask of Eq. 3
     (the loss acts on the soft mask, not on its hard straight-through value);
   * L_sh = mean over the Gaussians of sum_l w_l sigmoid(m_i^l), bands l = 1..deg, with each

@@ -173,6 +173,8 @@ RenderArgs render_args(const gs_projected* p, const gs_binning* b, const gs_opts
   a.nslots = chunk_slots(b->capacity, o);
   a.slot_owner = nullptr;
   a.state = nullptr;
+  a.hits = nullptr;
+  a.n = 0;
   return a;
 }
 
@@ -345,6 +347,38 @@ int gs_render_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t V, const
   if (e != hipSuccess) return GS_E_HIP;
   return launched(launch_project_bwd(project_bwd_args(pa, opts, proj, bins, grad_pair, grads, g->sh_degree, ws, nrec),
                                      vt, g->sh_degree, s));
+}
+
+int gs_count_hits(const gs_projected* proj, const gs_binning* bins, const gs_camera* cams, int32_t V, int64_t n,
+                  const gs_opts* opts, uint32_t* hits, gs_stream_t stream) {
+  ViewTable vt;
+  if (!proj || n < 0 || !view_table(cams, V, opts, &vt, nullptr)) return GS_E_INVALID;
+  if (!binning_ok(bins, (int64_t)V * n)) return GS_E_INVALID;
+  if (n > 0 && (!proj->splats || !hits)) return GS_E_INVALID;
+  const int d = device_ok();
+  if (d != GS_OK) return d;
+  RenderArgs a = render_args(proj, bins, opts);
+  a.hits = hits;
+  a.n = n;
+  return launched(launch_count_hits(a, vt, (hipStream_t)stream));
+}
+
+size_t gs_significance_workspace_size(void) { return sizeof(SelectState); }
+
+int gs_significance(const gs_gaussians* g, const uint32_t* hits, float volume_quantile, float* score, void* ws,
+                    size_t ws_bytes, gs_stream_t stream) {
+  if (!g || g->n < 0 || g->n >= (1ll << 32)) return GS_E_INVALID;
+  if (!(volume_quantile > 0.0f && volume_quantile <= 1.0f)) return GS_E_INVALID;
+  const int64_t n = g->n;
+  if (n > 0 && (!g->log_scales || !g->opacity_logits || !hits || !score)) return GS_E_INVALID;
+  if (!ws || ws_bytes < sizeof(SelectState)) return GS_E_INVALID;
+  float thr = 0.0f;
+  if (g->mask_logits && !mask_threshold(g->mask_eps, &thr)) return GS_E_INVALID;
+  const int d = device_ok();
+  if (d != GS_OK) return d;
+  const int64_t r = std::min<int64_t>(std::max<int64_t>((int64_t)std::ceil((double)volume_quantile * (double)n), 1), n);
+  return launched(launch_significance(g->log_scales, g->opacity_logits, g->mask_logits, thr, hits, n,
+                                      (uint32_t)(r - 1), (SelectState*)ws, score, (hipStream_t)stream));
 }
 
 int gs_blend_bwd(const gs_camera* cams, int32_t V, int64_t n, const gs_opts* opts, const gs_projected* proj,

@@ -49,6 +49,9 @@ struct RenderArgs {
   int64_t nslots;
   uint32_t* slot_owner;
   float4* state;
+  // hit counting (Eq. 4): per-Gaussian counters, n Gaussians per view
+  uint32_t* hits;
+  int64_t n;
 };
 
 struct BinOut {
@@ -101,6 +104,18 @@ hipError_t launch_loss(const LossViews& lv, const float* image, const float* tar
 hipError_t launch_mask_loss(const float* m, const float* msh, int64_t n, int deg, float lam_m, float lam_sh,
                             float* gm, float* gsh, float* loss, float* bsum, hipStream_t s);
 
+// Radix-select state of the volume quantile (significance score).
+struct SelectState {
+  uint32_t prefix;  // key bits chosen so far
+  uint32_t rank;    // rank still wanted among the keys matching the prefix
+  uint32_t pad[2];
+  uint32_t hist[256];
+};
+
+hipError_t launch_significance(const float* log_scales, const float* opacity_logits, const float* mask_logits,
+                               float mask_thr, const uint32_t* hits, int64_t n, uint32_t rank, SelectState* st,
+                               float* score, hipStream_t s);
+
 // Workspace carve-up of gs_bin_sort / gs_render_bwd.
 struct SortPlan {
   int64_t nrec;             // V * n
@@ -119,6 +134,8 @@ hipError_t launch_bin_sort(const SortPlan& plan, const float4* splats, const uin
 
 hipError_t launch_render_fwd(const RenderArgs& a, const ViewTable& vt, float* image, float* T_final,
                              int32_t* last_contrib, hipStream_t s);
+
+hipError_t launch_count_hits(const RenderArgs& a, const ViewTable& vt, hipStream_t s);
 
 hipError_t launch_render_bwd(const RenderArgs& a, const ViewTable& vt, const float* T_final,
                              const int32_t* last_contrib, const float* dL_dimage, float* grad_pair, hipStream_t s);

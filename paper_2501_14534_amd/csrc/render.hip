@@ -256,7 +256,12 @@ __device__ __forceinline__ float reduce_scatter9(const float (&x)[GS_GRAD_FLOATS
   return v;
 }
 
-template <int PPT, bool CULL>
+// COUNT: the same walk, counting instead of blending: per Gaussian, the
+// number of pixels where it is composited (the ray hits of Eq. 4), added to
+// a.hits; no image, no chunk states.  Per record and batch, the waves add
+// their ballot counts into an LDS counter (in place of the staged colours),
+// which is flushed to the Gaussian's global counter once the batch is walked.
+template <int PPT, bool CULL, bool COUNT>
 __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable vt, float* __restrict__ image,
                                                          float* __restrict__ T_final, int32_t* __restrict__ last_out) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -272,6 +277,9 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable
   float4* s_b = L.b;
   float4* s_c = L.c;
   uint8_t* s_mask = L.mask;
+  uint32_t* s_hits = (uint32_t*)L.c;  // COUNT only
+  if (COUNT)
+    for (int i = threadIdx.x; i < a.batch; i += blockDim.x) s_hits[i] = 0u;
 
   // C: colour composited so far (the image); S: colour composited since the
   // last chunk boundary (kept apart so that the colour after a boundary is a
@@ -293,7 +301,7 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable
   }
 
   const int tpx = 1 << (a.log2_tw + a.log2_th);
-  const int lc = a.log2_chunk;
+  const int lc = COUNT ? 31 : a.log2_chunk;  // counting records no chunk states
   int nbnd = 0;  // chunk boundaries recorded (uniform)
   // batches never straddle a chunk boundary
   auto batch_end = [&](uint32_t b0) -> uint32_t {
@@ -314,7 +322,7 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable
     const uint32_t rec = a.ids[bs + t];
     pa = a.splats[(size_t)rec * 3 + 0];
     pb = a.splats[(size_t)rec * 3 + 1];
-    pc = a.splats[(size_t)rec * 3 + 2];
+    if (!COUNT) pc = a.splats[(size_t)rec * 3 + 2];
   }
   if (be + t < be2) nid = a.ids[be + t];
   while (bs < tc.end) {
@@ -335,7 +343,7 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable
     for (int w = 0; w < nwaves; ++w) any |= s_alive[w];
     if (!any) break;
     const uint64_t rel = bs - tc.start;
-    if (rel != 0 && (rel & ((1ull << lc) - 1)) == 0) {
+    if (!COUNT && rel != 0 && (rel & ((1ull << lc) - 1)) == 0) {
       // a chunk boundary of the backward: record each pixel's transmittance
       // here and the colour of the chunk that ends here, then start a new chunk
       const int64_t slot = (int64_t)(bs >> lc);
@@ -352,7 +360,7 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable
     if (t < cnt) {  // entry t from the registers
       s_a[t] = pa;
       s_b[t] = pb;
-      s_c[t] = pc;
+      if (!COUNT) s_c[t] = pc;
       if (CULL) s_mask[t] = (uint8_t)footprint_mask(pa, pb, nwaves, s_box);
     }
     for (int i = t + nthreads; i < cnt; i += nthreads) {  // batches deeper than the workgroup
@@ -361,7 +369,7 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable
       const float4 rb = a.splats[(size_t)rec * 3 + 1];
       s_a[i] = ra;
       s_b[i] = rb;
-      s_c[i] = a.splats[(size_t)rec * 3 + 2];
+      if (!COUNT) s_c[i] = a.splats[(size_t)rec * 3 + 2];
       if (CULL) s_mask[i] = (uint8_t)footprint_mask(ra, rb, nwaves, s_box);
     }
     // issue the next batch's record loads and the following batch's id loads
@@ -369,7 +377,7 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable
     if (be + t < be2) {
       pa = a.splats[(size_t)nid * 3 + 0];
       pb = a.splats[(size_t)nid * 3 + 1];
-      pc = a.splats[(size_t)nid * 3 + 2];
+      if (!COUNT) pc = a.splats[(size_t)nid * 3 + 2];
     }
     nid = be2 + t < be3 ? a.ids[be2 + t] : 0u;
     __syncthreads();
@@ -385,6 +393,7 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable
       // that skips the splat adds exact zeros
       auto blend = [&](int j, const float4& ra, const float4& rb, const float4& rc) {
         const int idx = (int)(bs + j - tc.start) + 1;
+        uint32_t taken = 0;  // COUNT: pixels of this wave that composite record j
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
           Eval e;
@@ -403,25 +412,40 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable
           S2[p] += rc.z * w;
           T[p] = take ? Tn : T[p];
           last[p] = take ? idx : last[p];
+          if (COUNT) taken += (uint32_t)__popcll(__ballot(take));
         }
+        if (COUNT && lane == 0 && taken != 0) atomicAdd(s_hits + j, taken);
       };
       // two register sets in turn: the next record loads while this one blends
+      const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
       int j0 = c * kWave + __builtin_ctzll(m);
       m &= m - 1;
-      float4 a0 = s_a[j0], b0 = s_b[j0], c0 = s_c[j0];
+      float4 a0 = s_a[j0], b0 = s_b[j0], c0 = COUNT ? zero4 : s_c[j0];
       for (;;) {
         const bool more1 = m != 0;
         const int j1 = more1 ? c * kWave + __builtin_ctzll(m) : j0;
         m &= m - 1;
-        const float4 a1 = s_a[j1], b1 = s_b[j1], c1 = s_c[j1];
+        const float4 a1 = s_a[j1], b1 = s_b[j1], c1 = COUNT ? zero4 : s_c[j1];
         blend(j0, a0, b0, c0);
         if (!more1) break;
         const bool more2 = m != 0;
         j0 = more2 ? c * kWave + __builtin_ctzll(m) : j1;
         m &= m - 1;
-        a0 = s_a[j0], b0 = s_b[j0], c0 = s_c[j0];
+        a0 = s_a[j0], b0 = s_b[j0], c0 = COUNT ? zero4 : s_c[j0];
         blend(j1, a1, b1, c1);
         if (!more2) break;
+      }
+    }
+    if (COUNT) {
+      // flush the batch's counters (each thread clears the ones it reads; the
+      // next batch's additions start after the next loop-top barrier)
+      __syncthreads();
+      for (int i = t; i < cnt; i += nthreads) {
+        const uint32_t h = s_hits[i];
+        if (h != 0) {
+          atomicAdd(a.hits + ((int64_t)a.ids[bs + i] - (int64_t)tc.view * a.n), h);
+          s_hits[i] = 0u;
+        }
       }
     }
     bs = be;
@@ -429,6 +453,7 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable
     be2 = be3;
   }
 
+  if (COUNT) return;
   // Each recorded state becomes (T there, colour composited after it): the
   // suffix sums of the chunks' colours, last chunk first.
   for (int k = nbnd; k >= 1; --k) {
@@ -681,9 +706,20 @@ static void fwd_ppt(const RenderArgs& a, const ViewTable& vt, float* image, floa
   const dim3 grid((unsigned)vt.total_tiles), block((unsigned)nt);
   const size_t sh = lds_bytes(a.batch, nt / kWave, false);
   if (a.cull)
-    hipLaunchKernelGGL((render_fwd_kernel<PPT, true>), grid, block, sh, s, a, vt, image, T_final, last);
+    hipLaunchKernelGGL((render_fwd_kernel<PPT, true, false>), grid, block, sh, s, a, vt, image, T_final, last);
   else
-    hipLaunchKernelGGL((render_fwd_kernel<PPT, false>), grid, block, sh, s, a, vt, image, T_final, last);
+    hipLaunchKernelGGL((render_fwd_kernel<PPT, false, false>), grid, block, sh, s, a, vt, image, T_final, last);
+}
+
+template <int PPT>
+static void count_ppt(const RenderArgs& a, const ViewTable& vt, hipStream_t s) {
+  const int nt = tile_threads(a);
+  const dim3 grid((unsigned)vt.total_tiles), block((unsigned)nt);
+  const size_t sh = lds_bytes(a.batch, nt / kWave, false);
+  if (a.cull)
+    hipLaunchKernelGGL((render_fwd_kernel<PPT, true, true>), grid, block, sh, s, a, vt, nullptr, nullptr, nullptr);
+  else
+    hipLaunchKernelGGL((render_fwd_kernel<PPT, false, true>), grid, block, sh, s, a, vt, nullptr, nullptr, nullptr);
 }
 
 template <int PPT>
@@ -708,6 +744,16 @@ hipError_t launch_render_fwd(const RenderArgs& a, const ViewTable& vt, float* im
     case 1: fwd_ppt<1>(a, vt, image, T_final, last_contrib, s); break;
     case 2: fwd_ppt<2>(a, vt, image, T_final, last_contrib, s); break;
     default: fwd_ppt<4>(a, vt, image, T_final, last_contrib, s); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_count_hits(const RenderArgs& a, const ViewTable& vt, hipStream_t s) {
+  if (vt.total_tiles == 0) return hipSuccess;
+  switch (a.ppt) {
+    case 1: count_ppt<1>(a, vt, s); break;
+    case 2: count_ppt<2>(a, vt, s); break;
+    default: count_ppt<4>(a, vt, s); break;
   }
   return hipGetLastError();
 }

@@ -21,7 +21,7 @@ MAX_BATCH = 1024
 
 EXPORTS = ("gs_view_sizes", "gs_workspace_size", "gs_project", "gs_bin_sort", "gs_render_fwd", "gs_render_bwd",
            "gs_blend_bwd", "gs_project_bwd", "gs_loss_workspace_size", "gs_loss_l1_dssim", "gs_mask_loss_workspace_size", "gs_mask_loss",
-           "gs_strerror")
+           "gs_count_hits", "gs_significance_workspace_size", "gs_significance", "gs_strerror")
 
 vp = C.c_void_p
 
@@ -103,6 +103,12 @@ def load():
     L.gs_mask_loss_workspace_size.restype = C.c_size_t
     L.gs_mask_loss.argtypes = [P(GsGaussians), C.c_float, C.c_float, vp, P(GsGrads), vp, C.c_size_t, vp]
     L.gs_mask_loss.restype = C.c_int
+    L.gs_count_hits.argtypes = [P(GsProjected), P(GsBinning), P(GsCamera), C.c_int32, C.c_int64, P(GsOpts), vp, vp]
+    L.gs_count_hits.restype = C.c_int
+    L.gs_significance_workspace_size.argtypes = []
+    L.gs_significance_workspace_size.restype = C.c_size_t
+    L.gs_significance.argtypes = [P(GsGaussians), vp, C.c_float, vp, vp, C.c_size_t, vp]
+    L.gs_significance.restype = C.c_int
     L.gs_strerror.argtypes = [C.c_int]
     L.gs_strerror.restype = C.c_char_p
     _lib = L
@@ -199,6 +205,18 @@ def loss_workspace_size(cams_arr, V) -> int:
 def loss_l1_dssim(image, target, cams_arr, V, lambda_ssim, loss, dL_dimage, ws, ws_bytes, stream) -> int:
     return load().gs_loss_l1_dssim(image, target, cams_arr, V, float(lambda_ssim), loss, dL_dimage, ws, ws_bytes,
                                    stream)
+
+
+def count_hits(proj, bins, cams_arr, V, n, opts_s, hits, stream) -> int:
+    return load().gs_count_hits(C.byref(proj), C.byref(bins), cams_arr, V, int(n), C.byref(opts_s), hits, stream)
+
+
+def significance_workspace_size() -> int:
+    return int(load().gs_significance_workspace_size())
+
+
+def significance(g, hits, volume_quantile, score, ws, ws_bytes, stream) -> int:
+    return load().gs_significance(C.byref(g), hits, float(volume_quantile), score, ws, ws_bytes, stream)
 
 
 def mask_loss_workspace_size(n) -> int:

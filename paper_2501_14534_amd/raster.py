@@ -133,6 +133,24 @@ class Rasterizer:
         gs.check(gs.project_bwd(g, self.cams_arr, self.V, self.opts_s, self.proj, self.bins, gs.ptr(grad_pair), gr,
                                 gs.ptr(self.ws), self.ws_bytes, _stream()), "gs_project_bwd")
 
+    def count_hits(self, hits: torch.Tensor, bins: Optional[gs.GsBinning] = None) -> None:
+        """Adds the ray hits of Eq. 4 over the current lists (last bin_sort) into hits [n] (int32
+        tensor holding uint32 counts).  `bins` may replace the lists (same buffers, other ranges)."""
+        if hits.numel() < self.n or hits.dtype != torch.int32 or not hits.is_contiguous():
+            raise ValueError("hits must be a contiguous int32 tensor of n counters")
+        gs.check(gs.count_hits(self.proj, bins if bins is not None else self.bins, self.cams_arr, self.V, self.n,
+                               self.opts_s, gs.ptr(hits), _stream()), "gs_count_hits")
+
+    def accumulate_hits(self, params, hits: torch.Tensor) -> None:
+        """project -> bin/sort (grown on overflow) -> count: this view set's hits added into `hits`."""
+        self.project(params)
+        self.bin_sort()
+        if self.overflowed():
+            self.set_capacity(int(self.pairs() * 1.25) + 1024)
+            self.bin_sort()
+            assert not self.overflowed()
+        self.count_hits(hits)
+
     def overflowed(self) -> bool:
         return bool(self.status.item())
 
@@ -186,6 +204,31 @@ class Rasterizer:
 
     def zero_grads(self, params) -> Dict[str, torch.Tensor]:
         return {k: torch.zeros_like(v) for k, v in params.items() if v is not None}
+
+
+def significance(params: Dict[str, torch.Tensor], hits: torch.Tensor, volume_quantile: float = 0.9,
+                 mask_eps: float = 0.5, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Significance score of Eq. 4 from summed ray hits: hits x o' x min(volume / v_q, 1) [n]."""
+    n = int(params["log_scales"].shape[-1])
+    g = gs.gaussians(params, n, 0, mask_eps, 0.5)
+    score = out if out is not None else torch.empty(n, dtype=torch.float32, device=hits.device)
+    ws_bytes = gs.significance_workspace_size()
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=hits.device)
+    gs.check(gs.significance(g, gs.ptr(hits), volume_quantile, gs.ptr(score), gs.ptr(ws), ws_bytes, _stream()),
+             "gs_significance")
+    return score
+
+
+def significance_scores(params: Dict[str, torch.Tensor], sh_degree: int, cams: Sequence, opts,
+                        views_per_call: int = 8, volume_quantile: float = 0.9, mask_eps: float = 0.5,
+                        sh_mask_eps: float = 0.5) -> Dict[str, torch.Tensor]:
+    """Eq. 4 over a set of (training) views: ray hits summed over batches of views, then the score."""
+    n = int(params["means"].shape[-1])
+    hits = torch.zeros(n, dtype=torch.int32, device=params["means"].device)
+    for k in range(0, len(cams), views_per_call):
+        r = Rasterizer(n, sh_degree, cams[k:k + views_per_call], opts, mask_eps=mask_eps, sh_mask_eps=sh_mask_eps)
+        r.accumulate_hits(params, hits)
+    return dict(hits=hits, score=significance(params, hits, volume_quantile, mask_eps))
 
 
 class RasterizeFn(torch.autograd.Function):

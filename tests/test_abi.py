@@ -162,3 +162,29 @@ def test_loss_entry_points_validate_on_the_host(lib):
     assert f(4096, None, cams, V, C.c_float(0.2), 4096, 4096, 4096, need, None) == gs.GS_E_INVALID
     assert f(4096, 4096, cams, V, C.c_float(0.2), 4096, 4096, 4096, need - 1, None) == gs.GS_E_INVALID
     assert f(4096, 4096, cams, V, C.c_float(0.2), 4096, 4096, None, need, None) == gs.GS_E_INVALID
+
+
+def test_significance_entry_points_validate_on_the_host(lib):
+    wl = scenes.config(1, n=64)
+    cams = gs.cameras(wl.cams)
+    o = gs.options(wl.opts)
+    proj = gs.GsProjected(4096, 4096)
+    bins = gs.GsBinning(4096, 4096, 4096, 4096, 4096, None, 100, 4096, 4096)
+    assert lib.gs_count_hits(C.byref(proj), C.byref(bins), cams, 1, 64, C.byref(o), None, None) == gs.GS_E_INVALID
+    assert lib.gs_count_hits(C.byref(proj), C.byref(bins), cams, 0, 64, C.byref(o), 4096, None) == gs.GS_E_INVALID
+    nob = gs.GsBinning(4096, 4096, 4096, 4096, None, None, 100, 4096, 4096)  # ranges missing
+    assert lib.gs_count_hits(C.byref(proj), C.byref(nob), cams, 1, 64, C.byref(o), 4096, None) == gs.GS_E_INVALID
+    need = gs.significance_workspace_size()
+    assert need >= 4 * 256  # one 256-bin histogram
+    g = gs.GsGaussians()
+    g.log_scales, g.opacity_logits, g.n, g.mask_eps = 4096, 4096, 1000, 0.5
+    f = lib.gs_significance
+    for q in (0.0, -0.5, 1.5, float("nan")):
+        assert f(C.byref(g), 4096, C.c_float(q), 4096, 4096, need, None) == gs.GS_E_INVALID, q
+    assert f(C.byref(g), None, C.c_float(0.9), 4096, 4096, need, None) == gs.GS_E_INVALID  # hits missing
+    assert f(C.byref(g), 4096, C.c_float(0.9), None, 4096, need, None) == gs.GS_E_INVALID  # score missing
+    assert f(C.byref(g), 4096, C.c_float(0.9), 4096, 4096, need - 1, None) == gs.GS_E_INVALID
+    g.mask_logits, g.mask_eps = 4096, 1.0  # mask threshold outside (0, 1)
+    assert f(C.byref(g), 4096, C.c_float(0.9), 4096, 4096, need, None) == gs.GS_E_INVALID
+    g.mask_logits, g.mask_eps, g.n = None, 0.5, 1 << 32
+    assert f(C.byref(g), 4096, C.c_float(0.9), 4096, 4096, need, None) == gs.GS_E_INVALID
