@@ -103,9 +103,12 @@ def project(p, scene, cam, opts):
                      torch.stack([zero, cam.fy / tz, -cam.fy * ry / tz], 0)], 0)  # [2,3,N]
     Tm = torch.einsum("ijn,jk->ikn", J, R)
     S2 = torch.einsum("ian,abn,jbn->ijn", Tm, Sig, Tm)
-    a = S2[0, 0] + opts.lowpass
+    lp = float(opts.lowpass)
+    if getattr(opts, "lowpass_progressive", 0):   # Sec. 3.2.4: s = max(s0, H W / (9 pi N))
+        lp = max(lp, cam.height * cam.width / (9.0 * math.pi * n))
+    a = S2[0, 0] + lp
     b = S2[0, 1]
-    c = S2[1, 1] + opts.lowpass
+    c = S2[1, 1] + lp
     det = a * c - b * b
     keep &= det > 0
     A, B, Cc = c / det, -b / det, a / det

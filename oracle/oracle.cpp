@@ -63,6 +63,7 @@ struct OrcOpts {
   double lowpass;
   double bg[3];
   int32_t tile_w, tile_h;
+  int32_t lowpass_progressive;
 };
 
 struct OrcGrads {  // accumulated (+=); NULL members are skipped
@@ -494,6 +495,17 @@ void orc_cov3d(const OrcGaussians* g, double* out) {
 // Projection of all n Gaussians into one view.
 //   valid [n]; uv [n][2]; conic [n][3]; depth [n]; radius [n]; opacity [n]
 //   (masked o'); rgb [n][3]; cov2d [n][3] (Sigma' + sI; may be NULL).
+// Options of one view.  With progressive scaling (Sec. 3.2.4) the low-pass s
+// of the view is HW / (9 pi N) for N Gaussians -- each projected Gaussian then
+// covers at least 9 pi s, the share of the image that N Gaussians fill --
+// bounded below by the given s (0.3).
+OrcOpts view_opts(const OrcOpts& o, const OrcCamera& c, int64_t n) {
+  OrcOpts e = o;
+  if (o.lowpass_progressive && n > 0)
+    e.lowpass = std::max(o.lowpass, (double)c.width * (double)c.height / (9.0 * M_PI * (double)n));
+  return e;
+}
+
 // Culled Gaussians get valid = 0 and zeros elsewhere.
 void orc_project(const OrcGaussians* g, const OrcCamera* cam, const OrcOpts* o, int32_t* valid, double* uv,
                  double* conic, double* depth, int32_t* radius, double* opacity, double* rgb, double* cov2d) {
@@ -501,6 +513,7 @@ void orc_project(const OrcGaussians* g, const OrcCamera* cam, const OrcOpts* o, 
   double campos[3];
   campos_of(*cam, campos);
   const int deg = g->sh_degree;
+  const OrcOpts ov = view_opts(*o, *cam, n);
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
     valid[i] = 0;
@@ -518,7 +531,7 @@ void orc_project(const OrcGaussians* g, const OrcCamera* cam, const OrcOpts* o, 
     if (g->mask_logits) ml = g->mask_logits[i];
     Geom<double> ge;
     if (!project_geom<double>(mu, ls, q, g->opacity_logits[i], g->mask_logits ? &ml : nullptr, g->mask_eps, *cam,
-                              *o, &ge))
+                              ov, &ge))
       continue;
     double dc[3], rest[15][3], bm[3], col[3];
     for (int c = 0; c < 3; ++c) dc[c] = g->sh_dc[c * n + i];
@@ -789,6 +802,7 @@ void orc_project_bwd(const OrcGaussians* g, const OrcCamera* cam, const OrcOpts*
   const int K = (deg + 1) * (deg + 1);
   double campos[3];
   campos_of(*cam, campos);
+  const OrcOpts ov = view_opts(*o, *cam, n);
 #pragma omp parallel for schedule(dynamic, 256)
   for (int64_t i = 0; i < n; ++i) {
     const double* gr = &grad_rec[9 * i];
@@ -804,7 +818,7 @@ void orc_project_bwd(const OrcGaussians* g, const OrcCamera* cam, const OrcOpts*
     ol = DG::var(g->opacity_logits[i], 10);
     if (g->mask_logits) ml = DG::var(g->mask_logits[i], 11);
     Geom<DG> ge;
-    if (!project_geom<DG>(mu, ls, q, ol, g->mask_logits ? &ml : nullptr, g->mask_eps, *cam, *o, &ge)) continue;
+    if (!project_geom<DG>(mu, ls, q, ol, g->mask_logits ? &ml : nullptr, g->mask_eps, *cam, ov, &ge)) continue;
     double dgeo[12] = {0};
     const DG* outs[6] = {&ge.u, &ge.v, &ge.A, &ge.B, &ge.C, &ge.op};
     for (int c = 0; c < 6; ++c)

@@ -47,7 +47,8 @@ class OrcCamera(C.Structure):
 
 class OrcOpts(C.Structure):
     _fields_ = [("near_plane", C.c_double), ("tan_clamp", C.c_double), ("lowpass", C.c_double),
-                ("bg", C.c_double * 3), ("tile_w", C.c_int32), ("tile_h", C.c_int32)]
+                ("bg", C.c_double * 3), ("tile_w", C.c_int32), ("tile_h", C.c_int32),
+                ("lowpass_progressive", C.c_int32)]
 
 
 class OrcGrads(C.Structure):
@@ -141,6 +142,7 @@ def opts_struct(o) -> OrcOpts:
     for i in range(3):
         s.bg[i] = float(o.bg[i])
     s.tile_w, s.tile_h = int(o.tile_w), int(o.tile_h)
+    s.lowpass_progressive = int(getattr(o, "lowpass_progressive", 0))
     return s
 
 
