@@ -83,7 +83,7 @@ typedef struct gs_camera {
 typedef struct gs_opts {
   float near_plane;  /* cull when camera z <= near_plane (e.g. 0.2)                        */
   float tan_clamp;   /* lateral ratio guard of the EWA Jacobian, in half fields of view (1.3) */
-  float lowpass;     /* s of Sigma' + sI (Sec. 3.2.4; 0.3, or max(0.3, HW/(9 pi N)))       */
+  float lowpass;     /* s of Sigma' + sI (Sec. 3.2.4; 0.3), >= 0; see lowpass_progressive  */
   float bg[3];       /* background colour added with the final transmittance              */
   int32_t tile_w;    /* tile width in pixels, power of two                                 */
   int32_t tile_h;    /* tile height in pixels, power of two; tile_w*tile_h in [64, 1024]   */
@@ -95,6 +95,9 @@ typedef struct gs_opts {
                                 two in [16, 2^20], or 0 for one item per tile.  The forward
                                 records each pixel's state at every multiple of bwd_chunk so
                                 the backward can walk the chunks of one long list in parallel. */
+  int32_t lowpass_progressive; /* 1: progressive scaling (Sec. 3.2.4): view v uses
+                                  s_v = max(lowpass, W_v H_v / (9 pi n)) for the n Gaussians of
+                                  the call (computed in double, rounded to float); 0: s = lowpass */
 } gs_opts;
 
 /* Projected (view, Gaussian) records, written by gs_project.
@@ -291,6 +294,25 @@ int gs_count_hits(const gs_projected* proj, const gs_binning* bins, const gs_cam
 size_t gs_significance_workspace_size(void);
 int gs_significance(const gs_gaussians* g, const uint32_t* hits, float volume_quantile, float* score, void* ws,
                     size_t ws_bytes, gs_stream_t stream);
+
+/* Target blur of progressive training (Sec. 3.2.4; 9 x 9, sigma 2.4 at the
+ * start, Sec. 4.2): a ksize x ksize Gaussian, the outer product of two
+ * normalised ksize-tap Gaussians of standard deviation sigma, correlated with
+ * each [H][W] plane mirrored about its edge pixels (index -1 reads index 1).
+ * in, out: device, [sum_v 3 H_v W_v] planar per view, views concatenated (the
+ * layout of gs_render_fwd's image); distinct buffers.  Only the cameras' width
+ * and height are read.  ksize odd in [1, 31]; sigma > 0.  out is written. */
+int gs_blur_views(const float* in, float* out, const gs_camera* cams, int32_t V, int32_t ksize, float sigma,
+                  gs_stream_t stream);
+
+/* Target resize of progressive training (Eq. 6): view v is resampled from
+ * in_cams[v]'s size W x H to out_cams[v]'s size W' x H' by area averaging:
+ * output pixel (x', y') is the mean of the piecewise-constant input over
+ * [x' W / W', (x' + 1) W / W') x [y' H / H', (y' + 1) H / H') (exact
+ * overlap weights).  in, out: device, views concatenated as above, not
+ * overlapping.  Only the cameras' width and height are read. */
+int gs_resize_views(const float* in, const gs_camera* in_cams, float* out, const gs_camera* out_cams, int32_t V,
+                    gs_stream_t stream);
 
 /* Static description of a return code. */
 const char* gs_strerror(int code);

@@ -1,6 +1,7 @@
 // Host side of the libgs C ABI: argument validation, per-view constant
 // tables, workspace carve-up and kernel launches on the caller's stream.
 // Nothing here allocates, frees, synchronises or reads device memory.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -54,6 +55,7 @@ bool opts_ok(const gs_opts* o) {
   if (o->subtile_cull != 0 && o->subtile_cull != 1) return false;
   if (o->bwd_chunk != 0 && (!pow2(o->bwd_chunk) || o->bwd_chunk < 16 || o->bwd_chunk > (1 << 20))) return false;
   if (!std::isfinite(o->lowpass) || o->lowpass < 0.0f) return false;
+  if (o->lowpass_progressive != 0 && o->lowpass_progressive != 1) return false;
   if (!std::isfinite(o->near_plane) || !(o->near_plane > 0.0f)) return false;  // depths > 0 order as bits
   if (!(o->tan_clamp > 0.0f)) return false;
   for (int c = 0; c < 3; ++c)
@@ -86,6 +88,7 @@ bool view_table(const gs_camera* cams, int32_t V, const gs_opts* o, ViewTable* v
     if (a.TX > 65535 || a.TY > 65535) return false;  // tile rectangles are packed as 16-bit sizes
     a.tile_off = (int32_t)to;
     a.pix_off = (int32_t)po;
+    a.lowpass = o->lowpass;
     to += (int64_t)a.TX * a.TY;
     po += (int64_t)c.width * c.height;
     if (to >= (1ll << 31) || 3 * po >= (1ll << 31)) return false;
@@ -94,6 +97,18 @@ bool view_table(const gs_camera* cams, int32_t V, const gs_opts* o, ViewTable* v
   vt->total_tiles = (int32_t)to;
   if (total_pixels) *total_pixels = po;
   return true;
+}
+
+// Per-view low-pass of a call on n Gaussians: with progressive scaling
+// (Sec. 3.2.4) s_v = max(lowpass, W_v H_v / (9 pi n)), so that each projected
+// Gaussian covers at least 9 pi s_v, the share of the view that n of them fill.
+void set_lowpass(ViewTable* vt, const gs_opts* o, int64_t n) {
+  for (int v = 0; v < vt->nviews; ++v) {
+    ViewArgs& a = vt->v[v];
+    double s = o->lowpass;
+    if (o->lowpass_progressive && n > 0) s = std::max(s, (double)a.W * (double)a.H / (9.0 * M_PI * (double)n));
+    a.lowpass = (float)s;
+  }
 }
 
 bool gaussians_ok(const gs_gaussians* g, ProjectArgs* a) {
@@ -210,7 +225,6 @@ void attach_state(RenderArgs* a, uint64_t capacity, int64_t nrec, const gs_opts*
 ProjectBwdArgs project_bwd_args(ProjectArgs pa, const gs_opts* opts, const gs_projected* proj, const gs_binning* bins,
                                 const float* grad_pair, const gs_grads* grads, int deg, void* ws, int64_t nrec) {
   pa.near_plane = opts->near_plane;
-  pa.lowpass = opts->lowpass;
   pa.inv_tw = 1.0f / (float)opts->tile_w;
   pa.inv_th = 1.0f / (float)opts->tile_h;
   ProjectBwdArgs b;
@@ -272,12 +286,12 @@ int gs_project(const gs_gaussians* g, const gs_camera* cams, int32_t V, const gs
   ProjectArgs a;
   ViewTable vt;
   if (!gaussians_ok(g, &a) || !view_table(cams, V, opts, &vt, nullptr)) return GS_E_INVALID;
+  set_lowpass(&vt, opts, g->n);
   if (!out || (g->n > 0 && (!out->splats || !out->tiles_touched))) return GS_E_INVALID;
   if (((uintptr_t)out->splats & 15) != 0) return GS_E_INVALID;
   const int d = device_ok();
   if (d != GS_OK) return d;
   a.near_plane = opts->near_plane;
-  a.lowpass = opts->lowpass;
   a.inv_tw = 1.0f / (float)opts->tile_w;
   a.inv_th = 1.0f / (float)opts->tile_h;
   a.splats = (float4*)out->splats;
@@ -332,6 +346,7 @@ int gs_render_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t V, const
   ProjectArgs pa;
   ViewTable vt;
   if (!gaussians_ok(g, &pa) || !view_table(cams, V, opts, &vt, nullptr)) return GS_E_INVALID;
+  set_lowpass(&vt, opts, g->n);
   if (!proj || !T_final || !last_contrib || !dL_dimage || !grads) return GS_E_INVALID;
   if (!binning_ok(bins, (int64_t)V * g->n)) return GS_E_INVALID;
   if (g->n > 0 && (!proj->splats || !proj->tiles_touched)) return GS_E_INVALID;
@@ -402,6 +417,7 @@ int gs_project_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t V, cons
   ProjectArgs pa;
   ViewTable vt;
   if (!gaussians_ok(g, &pa) || !view_table(cams, V, opts, &vt, nullptr)) return GS_E_INVALID;
+  set_lowpass(&vt, opts, g->n);
   if (!proj || !grads || !binning_ok(bins, (int64_t)V * g->n)) return GS_E_INVALID;
   if (g->n > 0 && (!grad_pair || !proj->tiles_touched)) return GS_E_INVALID;
   const int64_t nrec = (int64_t)V * g->n;
@@ -480,6 +496,53 @@ int gs_loss_l1_dssim(const float* image, const float* target, const gs_camera* c
   if (d != GS_OK) return d;
   return launched(launch_loss(lv, image, target, lambda_ssim, loss, dL_dimage, w.dmap, w.bsum, w.per_view,
                               (hipStream_t)stream));
+}
+
+int gs_blur_views(const float* in, float* out, const gs_camera* cams, int32_t V, int32_t ksize, float sigma,
+                  gs_stream_t stream) {
+  BlurArgs b;
+  int64_t px = 0;
+  if (!loss_views(cams, V, &b.views, &px)) return GS_E_INVALID;
+  if (!in || !out || in == out) return GS_E_INVALID;
+  if (ksize < 1 || ksize > 2 * kMaxBlurRadius + 1 || ksize % 2 == 0) return GS_E_INVALID;
+  if (!std::isfinite(sigma) || !(sigma > 0.0f)) return GS_E_INVALID;
+  const int d = device_ok();
+  if (d != GS_OK) return d;
+  b.r = (ksize - 1) / 2;
+  double g[2 * kMaxBlurRadius + 1], sum = 0.0;
+  for (int k = 0; k < ksize; ++k) {
+    const double t = (double)(k - b.r);
+    sum += (g[k] = std::exp(-t * t / (2.0 * (double)sigma * (double)sigma)));
+  }
+  for (int k = 0; k < 2 * kMaxBlurRadius + 1; ++k) b.g[k] = k < ksize ? (float)(g[k] / sum) : 0.0f;
+  return launched(launch_blur(in, out, b, (hipStream_t)stream));
+}
+
+int gs_resize_views(const float* in, const gs_camera* in_cams, float* out, const gs_camera* out_cams, int32_t V,
+                    gs_stream_t stream) {
+  if (!in || !out || !in_cams || !out_cams || V < 1 || V > GS_MAX_VIEWS) return GS_E_INVALID;
+  ResizeArgs a;
+  std::memset(&a, 0, sizeof(a));
+  int64_t io = 0, oo = 0;
+  for (int v = 0; v < V; ++v) {
+    ResizeView& q = a.v[v];
+    q.W = in_cams[v].width, q.H = in_cams[v].height;
+    q.Wo = out_cams[v].width, q.Ho = out_cams[v].height;
+    if (q.W <= 0 || q.H <= 0 || q.Wo <= 0 || q.Ho <= 0) return GS_E_INVALID;
+    q.in_off = io, q.out_off = oo;
+    q.inv_area = (float)(1.0 / ((double)q.W * (double)q.H));
+    io += (int64_t)q.W * q.H;
+    oo += (int64_t)q.Wo * q.Ho;
+    if (3 * io >= (1ll << 40) || 3 * oo >= (1ll << 40)) return GS_E_INVALID;
+  }
+  a.nviews = V;
+  a.total_out = 3 * oo;
+  // the buffers must not overlap: every output value reads other input values
+  const char *i0 = (const char*)in, *i1 = i0 + 12 * io, *o0 = (const char*)out, *o1 = o0 + 12 * oo;
+  if (i0 < o1 && o0 < i1) return GS_E_INVALID;
+  const int d = device_ok();
+  if (d != GS_OK) return d;
+  return launched(launch_resize(in, out, a, (hipStream_t)stream));
 }
 
 size_t gs_mask_loss_workspace_size(int64_t n) {

@@ -27,6 +27,7 @@ struct ViewArgs {
   int32_t W, H, TX, TY;
   int32_t tile_off;    // first global tile of the view
   int32_t pix_off;     // first pixel of the view in the concatenated planes
+  float lowpass;       // s of Sigma' + sI for this view
 };
 
 struct ViewTable {

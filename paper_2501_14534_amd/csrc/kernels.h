@@ -21,7 +21,6 @@ struct ProjectArgs {
   float mask_thr;     // logit(mask_eps), rounded down to float
   float sh_mask_thr;  // logit(sh_mask_eps), rounded down to float
   float near_plane;
-  float lowpass;
   float inv_tw, inv_th;
   float4* splats;
   uint32_t* tiles_touched;
@@ -97,6 +96,49 @@ struct LossViews {
   int32_t total_blocks;
   float g[11];  // normalised Gaussian taps of the 11 x 11 window's 1-D factor
 };
+
+// Workgroup b of an image call: its view, colour plane and 16 x 16 tile.
+struct LossTile {
+  int view, plane, tx, ty;
+};
+
+__device__ __forceinline__ LossTile loss_tile(const LossViews& lv, int b) {
+  LossTile t;
+  int v = 0;
+  while (v + 1 < lv.nviews && b >= lv.v[v + 1].block_off) ++v;
+  const LossView& q = lv.v[v];
+  const int lb = b - q.block_off;
+  const int per_plane = q.TX * q.TY;
+  t.view = v;
+  t.plane = lb / per_plane;
+  const int r = lb - t.plane * per_plane;
+  t.ty = r / q.TX;
+  t.tx = r - t.ty * q.TX;
+  return t;
+}
+
+// Target blur: the views' 16 x 16 tiles, radius r = (k - 1) / 2 and the k taps.
+constexpr int kMaxBlurRadius = 15;
+struct BlurArgs {
+  LossViews views;
+  int32_t r;
+  float g[2 * kMaxBlurRadius + 1];
+};
+
+// Target resize: per view the input and output sizes and pixel offsets.
+struct ResizeView {
+  int32_t W, H, Wo, Ho;
+  int64_t in_off, out_off;
+  float inv_area;  // 1 / (W H)
+};
+struct ResizeArgs {
+  ResizeView v[GS_MAX_VIEWS];
+  int32_t nviews;
+  int64_t total_out;  // 3 * sum of W' H'
+};
+
+hipError_t launch_blur(const float* in, float* out, const BlurArgs& b, hipStream_t s);
+hipError_t launch_resize(const float* in, float* out, const ResizeArgs& a, hipStream_t s);
 
 hipError_t launch_loss(const LossViews& lv, const float* image, const float* target, float lambda, float* loss,
                        float* dL, float* dmap, float* bsum, double* per_view, hipStream_t s);

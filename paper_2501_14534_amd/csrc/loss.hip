@@ -31,25 +31,6 @@ constexpr int kLS = kLT + 2 * kLR;   // staged edge (26)
 constexpr float kSsimC1 = 0.0001f;   // (0.01)^2
 constexpr float kSsimC2 = 0.0009f;   // (0.03)^2
 
-struct LossTile {
-  int view, plane, tx, ty;
-};
-
-__device__ __forceinline__ LossTile loss_tile(const LossViews& lv, int b) {
-  LossTile t;
-  int v = 0;
-  while (v + 1 < lv.nviews && b >= lv.v[v + 1].block_off) ++v;
-  const LossView& q = lv.v[v];
-  const int lb = b - q.block_off;
-  const int per_plane = q.TX * q.TY;
-  t.view = v;
-  t.plane = lb / per_plane;
-  const int r = lb - t.plane * per_plane;
-  t.ty = r / q.TX;
-  t.tx = r - t.ty * q.TX;
-  return t;
-}
-
 // Staged value at (row, col) of the tile's window: zero outside the image.
 __device__ __forceinline__ float staged(const float* plane, int W, int H, int x0, int y0, int i) {
   const int r = i / kLS, c = i - r * kLS;

@@ -121,9 +121,9 @@ __global__ __launch_bounds__(256) void project_kernel(ProjectArgs a, ViewTable v
       const float sb0 = S00 * b0 + S01 * b1 + S02 * b2, sb1 = S01 * b0 + S11 * b1 + S12 * b2,
                   sb2 = S02 * b0 + S12 * b1 + S22 * b2;
       // Sigma' + sI (Sec. 3.2.4)
-      const float ca = a0 * sa0 + a1 * sa1 + a2 * sa2 + a.lowpass;
+      const float ca = a0 * sa0 + a1 * sa1 + a2 * sa2 + c.lowpass;
       const float cb = a0 * sb0 + a1 * sb1 + a2 * sb2;
-      const float cc = b0 * sb0 + b1 * sb1 + b2 * sb2 + a.lowpass;
+      const float cc = b0 * sb0 + b1 * sb1 + b2 * sb2 + c.lowpass;
       const float det = ca * cc - cb * cb;
       vis = det > 0.f;
       if (vis) {

@@ -327,9 +327,9 @@ __global__ __launch_bounds__(256) void project_bwd_geom_kernel(ProjectBwdArgs b,
       TS[rr][1] = Tm[rr][0] * Sig[1] + Tm[rr][1] * Sig[3] + Tm[rr][2] * Sig[4];
       TS[rr][2] = Tm[rr][0] * Sig[2] + Tm[rr][1] * Sig[4] + Tm[rr][2] * Sig[5];
     }
-    const double ca = TS[0][0] * Tm[0][0] + TS[0][1] * Tm[0][1] + TS[0][2] * Tm[0][2] + (double)a.lowpass;
+    const double ca = TS[0][0] * Tm[0][0] + TS[0][1] * Tm[0][1] + TS[0][2] * Tm[0][2] + (double)c.lowpass;
     const double cb = TS[0][0] * Tm[1][0] + TS[0][1] * Tm[1][1] + TS[0][2] * Tm[1][2];
-    const double cc = TS[1][0] * Tm[1][0] + TS[1][1] * Tm[1][1] + TS[1][2] * Tm[1][2] + (double)a.lowpass;
+    const double cc = TS[1][0] * Tm[1][0] + TS[1][1] * Tm[1][1] + TS[1][2] * Tm[1][2] + (double)c.lowpass;
     const double idet = 1.0 / (ca * cc - cb * cb);
     const double QA = cc * idet, QB = -cb * idet, QC = ca * idet;
     // dL/dSigma' = -Q G_Q Q

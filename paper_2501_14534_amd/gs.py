@@ -21,7 +21,8 @@ MAX_BATCH = 1024
 
 EXPORTS = ("gs_view_sizes", "gs_workspace_size", "gs_project", "gs_bin_sort", "gs_render_fwd", "gs_render_bwd",
            "gs_blend_bwd", "gs_project_bwd", "gs_loss_workspace_size", "gs_loss_l1_dssim", "gs_mask_loss_workspace_size", "gs_mask_loss",
-           "gs_count_hits", "gs_significance_workspace_size", "gs_significance", "gs_strerror")
+           "gs_count_hits", "gs_significance_workspace_size", "gs_significance", "gs_blur_views",
+           "gs_resize_views", "gs_strerror")
 
 vp = C.c_void_p
 
@@ -41,7 +42,7 @@ class GsOpts(C.Structure):
     _fields_ = [("near_plane", C.c_float), ("tan_clamp", C.c_float), ("lowpass", C.c_float),
                 ("bg", C.c_float * 3), ("tile_w", C.c_int32), ("tile_h", C.c_int32),
                 ("batch_depth", C.c_int32), ("pixels_per_thread", C.c_int32), ("subtile_cull", C.c_int32),
-                ("bwd_chunk", C.c_int32)]
+                ("bwd_chunk", C.c_int32), ("lowpass_progressive", C.c_int32)]
 
 
 class GsProjected(C.Structure):
@@ -109,6 +110,10 @@ def load():
     L.gs_significance_workspace_size.restype = C.c_size_t
     L.gs_significance.argtypes = [P(GsGaussians), vp, C.c_float, vp, vp, C.c_size_t, vp]
     L.gs_significance.restype = C.c_int
+    L.gs_blur_views.argtypes = [vp, vp, P(GsCamera), C.c_int32, C.c_int32, C.c_float, vp]
+    L.gs_blur_views.restype = C.c_int
+    L.gs_resize_views.argtypes = [vp, P(GsCamera), vp, P(GsCamera), C.c_int32, vp]
+    L.gs_resize_views.restype = C.c_int
     L.gs_strerror.argtypes = [C.c_int]
     L.gs_strerror.restype = C.c_char_p
     _lib = L
@@ -149,6 +154,7 @@ def options(o) -> GsOpts:
     s.batch_depth, s.pixels_per_thread = int(o.batch_depth), int(o.pixels_per_thread)
     s.subtile_cull = int(getattr(o, "subtile_cull", 1))
     s.bwd_chunk = int(getattr(o, "bwd_chunk", 1024))
+    s.lowpass_progressive = int(getattr(o, "lowpass_progressive", 0))
     return s
 
 
@@ -217,6 +223,14 @@ def significance_workspace_size() -> int:
 
 def significance(g, hits, volume_quantile, score, ws, ws_bytes, stream) -> int:
     return load().gs_significance(C.byref(g), hits, float(volume_quantile), score, ws, ws_bytes, stream)
+
+
+def blur_views(inp, out, cams_arr, V, ksize, sigma, stream) -> int:
+    return load().gs_blur_views(inp, out, cams_arr, V, int(ksize), float(sigma), stream)
+
+
+def resize_views(inp, in_cams_arr, out, out_cams_arr, V, stream) -> int:
+    return load().gs_resize_views(inp, in_cams_arr, out, out_cams_arr, V, stream)
 
 
 def mask_loss_workspace_size(n) -> int:

@@ -188,3 +188,28 @@ def test_significance_entry_points_validate_on_the_host(lib):
     assert f(C.byref(g), 4096, C.c_float(0.9), 4096, 4096, need, None) == gs.GS_E_INVALID
     g.mask_logits, g.mask_eps, g.n = None, 0.5, 1 << 32
     assert f(C.byref(g), 4096, C.c_float(0.9), 4096, 4096, need, None) == gs.GS_E_INVALID
+
+
+def test_target_entry_points_validate_on_the_host(lib):
+    wl = scenes.config(4, n=10)
+    cams = gs.cameras(wl.cams)
+    V = len(wl.cams)
+    f = lib.gs_blur_views
+    for k, s in ((4, 1.0), (0, 1.0), (33, 1.0), (9, 0.0), (9, -1.0), (9, float("nan"))):
+        assert f(4096, 1 << 40, cams, V, k, C.c_float(s), None) == gs.GS_E_INVALID, (k, s)
+    assert f(4096, 4096, cams, V, 9, C.c_float(2.4), None) == gs.GS_E_INVALID  # in place
+    assert f(None, 4096, cams, V, 9, C.c_float(2.4), None) == gs.GS_E_INVALID
+    assert f(4096, 1 << 40, cams, 0, 9, C.c_float(2.4), None) == gs.GS_E_INVALID
+    g = lib.gs_resize_views
+    small = gs.cameras(wl.cams)
+    for c in small:
+        c.width, c.height = max(1, c.width // 8), max(1, c.height // 8)
+    assert g(4096, cams, None, small, V, None) == gs.GS_E_INVALID
+    assert g(4096, cams, 4096 + 64, small, V, None) == gs.GS_E_INVALID  # overlapping buffers
+    bad = gs.cameras(wl.cams)
+    bad[1].height = 0
+    assert g(4096, bad, 1 << 40, small, V, None) == gs.GS_E_INVALID
+    assert g(4096, cams, 1 << 40, small, 0, None) == gs.GS_E_INVALID
+    o = gs.options(dataclasses.replace(wl.opts, lowpass_progressive=2))
+    t, p = C.c_int64(), C.c_int64()
+    assert lib.gs_view_sizes(cams, V, C.byref(o), C.byref(t), C.byref(p)) == gs.GS_E_INVALID
