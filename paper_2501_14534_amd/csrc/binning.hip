@@ -8,7 +8,9 @@
 //      descriptor (first tile, rect width and height, canonical offset, id).
 //   3. LSD radix sort of the visible records by their 32 depth bits (four
 //      8-bit passes; stable, so equal depths keep record order).
-//   4. emit_pairs: the records, now in depth order, emit one (tile, canonical
+//   4. gather_reduce gathers the descriptors into depth order once (the only
+//      random access of the emission) and sums the pairs per block;
+//      emit_pairs: the records, now in depth order, emit one (tile, canonical
 //      pair index, record id) per touched tile into a contiguous
 //      depth-ordered range; a block fills its range slot by slot (binary
 //      search of the owning record in LDS), so writes are coalesced and big
@@ -127,10 +129,41 @@ __global__ __launch_bounds__(1024) void scan_top(const uint32_t* __restrict__ su
   }
 }
 
+// Exclusive scans of two values per thread over a 256-thread block (one pass
+// of barriers for both).
+__device__ __forceinline__ void block_exclusive_scan2_256(uint32_t x, uint32_t y, uint32_t* ex, uint32_t* ey,
+                                                          uint32_t* tx, uint32_t* ty, uint2* s_wave) {
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  uint32_t ix = x, iy = y;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint32_t a = __shfl_up(ix, o, kWave), b = __shfl_up(iy, o, kWave);
+    if (lane >= o) ix += a, iy += b;
+  }
+  if (lane == kWave - 1) s_wave[wave] = make_uint2(ix, iy);
+  __syncthreads();
+  uint32_t ox = 0, oy = 0, sx = 0, sy = 0;
+#pragma unroll
+  for (int w = 0; w < kScanThreads / kWave; ++w) {
+    const uint2 c = s_wave[w];
+    ox += (w < wave) ? c.x : 0u;
+    oy += (w < wave) ? c.y : 0u;
+    sx += c.x;
+    sy += c.y;
+  }
+  __syncthreads();
+  *ex = ix - x + ox;
+  *ey = iy - y + oy;
+  *tx = sx;
+  *ty = sy;
+}
+
 // Canonical emission offsets of every record (pairs of record r occupy
 // [offsets[r], offsets[r] + tiles_touched[r]), records in index order), and
 // the visible records packed in record order as (depth bits, compact index)
-// with their emission descriptors; drec[r] = depth bits for the keys.
+// with their emission descriptors; drec[r] = depth bits for the keys.  The
+// block's 1024 records are taken in four slices of 256 consecutive records,
+// one per thread, so loads and stores are coalesced.
 __global__ __launch_bounds__(kScanThreads) void compact_visible(const float4* __restrict__ splats,
                                                                 const uint32_t* __restrict__ tt, int64_t nrec,
                                                                 int64_t n, ViewTable vt, float inv_tw, float inv_th,
@@ -141,30 +174,27 @@ __global__ __launch_bounds__(kScanThreads) void compact_visible(const float4* __
                                                                 uint32_t* __restrict__ dkey,
                                                                 uint32_t* __restrict__ dval, uint4* __restrict__ desc,
                                                                 uint32_t* __restrict__ drec) {
-  __shared__ uint32_t s_wave[kScanThreads / kWave];
+  __shared__ uint2 s_wave[kScanThreads / kWave];
   if (*status != 0) return;  // overflow: no lists this step
   const int64_t blk = (int64_t)blockIdx.x * kScanTile;
-  const int li0 = threadIdx.x * kScanItems;
-  uint32_t c[kScanItems];
-  uint32_t s = 0, v = 0;
+  uint32_t ex_base = block_offsets[blockIdx.x], vx_base = vis_offsets[blockIdx.x];
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    const int64_t r = blk + li0 + k;
-    c[k] = r < nrec ? tt[r] : 0u;
-    s += c[k];
-    v += c[k] != 0u;
-  }
-  uint32_t tot;
-  uint32_t ex = block_exclusive_scan_256(s, &tot, s_wave) + block_offsets[blockIdx.x];
-  uint32_t vx = block_exclusive_scan_256(v, &tot, s_wave) + vis_offsets[blockIdx.x];
-#pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    const int64_t r = blk + li0 + k;
+    const int64_t r = blk + k * kScanThreads + threadIdx.x;
+    const uint32_t c = r < nrec ? tt[r] : 0u;
+    uint32_t ex, vx, ts, tv;
+    block_exclusive_scan2_256(c, c != 0u ? 1u : 0u, &ex, &vx, &ts, &tv, s_wave);
+    ex += ex_base;
+    vx += vx_base;
+    ex_base += ts;
+    vx_base += tv;
     if (r < nrec) offsets[r] = ex;
-    if (c[k]) {
+    if (c) {
       const float4 p0 = splats[r * 3 + 0];
       const float4 p1 = splats[r * 3 + 1];
-      const ViewArgs& va = vt.v[(int)(r / n)];
+      int v = 0;
+      while (v + 1 < vt.nviews && r >= (int64_t)(v + 1) * n) ++v;
+      const ViewArgs& va = vt.v[v];
       int x0, y0, x1, y1;
       tile_rect(p0.x, p0.y, p1.z, inv_tw, inv_th, va.TX, va.TY, &x0, &y0, &x1, &y1);
       const uint32_t dbits = __float_as_uint(p1.w);  // depth > near plane > 0: bits order as values
@@ -173,28 +203,32 @@ __global__ __launch_bounds__(kScanThreads) void compact_visible(const float4* __
       desc[vx] = make_uint4((uint32_t)(va.tile_off + y0 * va.TX + x0),
                             (uint32_t)(x1 - x0 + 1) | ((uint32_t)(y1 - y0 + 1) << 16), ex, (uint32_t)r);
       if (drec) drec[r] = dbits;
-      ++vx;
     }
-    ex += c[k];
   }
 }
 
-// Per block of 1024 depth-sorted records: their number of pairs.
+// Per block of 1024 depth-sorted records: their descriptors gathered into
+// depth order (sdesc, read sequentially by emit_pairs) and their number of
+// pairs.
 __global__ __launch_bounds__(kScanThreads) void gather_reduce(const uint4* __restrict__ desc,
                                                               const uint32_t* __restrict__ dval,
                                                               const uint32_t* __restrict__ nvis,
                                                               const int32_t* __restrict__ status,
+                                                              uint4* __restrict__ sdesc,
                                                               uint32_t* __restrict__ block_sums) {
   __shared__ uint32_t s_wave[kScanThreads / kWave];
   const uint32_t N = effective_count(nvis, status);
-  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  const int64_t blk = (int64_t)blockIdx.x * kScanTile;
   uint32_t s = 0;
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k)
-    if (base + k < N) {
-      const uint32_t wh = desc[dval[base + k]].y;
-      s += (wh & 0xffffu) * (wh >> 16);
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t m = blk + k * kScanThreads + threadIdx.x;
+    if (m < N) {
+      const uint4 d = desc[dval[m]];
+      sdesc[m] = d;
+      s += (d.y & 0xffffu) * (d.y >> 16);
     }
+  }
   uint32_t tot;
   block_exclusive_scan_256(s, &tot, s_wave);
   if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
@@ -202,10 +236,11 @@ __global__ __launch_bounds__(kScanThreads) void gather_reduce(const uint4* __res
 
 // Emission in depth order: sorted record m emits, at depth-ordered positions
 // [eoff(m), eoff(m) + w h), its tiles in row-major order of its tile
-// rectangle: tile id, the pair's canonical index offsets[r] + j, and r.
-__global__ __launch_bounds__(kScanThreads) void emit_pairs(const uint4* __restrict__ desc,
-                                                           const uint32_t* __restrict__ dval,
-                                                           const uint32_t* __restrict__ nvis, int64_t n,
+// rectangle: tile id, the pair's canonical index offsets[r] + j, and r.  The
+// block's descriptors are staged in LDS with coalesced loads; each thread
+// then scans the pair counts of 4 consecutive records.
+__global__ __launch_bounds__(kScanThreads) void emit_pairs(const uint4* __restrict__ sdesc,
+                                                           const uint32_t* __restrict__ nvis,
                                                            const uint32_t* __restrict__ eblock_offsets,
                                                            const int32_t* __restrict__ status, ViewTable vt,
                                                            uint32_t* __restrict__ tkey, uint32_t* __restrict__ tval,
@@ -220,28 +255,36 @@ __global__ __launch_bounds__(kScanThreads) void emit_pairs(const uint4* __restri
   const uint32_t N = effective_count(nvis, status);
   const int64_t blk = (int64_t)blockIdx.x * kScanTile;
   if (blk >= N) return;  // uniform
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int li = k * kScanThreads + threadIdx.x;
+    const int64_t m = blk + li;
+    uint32_t cnt = 0u;
+    if (m < N) {
+      const uint4 d = sdesc[m];
+      const uint32_t w = d.y & 0xffffu;
+      cnt = w * (d.y >> 16);
+      int v = 0;  // view of the record's first tile
+      while (v + 1 < vt.nviews && d.x >= (uint32_t)vt.v[v + 1].tile_off) ++v;
+      s_base[li] = d.x;
+      s_w[li] = w;
+      s_off[li] = d.z;
+      s_rec[li] = d.w;
+      s_tx[li] = (uint32_t)vt.v[v].TX;
+    }
+    s_pref[li] = cnt;
+  }
+  __syncthreads();
   const int li0 = threadIdx.x * kScanItems;
   uint32_t c[kScanItems];
   uint32_t s = 0;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    const int64_t m = blk + li0 + k;
-    const int li = li0 + k;
-    c[k] = 0u;
-    if (m < N) {
-      const uint4 d = desc[dval[m]];
-      const uint32_t w = d.y & 0xffffu;
-      c[k] = w * (d.y >> 16);
-      s_base[li] = d.x;
-      s_w[li] = w;
-      s_off[li] = d.z;
-      s_rec[li] = d.w;
-      s_tx[li] = (uint32_t)vt.v[(int)((int64_t)d.w / n)].TX;
-    }
+    c[k] = s_pref[li0 + k];
     s += c[k];
   }
   uint32_t total;
-  uint32_t ex = block_exclusive_scan_256(s, &total, s_wave);
+  uint32_t ex = block_exclusive_scan_256(s, &total, s_wave);  // its barriers order the reads above
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     s_pref[li0 + k] = ex;
@@ -322,9 +365,13 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
 }
 
 // One stable scatter pass for 32-bit keys; NV value arrays travel with the
-// keys (NV = 1 or 2; the second may be null when NV = 1).  The block's 4096
-// elements are first ranked into LDS in (digit, index) order, then written
-// out run by run, so consecutive threads write consecutive addresses.
+// keys (NV = 1 or 2; the second may be null when NV = 1).  Each wave owns a
+// contiguous quarter (1024 elements) of the block's 4096 and ranks its items
+// in element order against wave-private running digit counts in LDS (match
+// by ballots; only the leader of a digit group updates the count), so the
+// ranking needs no block barrier.  Then one barrier, per-digit prefixes over
+// the four waves, the elements placed in LDS in (digit, index) order, and
+// written out run by run, so consecutive threads write consecutive addresses.
 template <int NV>
 __global__ __launch_bounds__(kSortThreads) void radix_scatter(const uint32_t* __restrict__ kin,
                                                               const uint32_t* __restrict__ vin,
@@ -336,11 +383,10 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter(const uint32_t* __
                                                               int64_t nblk, const uint32_t* __restrict__ hist,
                                                               const uint32_t* __restrict__ digit_total) {
   constexpr int kWaves = kSortThreads / kWave;
+  constexpr int kPerWave = kSortTile / kWaves;
   __shared__ uint32_t s_gbase[kRadix];  // global position of this block's first element of each digit
   __shared__ uint32_t s_lbase[kRadix];  // its position within the block's digit-ordered elements
-  __shared__ uint32_t s_run[kRadix];
-  __shared__ uint32_t s_cnt[kWaves][kRadix];
-  __shared__ uint32_t s_pre[kWaves][kRadix];
+  __shared__ uint32_t s_cnt[kWaves][kRadix];  // running counts per wave, then the waves' prefixes
   __shared__ uint32_t s_wave[kWaves];
   __shared__ uint32_t s_k[kSortTile];
   __shared__ uint32_t s_v[kSortTile];
@@ -350,53 +396,55 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter(const uint32_t* __
   if (base >= K) return;  // uniform across the block
   const int nvalid = (int)min((int64_t)kSortTile, (int64_t)K - base);
   const int t = threadIdx.x, lane = t & (kWave - 1), wave = t / kWave;
-  uint32_t key[kSortItems];
-  uint32_t val[kSortItems], val2[NV == 2 ? kSortItems : 1];
-  s_run[t] = 0;
 #pragma unroll
   for (int w = 0; w < kWaves; ++w) s_cnt[w][t] = 0;
   __syncthreads();
+  uint32_t key[kSortItems], val[kSortItems], val2[NV == 2 ? kSortItems : 1], rk[kSortItems];
+  const uint64_t lt_mask = (1ull << lane) - 1ull;
+  uint32_t* cnt = s_cnt[wave];
 #pragma unroll
   for (int k = 0; k < kSortItems; ++k) {
-    const int li = k * kSortThreads + t;
-    if (li < nvalid) {
-      key[k] = kin[base + li];
-      val[k] = vin[base + li];
-      if (NV == 2) val2[k] = vin2[base + li];
-      atomicAdd(&s_run[(key[k] >> shift) & (kRadix - 1)], 1u);  // the block's digit counts
-    }
+    const int li = wave * kPerWave + k * kWave + lane;
+    const bool valid = li < nvalid;
+    key[k] = valid ? kin[base + li] : 0u;
+    val[k] = valid ? vin[base + li] : 0u;
+    if (NV == 2) val2[k] = valid ? vin2[base + li] : 0u;
+  }
+#pragma unroll
+  for (int k = 0; k < kSortItems; ++k) {
+    const int li = wave * kPerWave + k * kWave + lane;
+    const bool valid = li < nvalid;
+    const uint32_t d = (key[k] >> shift) & (kRadix - 1);
+    const uint64_t peers = match_digit(d, valid);
+    const uint32_t r = __popcll(peers & lt_mask);
+    const uint32_t c = valid ? cnt[d] : 0u;  // elements of digit d earlier in this wave
+    rk[k] = c + r;
+    if (valid && r == 0) cnt[d] = c + (uint32_t)__popcll(peers);
+    __builtin_amdgcn_wave_barrier();  // the wave's LDS updates stay in item order
   }
   __syncthreads();
-  uint32_t tot;
-  const uint32_t lb = block_exclusive_scan_256(s_run[t], &tot, s_wave);
-  const uint32_t dbase = block_exclusive_scan_256(digit_total[t], &tot, s_wave);
-  s_lbase[t] = lb;
-  s_gbase[t] = dbase + hist[(int64_t)t * nblk + blockIdx.x];
-  s_run[t] = lb;
+  {
+    // digit t: the waves' prefixes and the block's count
+    uint32_t run = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+      const uint32_t c = s_cnt[w][t];
+      s_cnt[w][t] = run;
+      run += c;
+    }
+    uint32_t tot;
+    const uint32_t lb = block_exclusive_scan_256(run, &tot, s_wave);
+    const uint32_t dbase = block_exclusive_scan_256(digit_total[t], &tot, s_wave);
+    s_lbase[t] = lb;
+    s_gbase[t] = dbase + hist[(int64_t)t * nblk + blockIdx.x];
+  }
   __syncthreads();
-  const uint64_t lt_mask = (1ull << lane) - 1ull;
 #pragma unroll
   for (int k = 0; k < kSortItems; ++k) {
-    const int li = k * kSortThreads + t;
-    const bool valid = li < nvalid;
-    const uint32_t d = valid ? (key[k] >> shift) & (kRadix - 1) : 0u;
-    const uint64_t peers = match_digit(d, valid);
-    const uint32_t rank = __popcll(peers & lt_mask);
-    if (valid && rank == 0) s_cnt[wave][d] = __popcll(peers);
-    __syncthreads();
-    {
-      uint32_t r = s_run[t];
-#pragma unroll
-      for (int w = 0; w < kWaves; ++w) {
-        s_pre[w][t] = r;
-        r += s_cnt[w][t];
-        s_cnt[w][t] = 0;
-      }
-      s_run[t] = r;
-    }
-    __syncthreads();
-    if (valid) {
-      const uint32_t pos = s_pre[wave][d] + rank;  // within the block
+    const int li = wave * kPerWave + k * kWave + lane;
+    if (li < nvalid) {
+      const uint32_t d = (key[k] >> shift) & (kRadix - 1);
+      const uint32_t pos = s_lbase[d] + cnt[d] + rk[k];
       s_k[pos] = key[k];
       s_v[pos] = val[k];
       if (NV == 2) s_v2[pos] = val2[k];
@@ -503,6 +551,7 @@ struct SortWs {
   uint32_t* dkey_alt;
   uint32_t* dval_alt;
   uint4* desc;              // [nrec] emission descriptors of the visible records (compact index)
+  uint4* sdesc;             // [nrec] the same in depth order
   uint32_t* drec;           // [nrec] depth bits by record (for the keys)
   uint32_t* tkey;           // [capacity] tile id of each pair
   uint32_t* tkey_alt;
@@ -536,6 +585,7 @@ static SortWs carve(const SortPlan& p, uint64_t capacity, void* ws) {
   w.dkey_alt = take(4 * nrec);
   w.dval_alt = take(4 * nrec);
   w.desc = (uint4*)take(16 * nrec);
+  w.sdesc = (uint4*)take(16 * nrec);
   w.drec = take(4 * nrec);
   w.tkey = take(4 * (size_t)capacity);
   w.tkey_alt = take(4 * (size_t)capacity);
@@ -595,13 +645,13 @@ hipError_t launch_bin_sort(const SortPlan& plan, const float4* splats, const uin
     radix_sort<uint32_t, 1>(w.dkey, w.dval, nullptr, w.dkey_alt, w.dval_alt, nullptr, 4, w.nvis, status,
                             plan.rec_sort_blocks, w, s);
     hipLaunchKernelGGL(gather_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, w.desc, w.dval, w.nvis, status,
-                       w.eblock_sums);
+                       w.sdesc, w.eblock_sums);
     hipLaunchKernelGGL(scan_top, dim3(1), dim3(1024), 0, s, w.eblock_sums, nb, w.eblock_offsets, (uint64_t)0,
                        w.nvis + 1, (int32_t*)nullptr);  // total unused (equals K)
     // emit so that the tile sort ends in (tkey, pair_index, ids)
     const bool even = plan.tile_passes % 2 == 0;
-    hipLaunchKernelGGL(emit_pairs, dim3((unsigned)nb), dim3(kScanThreads), 0, s, w.desc, w.dval, w.nvis, n,
-                       w.eblock_offsets, status, vt, even ? w.tkey : w.tkey_alt, even ? out.pair_index : w.tval_alt,
+    hipLaunchKernelGGL(emit_pairs, dim3((unsigned)nb), dim3(kScanThreads), 0, s, w.sdesc, w.nvis, w.eblock_offsets,
+                       status, vt, even ? w.tkey : w.tkey_alt, even ? out.pair_index : w.tval_alt,
                        even ? out.ids : w.trec_alt);
     if (even)
       radix_sort<uint32_t, 2>(w.tkey, out.pair_index, out.ids, w.tkey_alt, w.tval_alt, w.trec_alt, plan.tile_passes,
