@@ -54,6 +54,7 @@ def parse():
     ap.add_argument("--ppt", type=int, default=None)
     ap.add_argument("--cull", type=int, default=None, choices=[0, 1], help="sub-tile culling override")
     ap.add_argument("--bwd-chunk", type=int, default=None, help="backward chunk length override (0: one per tile)")
+    ap.add_argument("--fwd-chunk", type=int, default=None, help="forward chunk length override (0: one per tile)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target CPU work of the oracle sample")
     ap.add_argument("--calibration-copy-bytes", type=int, default=0,
                     help="also launch a plain copy kernel (elementwise x1) of this many bytes, for counter scaling")
@@ -124,6 +125,8 @@ def main():
         opts = dataclasses.replace(opts, subtile_cull=args.cull)
     if args.bwd_chunk is not None:
         opts = dataclasses.replace(opts, bwd_chunk=args.bwd_chunk)
+    if args.fwd_chunk is not None:
+        opts = dataclasses.replace(opts, fwd_chunk=args.fwd_chunk)
     sc = wl.scene
     V = len(wl.cams)
     pixels = wl.pixels
@@ -307,7 +310,7 @@ def main():
                    "resolutions": [f"{c.width}x{c.height}" for c in wl.cams], "sh_degree": sc.sh_degree,
                    "tile": f"{opts.tile_w}x{opts.tile_h}", "batch_depth": opts.batch_depth,
                    "pixels_per_thread": opts.pixels_per_thread, "subtile_cull": opts.subtile_cull,
-                   "bwd_chunk": opts.bwd_chunk,
+                   "bwd_chunk": opts.bwd_chunk, "fwd_chunk": opts.fwd_chunk,
                    "graph": not args.no_graph},
         "per_view": per_view,
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},

@@ -95,6 +95,12 @@ typedef struct gs_opts {
                                 two in [16, 2^20], or 0 for one item per tile.  The forward
                                 records each pixel's state at every multiple of bwd_chunk so
                                 the backward can walk the chunks of one long list in parallel. */
+  int32_t fwd_chunk;         /* entries of a tile's list per forward work item: a power of two
+                                in [64, 2^24], or 0 for one item per tile.  Longer lists are
+                                walked in chunks in parallel: each chunk starts from the product
+                                of the earlier chunks' (1 - alpha) factors, computed by a
+                                product pass first; the image equals the single walk's up to
+                                rounding.  Needs more workspace (gs_workspace_size). */
   int32_t lowpass_progressive; /* 1: progressive scaling (Sec. 3.2.4): view v uses
                                   s_v = max(lowpass, W_v H_v / (9 pi n)) for the n Gaussians of
                                   the call (computed in double, rounded to float); 0: s = lowpass */

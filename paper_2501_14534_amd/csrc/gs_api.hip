@@ -54,6 +54,7 @@ bool opts_ok(const gs_opts* o) {
   if (o->batch_depth < 1 || o->batch_depth > GS_MAX_BATCH) return false;
   if (o->subtile_cull != 0 && o->subtile_cull != 1) return false;
   if (o->bwd_chunk != 0 && (!pow2(o->bwd_chunk) || o->bwd_chunk < 16 || o->bwd_chunk > (1 << 20))) return false;
+  if (o->fwd_chunk != 0 && (!pow2(o->fwd_chunk) || o->fwd_chunk < 64 || o->fwd_chunk > (1 << 24))) return false;
   if (!std::isfinite(o->lowpass) || o->lowpass < 0.0f) return false;
   if (o->lowpass_progressive != 0 && o->lowpass_progressive != 1) return false;
   if (!std::isfinite(o->near_plane) || !(o->near_plane > 0.0f)) return false;  // depths > 0 order as bits
@@ -145,15 +146,36 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // Chunk length of the backward work items (2^31: one item per tile).
 int log2_chunk(const gs_opts* o) { return o->bwd_chunk ? ilog2(o->bwd_chunk) : 31; }
 int64_t chunk_slots(uint64_t capacity, const gs_opts* o) { return (int64_t)(capacity >> log2_chunk(o)) + 1; }
+int log2_fchunk(const gs_opts* o) { return o->fwd_chunk ? ilog2(o->fwd_chunk) : 31; }
+int64_t fchunk_slots(uint64_t capacity, const gs_opts* o) {
+  return o->fwd_chunk ? (int64_t)(capacity >> log2_fchunk(o)) + 1 : 0;
+}
 
 // Per-chunk pixel states, after the backward's own regions in the workspace:
 // slot owners [slots] u32, then states [slots][tile pixels] float4.
 size_t state_owner_bytes(uint64_t capacity, const gs_opts* o) {
   return align256(sizeof(uint32_t) * (size_t)chunk_slots(capacity, o));
 }
+// Forward chunking: owners [fslots] u32, products [fslots][px] f32, results
+// [2 fslots][px] float4 and [2 fslots][px] i32, suffix colours [fslots][px] float4.
+struct FwdChunkWs {
+  size_t owner, prod, res, last, suf, bytes;
+};
+FwdChunkWs fwd_chunk_ws(uint64_t capacity, const gs_opts* o) {
+  const size_t fs = (size_t)fchunk_slots(capacity, o), px = (size_t)(o->tile_w * o->tile_h);
+  FwdChunkWs w;
+  w.owner = 0;
+  w.prod = w.owner + align256(4 * fs);
+  w.res = w.prod + align256(4 * fs * px);
+  w.last = w.res + align256(16 * 2 * fs * px);
+  w.suf = w.last + align256(4 * 2 * fs * px);
+  w.bytes = w.suf + align256(16 * fs * px);
+  return w;
+}
 size_t render_state_bytes(uint64_t capacity, const gs_opts* o) {
   return state_owner_bytes(capacity, o) +
-         align256(16 * (size_t)chunk_slots(capacity, o) * (size_t)(o->tile_w * o->tile_h));
+         align256(16 * (size_t)chunk_slots(capacity, o) * (size_t)(o->tile_w * o->tile_h)) +
+         (o->fwd_chunk ? fwd_chunk_ws(capacity, o).bytes : 0);
 }
 
 RenderArgs render_args(const gs_projected* p, const gs_binning* b, const gs_opts* o) {
@@ -190,6 +212,13 @@ RenderArgs render_args(const gs_projected* p, const gs_binning* b, const gs_opts
   a.state = nullptr;
   a.hits = nullptr;
   a.n = 0;
+  a.log2_fchunk = log2_fchunk(o);
+  a.nfslots = fchunk_slots(b->capacity, o);
+  a.fslot_owner = nullptr;
+  a.fprod = nullptr;
+  a.fres = nullptr;
+  a.flast = nullptr;
+  a.fsuf = nullptr;
   return a;
 }
 
@@ -220,6 +249,16 @@ void attach_state(RenderArgs* a, uint64_t capacity, int64_t nrec, const gs_opts*
   char* base = (char*)ws + bwd_ws_bytes(capacity, nrec);
   a->slot_owner = (uint32_t*)base;
   a->state = (float4*)(base + state_owner_bytes(capacity, o));
+  if (o->fwd_chunk) {
+    char* f = base + state_owner_bytes(capacity, o) +
+              align256(16 * (size_t)chunk_slots(capacity, o) * (size_t)(o->tile_w * o->tile_h));
+    const FwdChunkWs w = fwd_chunk_ws(capacity, o);
+    a->fslot_owner = (uint32_t*)(f + w.owner);
+    a->fprod = (float*)(f + w.prod);
+    a->fres = (float4*)(f + w.res);
+    a->flast = (int32_t*)(f + w.last);
+    a->fsuf = (float4*)(f + w.suf);
+  }
 }
 
 ProjectBwdArgs project_bwd_args(ProjectArgs pa, const gs_opts* opts, const gs_projected* proj, const gs_binning* bins,

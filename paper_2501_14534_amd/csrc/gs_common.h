@@ -66,23 +66,35 @@ __device__ __forceinline__ bool tile_rect(float u, float v, float r, float inv_t
   return true;
 }
 
+// exp(-q/2) = exp2(k q) with k = -log2(e)/2.  The walks stage each record
+// with its conic scaled for that: (a, b, c) = (k A, 2 k B, k C), so the
+// exponent is dx (a dx + b dy) + c dy dy.
+constexpr float kQScale = -0.5f * kLog2e;
+__device__ __forceinline__ float4 staged_a(float4 ra) {  // (u, v, a, b)
+  return make_float4(ra.x, ra.y, kQScale * ra.z, (2.0f * kQScale) * ra.w);
+}
+__device__ __forceinline__ float4 staged_b(float4 rb) {  // (c, o', radius, depth)
+  return make_float4(kQScale * rb.x, rb.y, rb.z, rb.w);
+}
+
 // One (pixel, splat) evaluation shared bit-for-bit by the forward and the
-// backward walks: square test, Gaussian falloff G and alpha = min(0.99, o' G).
-// Every operation is explicit (no contraction), so both kernels take identical
-// skip/stop decisions.  Returns false when the pixel is outside the square.
+// backward walks (both stage the same scaled conic): square test, Gaussian
+// falloff G and alpha = min(0.99, o' G).  Every operation is explicit (fused
+// multiply-adds written out, no other contraction), so both kernels take
+// identical skip/stop decisions.  Computed without branching; returns the
+// square test's outcome.
 struct Eval {
   float dx, dy, G, raw, alpha;
 };
 
-// eval_splat_all computes the same values without branching and returns the
-// square test's outcome; eval_splat skips the falloff outside the square.
-__device__ __forceinline__ bool eval_splat_all(float px, float py, float u, float v, float A, float B, float C,
+__device__ __forceinline__ bool eval_splat_all(float px, float py, float u, float v, float a, float b, float c,
                                                float o, float rad, Eval* e) {
 #pragma clang fp contract(off)
   const float dx = px - u;
   const float dy = py - v;
-  const float q = A * dx * dx + 2.0f * B * dx * dy + C * dy * dy;
-  const float G = __builtin_amdgcn_exp2f(q * (-0.5f * kLog2e));
+  const float t = __builtin_fmaf(b, dy, a * dx);
+  const float ex = __builtin_fmaf(dx, t, (c * dy) * dy);
+  const float G = __builtin_amdgcn_exp2f(ex);
   const float raw = o * G;
   e->dx = dx;
   e->dy = dy;
@@ -90,23 +102,6 @@ __device__ __forceinline__ bool eval_splat_all(float px, float py, float u, floa
   e->raw = raw;
   e->alpha = fminf(kAlphaMax, raw);
   return fabsf(dx) <= rad && fabsf(dy) <= rad;
-}
-
-__device__ __forceinline__ bool eval_splat(float px, float py, float u, float v, float A, float B, float C, float o,
-                                           float rad, Eval* e) {
-#pragma clang fp contract(off)
-  const float dx = px - u;
-  const float dy = py - v;
-  if (!(fabsf(dx) <= rad && fabsf(dy) <= rad)) return false;
-  const float q = A * dx * dx + 2.0f * B * dx * dy + C * dy * dy;
-  const float G = __builtin_amdgcn_exp2f(q * (-0.5f * kLog2e));
-  const float raw = o * G;
-  e->dx = dx;
-  e->dy = dy;
-  e->G = G;
-  e->raw = raw;
-  e->alpha = fminf(kAlphaMax, raw);
-  return true;
 }
 
 // Sum over the 64 lanes of a wave, result valid in lane 63.  Row-local

@@ -51,6 +51,20 @@ struct RenderArgs {
   // hit counting (Eq. 4): per-Gaussian counters, n Gaussians per view
   uint32_t* hits;
   int64_t n;
+  // forward chunking: lists longer than 2^log2_fchunk entries (31: off) are
+  // walked in chunks by separate workgroups.  Forward boundary q = start + kF
+  // (k >= 1) owns slot q >> log2_fchunk: fslot_owner[slot] = global tile;
+  // fprod[slot][pixel] = product of (1 - alpha) over the chunk ending at q;
+  // fres/flast[slot] = (colour, final T) / last index of the chunk ending at
+  // q, and at [nfslots + slot] those of a list's last chunk starting at q;
+  // fsuf[slot] = colour composited from q on (read by the backward).
+  int32_t log2_fchunk;
+  int64_t nfslots;
+  uint32_t* fslot_owner;
+  float* fprod;
+  float4* fres;
+  int32_t* flast;
+  float4* fsuf;
 };
 
 struct BinOut {

@@ -18,7 +18,9 @@
 // Forward: lanes whose pixels have terminated drop out of the walk through
 // the exec mask; a wave stops walking once all its pixels are done, and
 // before each batch the waves vote and the workgroup leaves once every pixel
-// is done.
+// is done.  Long lists can be split into forward chunks walked in parallel
+// (a product pass gives each chunk its starting transmittance; see
+// render_fwd_kernel), which shortens the critical path of the deepest tiles.
 //
 // Backward: the list is re-walked back to front from the tile's largest
 // last_contrib; each pixel recovers the transmittance in front of a splat by
@@ -256,19 +258,68 @@ __device__ __forceinline__ float reduce_scatter9(const float (&x)[GS_GRAD_FLOATS
   return v;
 }
 
-// COUNT: the same walk, counting instead of blending: per Gaussian, the
-// number of pixels where it is composited (the ray hits of Eq. 4), added to
-// a.hits; no image, no chunk states.  Per record and batch, the waves add
-// their ballot counts into an LDS counter (in place of the staged colours),
-// which is flushed to the Gaussian's global counter once the batch is walked.
-template <int PPT, bool CULL, bool COUNT>
+// Walk modes of the forward kernel.
+//   kFull:  Eq. 2 over one forward chunk of a tile's list (the whole list when
+//           forward chunking is off): the image, or the chunk's results.
+//   kCount: the same walk, counting instead of blending: per Gaussian, the
+//           number of pixels where it is composited (the ray hits of Eq. 4),
+//           added to a.hits; no image, no chunk states.  Per record and batch,
+//           the waves add their ballot counts into an LDS counter (in place
+//           of the staged colours), flushed to the Gaussian's global counter
+//           once the batch is walked.
+//   kTPass: the product of (1 - alpha) over the chunk's splats that pass the
+//           skip and square tests, ignoring the stop rule (stopped once under
+//           1e-4, where its value no longer matters).
+//
+// Forward chunking.  A list longer than F = 2^log2_fchunk entries is split
+// into chunks [start + kF, start + (k+1)F).  Three launches: every tile's
+// first chunk (the only launch without chunking), which also leaves each
+// pixel's transmittance after it (0 if it stopped) as the product P_0; the
+// product pass over chunks 1 .. m-2, for the pixels still going after chunk
+// 0 only; the full walk of chunks 1 .. m-1.  Chunk k starts from T_in =
+// P_0 ... P_{k-1}: a pixel whose product fell under 1e-4 stopped in an
+// earlier chunk (T only decreases), and otherwise T_in is its transmittance.
+// Each chunk of a long list stores its colour, final T and last index;
+// fwd_combine_kernel adds them up.  The critical path of a deep tile becomes
+// about three chunks instead of its whole list.
+enum : int { kFull = 0, kCount = 1, kTPass = 2 };
+
+template <int PPT, bool CULL, int MODE>
 __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable vt, float* __restrict__ image,
-                                                         float* __restrict__ T_final, int32_t* __restrict__ last_out) {
+                                                         float* __restrict__ T_final, int32_t* __restrict__ last_out,
+                                                         int64_t item_base) {
+  constexpr bool COUNT = MODE == kCount, TPASS = MODE == kTPass;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_alive[4];
   __shared__ Box s_box[4];
-  const int gtile = tile_of_block(a);
+  // Work items (blockIdx.x + item_base): [0, nfslots) are the forward chunks
+  // that start at a forward boundary (slot order); the rest are each tile's
+  // first chunk, in the tile schedule.  Counting launches have no chunk items.
+  const int lf = COUNT ? 31 : a.log2_fchunk;
+  const int64_t nfs = COUNT ? 0 : a.nfslots;
+  const int64_t item = (int64_t)blockIdx.x + item_base;
+  int gtile;
+  bool first;
+  if (item < nfs) {
+    const uint32_t owner = a.fslot_owner[item];
+    if (owner >= (uint32_t)vt.total_tiles) return;  // no boundary here (uniform)
+    gtile = (int)owner;
+    first = false;
+  } else {
+    const int b = (int)(item - nfs);
+    gtile = a.order ? (int)a.order[b] : b;
+    first = true;
+  }
   const TileCtx tc = tile_ctx(vt, a, gtile);
+  const uint64_t fmask = (1ull << lf) - 1;
+  const uint64_t cs64 = first ? (uint64_t)tc.start : (((uint64_t)item << lf) | ((uint64_t)tc.start & fmask));
+  if (!first && !(cs64 > (uint64_t)tc.start && cs64 < (uint64_t)tc.end)) return;  // a record not of this list
+  const uint32_t cs = (uint32_t)cs64;
+  const uint32_t ce = (uint32_t)min(cs64 + (1ull << lf), (uint64_t)tc.end);
+  const uint32_t len = tc.end - tc.start;
+  const uint32_t nfc = len == 0 ? 1u : (uint32_t)(((uint64_t)len + fmask) >> lf);  // forward chunks of the list
+  const uint32_t kf = (uint32_t)((cs64 - tc.start) >> lf);                           // this chunk
+  if (TPASS && (kf == 0 || kf + 1 == nfc)) return;  // chunk 0 leaves its own; the last one is not needed
   const ViewArgs& va = vt.v[tc.view];
   const int nthreads = blockDim.x;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave, nwaves = nthreads / kWave;
@@ -281,9 +332,10 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable
   if (COUNT)
     for (int i = threadIdx.x; i < a.batch; i += blockDim.x) s_hits[i] = 0u;
 
-  // C: colour composited so far (the image); S: colour composited since the
-  // last chunk boundary (kept apart so that the colour after a boundary is a
-  // sum of non-negative segments, accurate relative to itself)
+  // C: colour composited so far (the image, summed in list order whatever
+  // the tiling); S: colour composited since the last chunk boundary (kept
+  // apart so that the colour after a boundary is a sum of non-negative
+  // segments, accurate relative to itself)
   float px[PPT], py[PPT], T[PPT], C0[PPT], C1[PPT], C2[PPT], S0[PPT], S1[PPT], S2[PPT];
   int last[PPT];
   bool done[PPT];
@@ -301,21 +353,45 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable
   }
 
   const int tpx = 1 << (a.log2_tw + a.log2_th);
-  const int lc = COUNT ? 31 : a.log2_chunk;  // counting records no chunk states
+  const int lc = (COUNT || TPASS) ? 31 : a.log2_chunk;  // counting and products record no chunk states
+  // chunk k >= 1 starts from the product of the earlier chunks' products
+  bool dead[PPT];
+#pragma unroll
+  for (int p = 0; p < PPT; ++p) dead[p] = false;
+  if (MODE == kFull && kf > 0) {
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+      float t = 1.0f;
+      for (uint32_t j = 1; j <= kf; ++j)
+        t *= a.fprod[(int64_t)(((uint64_t)tc.start + ((uint64_t)j << lf)) >> lf) * tpx + threadIdx.x * PPT + p];
+      T[p] = t;
+      dead[p] = !done[p] && t < kTMin;
+      done[p] = done[p] || dead[p];
+    }
+  }
+  if (TPASS) {  // only the pixels still going after chunk 0
+    const float* p0 = a.fprod + (int64_t)(((uint64_t)tc.start + (1ull << lf)) >> lf) * tpx;
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) done[p] = done[p] || p0[threadIdx.x * PPT + p] < kTMin;
+  }
   int nbnd = 0;  // chunk boundaries recorded (uniform)
+  // first backward boundary this walk can record: the first multiple of 2^lc
+  // (relative to the list start) at or after cs, never the list start
+  uint64_t b0 = (uint64_t)tc.start + ((((uint64_t)cs - tc.start) + ((1ull << lc) - 1)) >> lc << lc);
+  if (b0 == (uint64_t)tc.start) b0 += 1ull << lc;
   // batches never straddle a chunk boundary
-  auto batch_end = [&](uint32_t b0) -> uint32_t {
-    const uint64_t rel = b0 - tc.start;
+  auto batch_end = [&](uint32_t b) -> uint32_t {
+    const uint64_t rel = b - tc.start;
     const uint64_t next = (uint64_t)tc.start + (((rel >> lc) + 1) << lc);
-    return (uint32_t)min(min((uint64_t)tc.end, (uint64_t)b0 + (uint64_t)a.batch), next);
+    return (uint32_t)min(min((uint64_t)ce, (uint64_t)b + (uint64_t)a.batch), next);
   };
   // Software-pipelined gather: while a batch is walked, thread t holds the
   // record of entry t of the next batch (loads in flight) and the id of entry
   // t of the batch after it.
   const int t = threadIdx.x;
-  uint32_t bs = tc.start;
-  uint32_t be = bs < tc.end ? batch_end(bs) : bs;
-  uint32_t be2 = be < tc.end ? batch_end(be) : be;
+  uint32_t bs = cs;
+  uint32_t be = bs < ce ? batch_end(bs) : bs;
+  uint32_t be2 = be < ce ? batch_end(be) : be;
   float4 pa = make_float4(0.f, 0.f, 0.f, 0.f), pb = pa, pc = pa;
   uint32_t nid = 0;
   if (bs + t < be) {
@@ -325,7 +401,7 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable
     if (!COUNT) pc = a.splats[(size_t)rec * 3 + 2];
   }
   if (be + t < be2) nid = a.ids[be + t];
-  while (bs < tc.end) {
+  while (bs < ce) {
     bool alive = false, live[PPT];
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
@@ -343,7 +419,7 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable
     for (int w = 0; w < nwaves; ++w) any |= s_alive[w];
     if (!any) break;
     const uint64_t rel = bs - tc.start;
-    if (!COUNT && rel != 0 && (rel & ((1ull << lc) - 1)) == 0) {
+    if (MODE == kFull && rel != 0 && (rel & ((1ull << lc) - 1)) == 0) {
       // a chunk boundary of the backward: record each pixel's transmittance
       // here and the colour of the chunk that ends here, then start a new chunk
       const int64_t slot = (int64_t)(bs >> lc);
@@ -358,8 +434,8 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable
     }
     const int cnt = (int)(be - bs);
     if (t < cnt) {  // entry t from the registers
-      s_a[t] = pa;
-      s_b[t] = pb;
+      s_a[t] = staged_a(pa);
+      s_b[t] = staged_b(pb);
       if (!COUNT) s_c[t] = pc;
       if (CULL) s_mask[t] = (uint8_t)footprint_mask(pa, pb, nwaves, s_box);
     }
@@ -367,13 +443,13 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable
       const uint32_t rec = a.ids[bs + i];
       const float4 ra = a.splats[(size_t)rec * 3 + 0];
       const float4 rb = a.splats[(size_t)rec * 3 + 1];
-      s_a[i] = ra;
-      s_b[i] = rb;
+      s_a[i] = staged_a(ra);
+      s_b[i] = staged_b(rb);
       if (!COUNT) s_c[i] = a.splats[(size_t)rec * 3 + 2];
       if (CULL) s_mask[i] = (uint8_t)footprint_mask(ra, rb, nwaves, s_box);
     }
     // issue the next batch's record loads and the following batch's id loads
-    const uint32_t be3 = be2 < tc.end ? batch_end(be2) : be2;
+    const uint32_t be3 = be2 < ce ? batch_end(be2) : be2;
     if (be + t < be2) {
       pa = a.splats[(size_t)nid * 3 + 0];
       pb = a.splats[(size_t)nid * 3 + 1];
@@ -402,7 +478,8 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable
           const float Tn = T[p] * (1.0f - e.alpha);
           const bool stop = use && Tn < kTMin;  // stop before this splat
           done[p] = done[p] || stop;
-          const bool take = use && !stop;
+          // the product pass multiplies the stopping splat in as well
+          const bool take = TPASS ? use : use && !stop;
           const float w = take ? e.alpha * T[p] : 0.0f;
           C0[p] += rc.x * w;
           C1[p] += rc.y * w;
@@ -454,10 +531,16 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable
   }
 
   if (COUNT) return;
-  // Each recorded state becomes (T there, colour composited after it): the
-  // suffix sums of the chunks' colours, last chunk first.
-  for (int k = nbnd; k >= 1; --k) {
-    const int64_t slot = (int64_t)(((uint64_t)tc.start + ((uint64_t)k << lc)) >> lc);
+  if (TPASS) {  // the product, at the boundary that ends this chunk
+    float* fp = a.fprod + (int64_t)((uint64_t)ce >> lf) * tpx;
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) fp[threadIdx.x * PPT + p] = T[p];
+    return;
+  }
+  // Each recorded state becomes (T there, colour composited after it within
+  // this walk): the suffix sums of the segments' colours, last one first.
+  for (int k = nbnd - 1; k >= 0; --k) {
+    const int64_t slot = (int64_t)((b0 + ((uint64_t)k << lc)) >> lc);
     float4* st = a.state + slot * tpx;
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
@@ -473,6 +556,20 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable
     }
   }
 
+  if (nfc > 1) {
+    // one chunk of several: its colour, final T and last index (-1: the pixel
+    // had stopped before the chunk), at the boundary that ends it, or for the
+    // last chunk at the one that starts it (second half of the arrays); the
+    // first chunk also leaves P_0 (0 for the pixels that stopped in it)
+    const int64_t idx = kf + 1 < nfc ? (int64_t)((uint64_t)ce >> lf) : a.nfslots + (int64_t)((uint64_t)cs >> lf);
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+      a.fres[idx * tpx + threadIdx.x * PPT + p] = make_float4(C0[p], C1[p], C2[p], T[p]);
+      a.flast[idx * tpx + threadIdx.x * PPT + p] = dead[p] ? -1 : last[p];
+      if (kf == 0) a.fprod[idx * tpx + threadIdx.x * PPT + p] = done[p] ? 0.0f : T[p];
+    }
+    return;
+  }
   const int64_t plane = (int64_t)va.W * va.H;
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
@@ -488,6 +585,71 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable
     }
   }
 }
+
+// Forward chunking: the tiles with several chunks.  Per pixel, the chunks'
+// colours are added from the last one down (giving the colour composited
+// from each forward boundary on, which the backward adds to its chunk
+// states), the final T is the one of the last chunk the pixel entered alive,
+// and the last index the largest.  One workgroup per tile, in the schedule.
+template <int PPT>
+__global__ __launch_bounds__(256) void fwd_combine_kernel(RenderArgs a, ViewTable vt, float* __restrict__ image,
+                                                          float* __restrict__ T_final,
+                                                          int32_t* __restrict__ last_out) {
+  const int gtile = tile_of_block(a);
+  const TileCtx tc = tile_ctx(vt, a, gtile);
+  const int lf = a.log2_fchunk;
+  const uint32_t len = tc.end - tc.start;
+  const uint32_t nfc = (uint32_t)(((uint64_t)len + ((1ull << lf) - 1)) >> lf);
+  if (nfc < 2) return;
+  const ViewArgs& va = vt.v[tc.view];
+  const int tpx = 1 << (a.log2_tw + a.log2_th);
+  const int64_t plane = (int64_t)va.W * va.H;
+#pragma unroll
+  for (int p = 0; p < PPT; ++p) {
+    int x, y;
+    pixel_of(a, PPT, threadIdx.x, p, tc.tx, tc.ty, &x, &y);
+    const int q = threadIdx.x * PPT + p;
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, Tf = 1.f;
+    bool have_T = false;
+    int last = 0;
+    for (int k = (int)nfc - 1; k >= 0; --k) {
+      const uint64_t bk = (uint64_t)tc.start + ((uint64_t)k << lf);
+      const int64_t idx = k + 1 < (int)nfc ? (int64_t)((bk + (1ull << lf)) >> lf) : a.nfslots + (int64_t)(bk >> lf);
+      const float4 r = a.fres[idx * tpx + q];
+      const int l = a.flast[idx * tpx + q];
+      s0 = r.x + s0;
+      s1 = r.y + s1;
+      s2 = r.z + s2;
+      if (k > 0) a.fsuf[(int64_t)(bk >> lf) * tpx + q] = make_float4(s0, s1, s2, 0.f);
+      if (!have_T && l >= 0) {
+        Tf = r.w;
+        have_T = true;
+      }
+      last = max(last, l);
+    }
+    if (x < va.W && y < va.H) {
+      const int64_t pix = (int64_t)y * va.W + x;
+      float* img = image + 3 * (int64_t)va.pix_off;
+      img[pix] = s0 + Tf * a.bg[0];
+      img[plane + pix] = s1 + Tf * a.bg[1];
+      img[2 * plane + pix] = s2 + Tf * a.bg[2];
+      T_final[va.pix_off + pix] = Tf;
+      last_out[va.pix_off + pix] = last;
+    }
+  }
+}
+
+// Owners of the forward boundaries: slot (start + kF) >> log2_fchunk of a
+// tile's list, k >= 1.  One thread per tile.
+__global__ void fwd_mark_kernel(RenderArgs a, int total_tiles) {
+  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gt >= total_tiles || *a.status != 0) return;
+  const uint64_t start = a.ranges[2 * gt], end = a.ranges[2 * gt + 1];
+  const int lf = a.log2_fchunk;
+  for (uint64_t q = start + (1ull << lf); q < end; q += 1ull << lf) a.fslot_owner[q >> lf] = (uint32_t)gt;
+}
+
+constexpr float kPosScale = 2.77258872223978124f;  // 4 ln 2 = -2 / kQScale
 
 template <int PPT, bool CULL>
 __global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs a, ViewTable vt, const float* __restrict__ T_final,
@@ -589,15 +751,34 @@ __global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs a, ViewTable
 
   // Starting state at the chunk's end: the final one when the walk ends in
   // this chunk, else the forward's record at ce (transmittance there, and the
-  // colour composited after it, which gives the dL/dC-weighted colour behind).
+  // colour composited after it, which gives the dL/dC-weighted colour behind)
+  // for the pixels that still composite after ce; the others keep the final
+  // state.  With forward chunking the record holds the colour composited
+  // after ce within its forward chunk; the later chunks' colour is added.
   if (ce < wlim) {
     const int tpx = 1 << (a.log2_tw + a.log2_th);
     const float4* st = a.state + (int64_t)(ce >> lg) * tpx;
+    const float4* sf = nullptr;
+    if (a.log2_fchunk < 31) {
+      const int lf = a.log2_fchunk;
+      const uint64_t nxt = (uint64_t)tc.start + ((((ce - tc.start) >> lf) + 1) << lf);  // next forward boundary
+      if (nxt < (uint64_t)tc.end) sf = a.fsuf + (int64_t)(nxt >> lf) * tpx;
+    }
+    const int rel = (int)(ce - tc.start);
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
-      const float4 v = st[threadIdx.x * PPT + p];
-      T[p] = v.x;
-      RdL[p] = RdL[p] + (v.y * g0[p] + v.z * g1[p] + v.w * g2[p]);
+      if (lc[p] > rel) {
+        const float4 v = st[threadIdx.x * PPT + p];
+        float c0 = v.y, c1 = v.z, c2 = v.w;
+        if (sf) {
+          const float4 w = sf[threadIdx.x * PPT + p];
+          c0 += w.x;
+          c1 += w.y;
+          c2 += w.z;
+        }
+        T[p] = v.x;
+        RdL[p] = RdL[p] + (c0 * g0[p] + c1 * g1[p] + c2 * g2[p]);
+      }
     }
   }
 
@@ -620,8 +801,8 @@ __global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs a, ViewTable
       const float4 ra = a.splats[(size_t)rec * 3 + 0];
       const float4 rb = a.splats[(size_t)rec * 3 + 1];
       s_e[i] = a.pair_index[bs + i];
-      s_a[i] = ra;
-      s_b[i] = rb;
+      s_a[i] = staged_a(ra);
+      s_b[i] = staged_b(rb);
       s_c[i] = a.splats[(size_t)rec * 3 + 2];
       if (CULL) s_mask[i] = (uint8_t)footprint_mask(ra, rb, nwaves, s_box);
     }
@@ -657,8 +838,10 @@ __global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs a, ViewTable
           x[2] += dLdq * e.dx * e.dx;
           x[3] += dLdq * 2.0f * e.dx * e.dy;
           x[4] += dLdq * e.dy * e.dy;
-          x[0] += -2.0f * dLdq * (ra.z * e.dx + ra.w * e.dy);
-          x[1] += -2.0f * dLdq * (ra.w * e.dx + rb.x * e.dy);
+          // -2 dL/dq (A dx + B dy, B dx + C dy) from the staged (a, b, c) = k (A, 2B, C):
+          // -2 / k = 4 ln 2
+          x[0] += kPosScale * dLdq * (ra.z * e.dx + 0.5f * ra.w * e.dy);
+          x[1] += kPosScale * dLdq * (0.5f * ra.w * e.dx + rb.x * e.dy);
         }
         if (__ballot(any) != 0) {  // wave-uniform: the whole wave takes part
           const float v = reduce_scatter9(x, b2, b3);
@@ -699,27 +882,40 @@ __global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs a, ViewTable
 
 static int tile_threads(const RenderArgs& a) { return (1 << (a.log2_tw + a.log2_th)) / a.ppt; }
 
+// Work items [item_base, item_base + items) of one walk launch.
+template <int PPT, int MODE>
+static void walk(const RenderArgs& a, const ViewTable& vt, float* image, float* T_final, int32_t* last,
+                 int64_t item_base, int64_t items, hipStream_t s) {
+  if (items <= 0) return;
+  const int nt = tile_threads(a);
+  const dim3 grid((unsigned)items), block((unsigned)nt);
+  const size_t sh = lds_bytes(a.batch, nt / kWave, false);
+  if (a.cull)
+    hipLaunchKernelGGL((render_fwd_kernel<PPT, true, MODE>), grid, block, sh, s, a, vt, image, T_final, last,
+                       item_base);
+  else
+    hipLaunchKernelGGL((render_fwd_kernel<PPT, false, MODE>), grid, block, sh, s, a, vt, image, T_final, last,
+                       item_base);
+}
+
 template <int PPT>
 static void fwd_ppt(const RenderArgs& a, const ViewTable& vt, float* image, float* T_final, int32_t* last,
                     hipStream_t s) {
-  const int nt = tile_threads(a);
-  const dim3 grid((unsigned)vt.total_tiles), block((unsigned)nt);
-  const size_t sh = lds_bytes(a.batch, nt / kWave, false);
-  if (a.cull)
-    hipLaunchKernelGGL((render_fwd_kernel<PPT, true, false>), grid, block, sh, s, a, vt, image, T_final, last);
-  else
-    hipLaunchKernelGGL((render_fwd_kernel<PPT, false, false>), grid, block, sh, s, a, vt, image, T_final, last);
+  if (a.nfslots > 0)
+    hipLaunchKernelGGL(fwd_mark_kernel, dim3((unsigned)((vt.total_tiles + 255) / 256)), dim3(256), 0, s, a,
+                       vt.total_tiles);
+  walk<PPT, kFull>(a, vt, image, T_final, last, a.nfslots, vt.total_tiles, s);  // every tile's first chunk
+  if (a.nfslots > 0) {
+    walk<PPT, kTPass>(a, vt, nullptr, nullptr, nullptr, 0, a.nfslots, s);  // products of chunks 1 .. m-2
+    walk<PPT, kFull>(a, vt, image, T_final, last, 0, a.nfslots, s);       // chunks 1 .. m-1
+    hipLaunchKernelGGL((fwd_combine_kernel<PPT>), dim3((unsigned)vt.total_tiles), dim3((unsigned)tile_threads(a)), 0,
+                       s, a, vt, image, T_final, last);
+  }
 }
 
 template <int PPT>
 static void count_ppt(const RenderArgs& a, const ViewTable& vt, hipStream_t s) {
-  const int nt = tile_threads(a);
-  const dim3 grid((unsigned)vt.total_tiles), block((unsigned)nt);
-  const size_t sh = lds_bytes(a.batch, nt / kWave, false);
-  if (a.cull)
-    hipLaunchKernelGGL((render_fwd_kernel<PPT, true, true>), grid, block, sh, s, a, vt, nullptr, nullptr, nullptr);
-  else
-    hipLaunchKernelGGL((render_fwd_kernel<PPT, false, true>), grid, block, sh, s, a, vt, nullptr, nullptr, nullptr);
+  walk<PPT, kCount>(a, vt, nullptr, nullptr, nullptr, 0, vt.total_tiles, s);
 }
 
 template <int PPT>
@@ -738,8 +934,9 @@ static void bwd_ppt(const RenderArgs& a, const ViewTable& vt, const float* T_fin
 hipError_t launch_render_fwd(const RenderArgs& a, const ViewTable& vt, float* image, float* T_final,
                              int32_t* last_contrib, hipStream_t s) {
   if (vt.total_tiles == 0) return hipSuccess;
-  const hipError_t e = launch_fill_u32(a.slot_owner, a.nslots, 0xffffffffu, s);  // no boundary recorded yet
+  hipError_t e = launch_fill_u32(a.slot_owner, a.nslots, 0xffffffffu, s);  // no boundary recorded yet
   if (e != hipSuccess) return e;
+  if (a.nfslots > 0 && (e = launch_fill_u32(a.fslot_owner, a.nfslots, 0xffffffffu, s)) != hipSuccess) return e;
   switch (a.ppt) {
     case 1: fwd_ppt<1>(a, vt, image, T_final, last_contrib, s); break;
     case 2: fwd_ppt<2>(a, vt, image, T_final, last_contrib, s); break;

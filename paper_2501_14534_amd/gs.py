@@ -42,7 +42,7 @@ class GsOpts(C.Structure):
     _fields_ = [("near_plane", C.c_float), ("tan_clamp", C.c_float), ("lowpass", C.c_float),
                 ("bg", C.c_float * 3), ("tile_w", C.c_int32), ("tile_h", C.c_int32),
                 ("batch_depth", C.c_int32), ("pixels_per_thread", C.c_int32), ("subtile_cull", C.c_int32),
-                ("bwd_chunk", C.c_int32), ("lowpass_progressive", C.c_int32)]
+                ("bwd_chunk", C.c_int32), ("fwd_chunk", C.c_int32), ("lowpass_progressive", C.c_int32)]
 
 
 class GsProjected(C.Structure):
@@ -154,6 +154,7 @@ def options(o) -> GsOpts:
     s.batch_depth, s.pixels_per_thread = int(o.batch_depth), int(o.pixels_per_thread)
     s.subtile_cull = int(getattr(o, "subtile_cull", 1))
     s.bwd_chunk = int(getattr(o, "bwd_chunk", 1024))
+    s.fwd_chunk = int(getattr(o, "fwd_chunk", 0))
     s.lowpass_progressive = int(getattr(o, "lowpass_progressive", 0))
     return s
 

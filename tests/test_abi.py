@@ -63,6 +63,9 @@ def test_workspace_size(lib):
     # smaller backward chunks need more chunk-state slots
     small = gs.options(dataclasses.replace(wl.opts, bwd_chunk=16))
     assert gs.workspace_size(100, cams, 1, small, 100000) > b
+    # and forward chunking its chunk results
+    fch = gs.options(dataclasses.replace(wl.opts, fwd_chunk=64))
+    assert gs.workspace_size(100, cams, 1, fch, 100000) > b
 
 
 def _bad_opts(wl):
@@ -76,6 +79,8 @@ def _bad_opts(wl):
     yield dataclasses.replace(wl.opts, tan_clamp=0.0)
     yield dataclasses.replace(wl.opts, bwd_chunk=100)                # not a power of two
     yield dataclasses.replace(wl.opts, bwd_chunk=8)                  # below 16
+    yield dataclasses.replace(wl.opts, fwd_chunk=32)                 # below 64
+    yield dataclasses.replace(wl.opts, fwd_chunk=1000)               # not a power of two
 
 
 def test_project_rejects_invalid_arguments(lib):

@@ -57,23 +57,29 @@ def test_bin_sort_bit_exact(P, case):
 
 
 @pytest.mark.parametrize("case", list(CASES))
-def test_render_fwd_parity(P, case):
+@pytest.mark.parametrize("fchunk", [0, 64])
+def test_render_fwd_parity(P, case, fchunk):
+    """Forward vs the oracle.  With fchunk 64 every list longer than 64 is walked in chunks by
+    several work items, each starting from the product pass's transmittance."""
     wl = CASES[case]()
-    print(f"[render_fwd] {case}", flush=True)
+    wl = dataclasses.replace(wl, opts=dataclasses.replace(wl.opts, fwd_chunk=fchunk))
+    print(f"[render_fwd] {case} fchunk {fchunk}", flush=True)
     r, _ = P.gpu_forward(wl)
     res = P.check_forward(wl, wl.opts, r)
     print({k: v for k, v in res.items() if k not in ("fw", "flagged")})
     assert res["flagged_frac"] <= 1e-3
 
 
-@pytest.mark.parametrize("chunk", [1024, 16])
+@pytest.mark.parametrize("chunk,fchunk", [(1024, 0), (16, 0), (16, 64), (1024, 256)])
 @pytest.mark.parametrize("case", list(CASES))
-def test_render_bwd_parity(P, case, chunk):
+def test_render_bwd_parity(P, case, chunk, fchunk):
     """Backward vs the oracle.  With chunk 16 every list longer than 16 is walked by several
-    work items in parallel, each starting from the state the forward recorded at its end."""
+    work items in parallel, each starting from the state the forward recorded at its end; with
+    a forward chunk as well, those states come from the chunked forward (plus the colour of the
+    later forward chunks)."""
     wl = CASES[case]()
-    wl = dataclasses.replace(wl, opts=dataclasses.replace(wl.opts, bwd_chunk=chunk))
-    print(f"[render_bwd] {case} chunk {chunk}", flush=True)
+    wl = dataclasses.replace(wl, opts=dataclasses.replace(wl.opts, bwd_chunk=chunk, fwd_chunk=fchunk))
+    print(f"[render_bwd] {case} chunk {chunk} fchunk {fchunk}", flush=True)
     r, params = P.gpu_forward(wl)
     fwd = P.check_forward(wl, wl.opts, r)
     res = P.check_backward(wl, wl.opts, r, params, fwd["flagged"], seed=3)
