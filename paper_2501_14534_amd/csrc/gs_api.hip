@@ -232,10 +232,10 @@ bool binning_ok(const gs_binning* b, int64_t nrec) {
 }
 
 // Backward workspace: per-pair gradients [capacity][9] floats, then per-record
-// geometry sums [V*n][6] doubles and colour mean terms [V*n][4] floats.
+// geometry sums [V*n][6] floats and colour terms [V*n][8] floats.
 size_t grad_pair_bytes(uint64_t capacity) { return align256(sizeof(float) * GS_GRAD_FLOATS * (size_t)capacity); }
 size_t rec_geo_bytes(int64_t nrec) { return align256(sizeof(float) * 6 * (size_t)nrec); }
-size_t rec_mu_bytes(int64_t nrec) { return align256(sizeof(float) * 4 * (size_t)nrec); }
+size_t rec_mu_bytes(int64_t nrec) { return align256(sizeof(float) * 8 * (size_t)nrec); }
 size_t bwd_ws_bytes(uint64_t capacity, int64_t nrec) {
   return grad_pair_bytes(capacity) + rec_geo_bytes(nrec) + rec_mu_bytes(nrec);
 }

@@ -3,13 +3,17 @@
 // call and added (+=) to the caller's gradient arrays.  Straight-through
 // estimator for the hard masks (Eq. 3, Eq. 5): d(mask)/d(logit) = sigmoid'.
 //
-// Three kernels (no atomics):
+// Four kernels (no atomics):
 //   sums:     one thread per (view, Gaussian) record: its pairs' gradients
 //             summed in emission order (double), rounded once to float (adjacent records' pairs are
 //             adjacent, so a wave reads one contiguous stretch);
-//   colour:   one thread per Gaussian: the SH chain (diffuse colour, bands
-//             1..3, band-mask logits, and the view-direction term of the
-//             mean) in single precision;
+//   colour:   one thread per Gaussian: the SH chain (diffuse colour,
+//             band-mask logits, and the view-direction term of the mean) in
+//             single precision;
+//   SH rest:  one thread per Gaussian: bands 1..3 of the colour gradient (its
+//             own kernel, so neither half holds both the coefficients and
+//             their 45 accumulators; skipped when that gradient is not asked
+//             for);
 //   geometry: one thread per Gaussian: the EWA chain in double precision (this half is bound by
 //             memory traffic, and the 2x2 inverse amplifies rounding by the
 //             condition number of Sigma'):
@@ -87,8 +91,9 @@ __device__ __forceinline__ float acc_mul_add(float t, float a, float b) {
 
 // Per record: sums of its pairs' 9 gradients in emission order, accumulated in
 // double and rounded once to float: rec_geo gets (u, v, A, B, C, o'),
-// rec_mu[0..2] the colour sums (the colour kernel replaces them with the
-// colour term of the mean gradient).
+// rec_mu[0..2] the colour sums (8 floats per record: the colour kernel
+// replaces them with the gradient of the clamped colour and writes the colour
+// term of the mean gradient to rec_mu[4..6]).
 __global__ __launch_bounds__(256) void record_sum_kernel(ProjectBwdArgs b, int64_t nrec) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nrec) return;
@@ -108,12 +113,44 @@ __global__ __launch_bounds__(256) void record_sum_kernel(ProjectBwdArgs b, int64
     b.g_mean2d[(v * 2 + 0) * n + i] += (float)gsum[0];
     b.g_mean2d[(v * 2 + 1) * n + i] += (float)gsum[1];
   }
-  float* cmu = b.rec_mu + r * 4;
+  float* cmu = b.rec_mu + r * 8;
   cmu[0] = (float)gsum[6];
   cmu[1] = (float)gsum[7];
   cmu[2] = (float)gsum[8];
 }
 
+// Views (bit v) in which record (v, i) touches a tile.
+__device__ __forceinline__ uint32_t visible_views(const ProjectBwdArgs& b, int V, int64_t n, int64_t i) {
+  uint32_t vis = 0;
+  for (int v = 0; v < V; ++v) vis |= (b.tiles_touched[(size_t)v * n + i] != 0u ? 1u : 0u) << v;
+  return vis;
+}
+
+// Band masks of Gaussian i (Eq. 5): sigmoid(m_l) > eps <=> m_l > logit(eps).
+__device__ __forceinline__ void band_masks(const ProjectArgs& a, int64_t n, int64_t i, float bm[3], bool on[4]) {
+  on[0] = on[1] = on[2] = on[3] = true;
+  bm[0] = bm[1] = bm[2] = 0.f;
+  if (a.sh_mask_logits) {
+#pragma unroll
+    for (int l = 1; l <= 3; ++l) {
+      bm[l - 1] = a.sh_mask_logits[(l - 1) * n + i];
+      on[l] = bm[l - 1] > a.sh_mask_thr;
+    }
+  }
+}
+
+// Unit view direction from the camera centre to the mean, and 1 / distance.
+__device__ __forceinline__ void view_dir(const ViewArgs& c, const float mu[3], float* dx, float* dy, float* dz,
+                                        float* il) {
+  const float d0 = mu[0] - c.campos[0], d1 = mu[1] - c.campos[1], d2 = mu[2] - c.campos[2];
+  *il = 1.0f / sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
+  *dx = d0 * *il, *dy = d1 * *il, *dz = d2 * *il;
+}
+
+// Colour chain per Gaussian over the views: the gradient of the clamped
+// colour (gpre, kept in rec_mu[0..2] for the SH-rest kernel), the diffuse
+// colour and band-mask gradients, and the colour term of the mean gradient
+// (rec_mu[4..6], through the view direction).
 template <int DEG>
 __global__ __launch_bounds__(256) void project_bwd_color_kernel(ProjectBwdArgs b, ViewTable vt) {
   const ProjectArgs& a = b.p;
@@ -121,10 +158,8 @@ __global__ __launch_bounds__(256) void project_bwd_color_kernel(ProjectBwdArgs b
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   if (*b.status != 0) return;  // binning overflowed: no lists, no gradients
-  const int V = vt.nviews;
-  bool any = false;
-  for (int v = 0; v < V; ++v) any |= b.tiles_touched[(size_t)v * n + i] != 0u;
-  if (!any) return;  // culled or off-screen in every view
+  const uint32_t vis = visible_views(b, vt.nviews, n, i);
+  if (!vis) return;  // culled or off-screen in every view
 
   float mu[3], dc[3];
 #pragma unroll
@@ -134,16 +169,10 @@ __global__ __launch_bounds__(256) void project_bwd_color_kernel(ProjectBwdArgs b
   }
   constexpr int NR = DEG > 0 ? (DEG + 1) * (DEG + 1) - 1 : 1;
   float rest[NR][3];
-  float bm[3] = {0.f, 0.f, 0.f};
-  bool band_on[4] = {true, true, true, true};
+  float bm[3];
+  bool band_on[4];
+  band_masks(a, n, i, bm, band_on);
   if (DEG > 0) {
-    if (a.sh_mask_logits) {
-#pragma unroll
-      for (int l = 1; l <= 3; ++l) {
-        bm[l - 1] = a.sh_mask_logits[(l - 1) * n + i];
-        band_on[l] = bm[l - 1] > a.sh_mask_thr;
-      }
-    }
     // every band's coefficients are read: the band-mask gradient needs them
     // even when the band is off (straight-through estimator)
 #pragma unroll
@@ -152,17 +181,25 @@ __global__ __launch_bounds__(256) void project_bwd_color_kernel(ProjectBwdArgs b
       for (int c = 0; c < 3; ++c) rest[k - 1][c] = a.sh_rest[((k - 1) * 3 + c) * n + i];
   }
   float tdc[3] = {0.f, 0.f, 0.f}, tbm[3] = {0.f, 0.f, 0.f};
-  float trest[NR][3];
-#pragma unroll
-  for (int k = 0; k < NR; ++k) trest[k][0] = trest[k][1] = trest[k][2] = 0.f;
 
-  for (int v = 0; v < V; ++v) {
+  // the visible views in order; the next one's colour sums load while this one is processed
+  uint32_t pend = vis;
+  int v = __builtin_ctz(pend);
+  pend &= pend - 1;
+  float4 cur = *(const float4*)(b.rec_mu + ((size_t)v * n + i) * 8);
+  for (;;) {
+    const bool more = pend != 0;
+    const int vn = more ? __builtin_ctz(pend) : v;
+    pend &= pend - 1;
+    const float4 nxt = *(const float4*)(b.rec_mu + ((size_t)vn * n + i) * 8);
     const size_t r = (size_t)v * n + i;
-    if (b.tiles_touched[r] == 0) continue;
-    float* cmu = b.rec_mu + r * 4;  // colour sums of this record's pairs (record_sum_kernel)
-    const float grgb[3] = {cmu[0], cmu[1], cmu[2]};
+    float* cmu = b.rec_mu + r * 8;  // colour sums of this record's pairs (record_sum_kernel)
+    const float grgb[3] = {cur.x, cur.y, cur.z};
     if (grgb[0] == 0.f && grgb[1] == 0.f && grgb[2] == 0.f) {
-      cmu[0] = cmu[1] = cmu[2] = 0.f;
+      cmu[4] = cmu[5] = cmu[6] = 0.f;
+      if (!more) break;
+      v = vn;
+      cur = nxt;
       continue;
     }
     const ViewArgs& c = vt.v[v];
@@ -170,11 +207,9 @@ __global__ __launch_bounds__(256) void project_bwd_color_kernel(ProjectBwdArgs b
     float Y[15];
     float dx = 0.f, dy = 0.f, dz = 0.f, il = 1.f;
     if (DEG > 0) {
-      const float d0 = mu[0] - c.campos[0], d1 = mu[1] - c.campos[1], d2 = mu[2] - c.campos[2];
-      il = 1.0f / sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
-      dx = d0 * il, dy = d1 * il, dz = d2 * il;
+      view_dir(c, mu, &dx, &dy, &dz, &il);
       sh_basis15(dx, dy, dz, Y);
-      // flat loops with constant trip counts keep rest/Y/trest in registers
+      // flat loops with constant trip counts keep rest/Y in registers
 #pragma unroll
       for (int k = 1; k < kShCoeffs; ++k) {
         const int l = sh_band(k);
@@ -201,11 +236,7 @@ __global__ __launch_bounds__(256) void project_bwd_color_kernel(ProjectBwdArgs b
         if (l > DEG) continue;
         const float cg = rest[k - 1][0] * gpre[0] + rest[k - 1][1] * gpre[1] + rest[k - 1][2] * gpre[2];
         band[l - 1] += Y[k - 1] * cg;
-        if (band_on[l]) {
-          wY[k - 1] = cg;
-#pragma unroll
-          for (int ch = 0; ch < 3; ++ch) trest[k - 1][ch] = acc_mul_add(trest[k - 1][ch], Y[k - 1], gpre[ch]);
-        }
+        if (band_on[l]) wY[k - 1] = cg;
       }
 #pragma unroll
       for (int l = 1; l <= DEG; ++l) {
@@ -219,26 +250,80 @@ __global__ __launch_bounds__(256) void project_bwd_color_kernel(ProjectBwdArgs b
       gmu_col[1] = (gdy - dy * dot) * il;
       gmu_col[2] = (gdz - dz * dot) * il;
     }
-    cmu[0] = gmu_col[0];
-    cmu[1] = gmu_col[1];
-    cmu[2] = gmu_col[2];
+    cmu[0] = gpre[0];
+    cmu[1] = gpre[1];
+    cmu[2] = gpre[2];
+    cmu[4] = gmu_col[0];
+    cmu[5] = gmu_col[1];
+    cmu[6] = gmu_col[2];
+    if (!more) break;
+    v = vn;
+    cur = nxt;
   }
 
 #pragma unroll
   for (int k = 0; k < 3; ++k)
     if (b.g_sh_dc) b.g_sh_dc[k * n + i] += tdc[k];
-  if (DEG > 0) {
-    if (b.g_sh_rest) {
+  if (DEG > 0 && b.g_sh_mask_logits && a.sh_mask_logits) {
 #pragma unroll
-      for (int k = 1; k <= NR; ++k)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) b.g_sh_rest[((k - 1) * 3 + c) * n + i] += trest[k - 1][c];
-    }
-    if (b.g_sh_mask_logits && a.sh_mask_logits) {
-#pragma unroll
-      for (int l = 1; l <= DEG; ++l) b.g_sh_mask_logits[(l - 1) * n + i] += tbm[l - 1];
-    }
+    for (int l = 1; l <= DEG; ++l) b.g_sh_mask_logits[(l - 1) * n + i] += tbm[l - 1];
   }
+}
+
+// SH bands 1..DEG of the colour gradient: sum over the views of Y_k(d_v) times
+// the clamped colour's gradient (bands whose hard mask is off get nothing),
+// added to the SH-rest gradient.  Not launched when that gradient is not
+// asked for (the steps between sparse SH-rest updates).
+template <int DEG>
+__global__ __launch_bounds__(256) void project_bwd_shrest_kernel(ProjectBwdArgs b, ViewTable vt) {
+  const ProjectArgs& a = b.p;
+  const int64_t n = a.n;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (*b.status != 0) return;
+  const uint32_t vis = visible_views(b, vt.nviews, n, i);
+  if (!vis) return;
+  float mu[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) mu[k] = a.means[k * n + i];
+  float bm[3];
+  bool band_on[4];
+  band_masks(a, n, i, bm, band_on);
+  constexpr int NR = (DEG + 1) * (DEG + 1) - 1;
+  float trest[NR][3];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) trest[k][0] = trest[k][1] = trest[k][2] = 0.f;
+  // the visible views in order; the next one's gradient loads while this one is processed
+  uint32_t pend = vis;
+  int v = __builtin_ctz(pend);
+  pend &= pend - 1;
+  float4 cur = *(const float4*)(b.rec_mu + ((size_t)v * n + i) * 8);  // the clamped colour's gradient
+  for (;;) {
+    const bool more = pend != 0;
+    const int vn = more ? __builtin_ctz(pend) : v;
+    pend &= pend - 1;
+    const float4 nxt = *(const float4*)(b.rec_mu + ((size_t)vn * n + i) * 8);
+    const float gpre[3] = {cur.x, cur.y, cur.z};
+    if (gpre[0] != 0.f || gpre[1] != 0.f || gpre[2] != 0.f) {  // else it adds exact zeros
+      float dx, dy, dz, il, Y[15];
+      view_dir(vt.v[v], mu, &dx, &dy, &dz, &il);
+      sh_basis15(dx, dy, dz, Y);
+#pragma unroll
+      for (int k = 1; k < kShCoeffs; ++k) {
+        const int l = sh_band(k);
+        if (l > DEG || !band_on[l]) continue;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) trest[k - 1][ch] = acc_mul_add(trest[k - 1][ch], Y[k - 1], gpre[ch]);
+      }
+    }
+    if (!more) break;
+    v = vn;
+    cur = nxt;
+  }
+#pragma unroll
+  for (int k = 1; k <= NR; ++k)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) b.g_sh_rest[((k - 1) * 3 + c) * n + i] += trest[k - 1][c];
 }
 
 __global__ __launch_bounds__(256) void project_bwd_geom_kernel(ProjectBwdArgs b, ViewTable vt) {
@@ -247,10 +332,8 @@ __global__ __launch_bounds__(256) void project_bwd_geom_kernel(ProjectBwdArgs b,
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   if (*b.status != 0) return;
-  const int V = vt.nviews;
-  bool any = false;
-  for (int v = 0; v < V; ++v) any |= b.tiles_touched[(size_t)v * n + i] != 0u;
-  if (!any) return;
+  const uint32_t vis = visible_views(b, vt.nviews, n, i);
+  if (!vis) return;
 
   float mu[3], ls[3], q[4];
 #pragma unroll
@@ -291,11 +374,11 @@ __global__ __launch_bounds__(256) void project_bwd_geom_kernel(ProjectBwdArgs b,
 
   float tmu[3] = {0.f, 0.f, 0.f}, tls[3] = {0.f, 0.f, 0.f}, tq[4] = {0.f, 0.f, 0.f, 0.f};
   float top = 0.f, tmask = 0.f;
-  for (int v = 0; v < V; ++v) {
+  for (uint32_t pend = vis; pend != 0; pend &= pend - 1) {  // the visible views in order
+    const int v = __builtin_ctz(pend);
     const size_t r = (size_t)v * n + i;
-    if (b.tiles_touched[r] == 0) continue;
     const float* geo = b.rec_geo + r * 6;
-    const float* cmu = b.rec_mu + r * 4;
+    const float* cmu = b.rec_mu + r * 8 + 4;  // colour term of the mean gradient
     const double gu = geo[0], gv = geo[1], gA = geo[2], gB = geo[3], gC = geo[4], go = geo[5];
     const float cm0 = cmu[0], cm1 = cmu[1], cm2 = cmu[2];
     if (gu == 0.0 && gv == 0.0 && gA == 0.0 && gB == 0.0 && gC == 0.0 && go == 0.0 && cm0 == 0.f && cm1 == 0.f &&
@@ -429,6 +512,13 @@ hipError_t launch_project_bwd(const ProjectBwdArgs& a, const ViewTable& vt, int 
     case 1: hipLaunchKernelGGL(project_bwd_color_kernel<1>, grid, block, 0, s, a, vt); break;
     case 2: hipLaunchKernelGGL(project_bwd_color_kernel<2>, grid, block, 0, s, a, vt); break;
     default: hipLaunchKernelGGL(project_bwd_color_kernel<3>, grid, block, 0, s, a, vt); break;
+  }
+  if (a.g_sh_rest && deg > 0) {
+    switch (deg) {
+      case 1: hipLaunchKernelGGL(project_bwd_shrest_kernel<1>, grid, block, 0, s, a, vt); break;
+      case 2: hipLaunchKernelGGL(project_bwd_shrest_kernel<2>, grid, block, 0, s, a, vt); break;
+      default: hipLaunchKernelGGL(project_bwd_shrest_kernel<3>, grid, block, 0, s, a, vt); break;
+    }
   }
   hipLaunchKernelGGL(project_bwd_geom_kernel, grid, block, 0, s, a, vt);
   return hipGetLastError();
