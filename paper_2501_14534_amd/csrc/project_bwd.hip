@@ -5,8 +5,8 @@
 //
 // Four kernels (no atomics):
 //   sums:     one thread per (view, Gaussian) record: its pairs' gradients
-//             summed in emission order (double), rounded once to float (adjacent records' pairs are
-//             adjacent, so a wave reads one contiguous stretch);
+//             summed in emission order (double), rounded once to float (adjacent
+//             records' pairs are adjacent, so a wave reads one contiguous stretch);
 //   colour:   one thread per Gaussian: the SH chain (diffuse colour,
 //             band-mask logits, and the view-direction term of the mean) in
 //             single precision;

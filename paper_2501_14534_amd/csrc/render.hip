@@ -698,6 +698,10 @@ __global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs a, ViewTable
   const bool b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1;
   const int k2 = 2 * (int)b3 + (int)b2, k1 = k2 + 3 * ((lane >> 4) & 1), my_e = k1 + 5 * ((lane >> 5) & 1);
   const bool writer = (lane & 3) == 0 && k2 <= 2 && k1 <= 4 && my_e < GS_GRAD_FLOATS;
+  // per element, the factor the walk leaves out: with m = -2 dL/dq,
+  // dL/d(u, v) = (-2/k) dL/dq (A dx + B dy, B dx + C dy) = -(2 ln 2) m (a dx + b/2 dy, ...),
+  // dL/d(A, B, C) = dL/dq (dx^2, 2 dx dy, dy^2) = -m (dx^2 / 2, dx dy, dy^2 / 2)
+  const float escale = my_e < 2 ? -0.5f * kPosScale : my_e == 3 ? -1.0f : my_e < 5 ? -0.5f : 1.0f;
 
   float px[PPT], py[PPT], T[PPT], g0[PPT], g1[PPT], g2[PPT], RdL[PPT];
   int lc[PPT];
@@ -815,6 +819,7 @@ __global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs a, ViewTable
       // one staged record: per-pixel partials, then the wave's sums into LDS
       auto grad = [&](int j, const float4& ra, const float4& rb, const float4& rc) {
         const int jr = (int)(bs - tc.start) + j;                   // index within the tile's list
+        const float hb = 0.5f * ra.w;                              // staged b / 2 = k B
         float x[GS_GRAD_FLOATS] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // u v A B C o' r g b
         bool any = false;
 #pragma unroll
@@ -834,18 +839,18 @@ __global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs a, ViewTable
           const float dLda = use && !(e.raw > kAlphaMax) ? T[p] * cd - RdL[p] * inv : 0.0f;
           RdL[p] += cd * wgt;
           x[5] += e.G * dLda;
-          const float dLdq = -0.5f * e.alpha * dLda;
-          x[2] += dLdq * e.dx * e.dx;
-          x[3] += dLdq * 2.0f * e.dx * e.dy;
-          x[4] += dLdq * e.dy * e.dy;
-          // -2 dL/dq (A dx + B dy, B dx + C dy) from the staged (a, b, c) = k (A, 2B, C):
-          // -2 / k = 4 ln 2
-          x[0] += kPosScale * dLdq * (ra.z * e.dx + 0.5f * ra.w * e.dy);
-          x[1] += kPosScale * dLdq * (0.5f * ra.w * e.dx + rb.x * e.dy);
+          // m = alpha dL/dalpha = -2 dL/dq; the constant factors of the conic and
+          // position gradients are applied once, after the wave's sums (kGradScale)
+          const float m = e.alpha * dLda;
+          x[2] += m * e.dx * e.dx;
+          x[3] += m * e.dx * e.dy;
+          x[4] += m * e.dy * e.dy;
+          x[0] += m * (ra.z * e.dx + hb * e.dy);
+          x[1] += m * (hb * e.dx + rb.x * e.dy);
         }
         if (__ballot(any) != 0) {  // wave-uniform: the whole wave takes part
           const float v = reduce_scatter9(x, b2, b3);
-          if (writer) s_part[(wave * batch + j) * GS_GRAD_FLOATS + my_e] = v;
+          if (writer) s_part[(wave * batch + j) * GS_GRAD_FLOATS + my_e] = v * escale;
         }
       };
       // two register sets in turn: the next record loads while this one is reduced
