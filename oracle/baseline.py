@@ -5,10 +5,12 @@ run as it stands -- not tuned for speed -- on the host cores it was built for
 (OpenMP threads as the environment sets them):
   * projection of every (view, Gaussian) record and binning/ordering of the
     whole workload are run in full;
-  * forward and backward compositing run on a random subset of tiles, sized
-    to the time budget, and are scaled to all tiles by the tile fraction;
-  * the projection backward runs on a random subset of records and is scaled
-    by the record fraction.
+  * forward and backward compositing run on every tile when a probe of 5% of
+    the tiles says that fits 60% of the time budget, else on a random subset
+    sized to the budget and scaled to all tiles by the tile fraction;
+  * the projection backward runs on every record when that fits 30% of the
+    budget, else on a random subset of one view's records, scaled by the
+    record fraction and the view count.
 The reported rate is total pixels / (sum of the scaled stage times).
 """
 from __future__ import annotations
@@ -47,12 +49,15 @@ def measure(wl, opts, target_seconds: float = 20.0, seed: int = 0) -> dict:
         return tf, tb
 
     order = rng.permutation(T)
-    probe = order[: max(1, T // 200)]
+    probe = order[: max(1, T // 20)]
     tf, tb = composite(probe)
     per_tile = (tf + tb) / len(probe)
-    budget = max(0.4 * target_seconds - (tf + tb), 0.0)
-    extra = int(min(T - len(probe), budget / max(per_tile, 1e-9)))
-    sample = order[: len(probe) + extra]
+    if per_tile * T <= 0.6 * target_seconds:
+        sample = order  # every tile fits the budget
+    else:
+        budget = max(0.4 * target_seconds - (tf + tb), 0.0)
+        extra = int(min(T - len(probe), budget / max(per_tile, 1e-9)))
+        sample = order[: len(probe) + extra]
     tf, tb = composite(sample)
     ft = len(sample) / T
 
@@ -64,14 +69,23 @@ def measure(wl, opts, target_seconds: float = 20.0, seed: int = 0) -> dict:
     gr = np.ones((sub.n, 9))
     _, tp = _t(lambda: O.project_bwd(sub, wl.cams[0], opts, gr, grads))
     per_rec = tp / sub.n
-    m = int(min(n, max(rec_cost_probe, 0.25 * target_seconds / max(per_rec, 1e-12))))
-    idx = rng.choice(n, size=m, replace=False)
-    sub = sc.subset(np.sort(idx))
-    grads = O.zero_grads(sub)
-    gr = np.ones((sub.n, 9))
-    _, tp = _t(lambda: O.project_bwd(sub, wl.cams[0], opts, gr, grads))
-    fr = sub.n / n
-    t_pbwd_full = tp / fr * V
+    if per_rec * n * V <= 0.3 * target_seconds:  # every view and Gaussian fits the budget
+        grads = O.zero_grads(sc)
+        gr = np.ones((n, 9))
+        t0 = time.perf_counter()
+        for c in wl.cams:
+            O.project_bwd(sc, c, opts, gr, grads)
+        tp = time.perf_counter() - t0
+        sub, fr, t_pbwd_full = sc, 1.0, tp
+    else:
+        m = int(min(n, max(rec_cost_probe, 0.25 * target_seconds / max(per_rec, 1e-12))))
+        idx = rng.choice(n, size=m, replace=False)
+        sub = sc.subset(np.sort(idx))
+        grads = O.zero_grads(sub)
+        gr = np.ones((sub.n, 9))
+        _, tp = _t(lambda: O.project_bwd(sub, wl.cams[0], opts, gr, grads))
+        fr = sub.n / n
+        t_pbwd_full = tp / fr * V
 
     total = t_proj + t_bin + tf / ft + tb / ft + t_pbwd_full
     return {
@@ -80,9 +94,10 @@ def measure(wl, opts, target_seconds: float = 20.0, seed: int = 0) -> dict:
         "cores": O.num_threads(),
         "kind": "oracle",
         "sample": (f"FP64 oracle: projection of all {V * n} records and binning of all {lists['K']} pairs in full; "
-                   f"forward+backward compositing on {len(sample)} of {T} tiles (random) scaled by the tile "
-                   f"fraction; projection backward on {sub.n} of {n} Gaussians scaled by the record fraction "
-                   f"and view count"),
+                   f"forward+backward compositing on {len(sample)} of {T} tiles" +
+                   (" (all)" if len(sample) == T else " (random), scaled by the tile fraction") +
+                   f"; projection backward on {sub.n} of {n} Gaussians" +
+                   (" in all views" if fr == 1.0 else " in one view, scaled by the record fraction and view count")),
         "stage_s": {"project": round(t_proj, 3), "bin": round(t_bin, 3),
                     "composite_fwd_scaled": round(tf / ft, 3), "composite_bwd_scaled": round(tb / ft, 3),
                     "project_bwd_scaled": round(t_pbwd_full, 3)},
