@@ -62,7 +62,7 @@ def measure(wl, opts, target_seconds: float = 20.0, seed: int = 0) -> dict:
     ft = len(sample) / T
 
     # projection backward: a random subset of records with unit splat gradients
-    rec_cost_probe = max(1, min(n, 2000))
+    rec_cost_probe = max(1, min(n, max(2000, n // 20)))
     idx = rng.choice(n, size=rec_cost_probe, replace=False)
     sub = sc.subset(np.sort(idx))
     grads = O.zero_grads(sub)
@@ -76,7 +76,7 @@ def measure(wl, opts, target_seconds: float = 20.0, seed: int = 0) -> dict:
         for c in wl.cams:
             O.project_bwd(sc, c, opts, gr, grads)
         tp = time.perf_counter() - t0
-        sub, fr, t_pbwd_full = sc, 1.0, tp
+        sub, fr, t_pbwd_full, all_views = sc, 1.0, tp, True
     else:
         m = int(min(n, max(rec_cost_probe, 0.25 * target_seconds / max(per_rec, 1e-12))))
         idx = rng.choice(n, size=m, replace=False)
@@ -86,6 +86,7 @@ def measure(wl, opts, target_seconds: float = 20.0, seed: int = 0) -> dict:
         _, tp = _t(lambda: O.project_bwd(sub, wl.cams[0], opts, gr, grads))
         fr = sub.n / n
         t_pbwd_full = tp / fr * V
+        all_views = False
 
     total = t_proj + t_bin + tf / ft + tb / ft + t_pbwd_full
     return {
@@ -97,7 +98,7 @@ def measure(wl, opts, target_seconds: float = 20.0, seed: int = 0) -> dict:
                    f"forward+backward compositing on {len(sample)} of {T} tiles" +
                    (" (all)" if len(sample) == T else " (random), scaled by the tile fraction") +
                    f"; projection backward on {sub.n} of {n} Gaussians" +
-                   (" in all views" if fr == 1.0 else " in one view, scaled by the record fraction and view count")),
+                   (" in all views" if all_views else " in one view, scaled by the record fraction and view count")),
         "stage_s": {"project": round(t_proj, 3), "bin": round(t_bin, 3),
                     "composite_fwd_scaled": round(tf / ft, 3), "composite_bwd_scaled": round(tb / ft, 3),
                     "project_bwd_scaled": round(t_pbwd_full, 3)},
