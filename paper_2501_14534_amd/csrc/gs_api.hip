@@ -471,7 +471,7 @@ int gs_project_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t V, cons
 // ---------------------------------------------------------------------------
 // Photometric loss (Eq. 7, L1 and D-SSIM terms)
 
-static bool loss_views(const gs_camera* cams, int32_t V, LossViews* lv, int64_t* total_px) {
+static bool loss_views(const gs_camera* cams, int32_t V, int tile, LossViews* lv, int64_t* total_px) {
   if (!cams || V < 1 || V > GS_MAX_VIEWS) return false;
   std::memset(lv, 0, sizeof(*lv));
   int64_t po = 0, bo = 0;
@@ -480,7 +480,7 @@ static bool loss_views(const gs_camera* cams, int32_t V, LossViews* lv, int64_t*
     if (W <= 0 || H <= 0) return false;
     LossView& q = lv->v[v];
     q.W = W, q.H = H;
-    q.TX = (W + 15) / 16, q.TY = (H + 15) / 16;
+    q.TX = (W + tile - 1) / tile, q.TY = (H + tile - 1) / tile;
     q.pix_off = po;
     q.block_off = (int32_t)bo;
     po += (int64_t)W * H;
@@ -518,7 +518,7 @@ static LossWs loss_ws(const LossViews& lv, int64_t total_px, void* ws) {
 size_t gs_loss_workspace_size(const gs_camera* cams, int32_t V) {
   LossViews lv;
   int64_t px = 0;
-  if (!loss_views(cams, V, &lv, &px)) return 0;
+  if (!loss_views(cams, V, kLossTile, &lv, &px)) return 0;
   return loss_ws(lv, px, nullptr).bytes;
 }
 
@@ -526,7 +526,7 @@ int gs_loss_l1_dssim(const float* image, const float* target, const gs_camera* c
                      float* loss, float* dL_dimage, void* ws, size_t ws_bytes, gs_stream_t stream) {
   LossViews lv;
   int64_t px = 0;
-  if (!loss_views(cams, V, &lv, &px)) return GS_E_INVALID;
+  if (!loss_views(cams, V, kLossTile, &lv, &px)) return GS_E_INVALID;
   if (!image || !target || !std::isfinite(lambda_ssim) || lambda_ssim < 0.0f || lambda_ssim > 1.0f)
     return GS_E_INVALID;
   const LossWs w = loss_ws(lv, px, ws);
@@ -541,7 +541,7 @@ int gs_blur_views(const float* in, float* out, const gs_camera* cams, int32_t V,
                   gs_stream_t stream) {
   BlurArgs b;
   int64_t px = 0;
-  if (!loss_views(cams, V, &b.views, &px)) return GS_E_INVALID;
+  if (!loss_views(cams, V, kBlurTile, &b.views, &px)) return GS_E_INVALID;
   if (!in || !out || in == out) return GS_E_INVALID;
   if (ksize < 1 || ksize > 2 * kMaxBlurRadius + 1 || ksize % 2 == 0) return GS_E_INVALID;
   if (!std::isfinite(sigma) || !(sigma > 0.0f)) return GS_E_INVALID;

@@ -97,8 +97,11 @@ struct ProjectBwdArgs {
   float* g_mean2d;
 };
 
-// Views of a loss call: per view its size, 16 x 16 tile grid, pixel offset
-// (views concatenated, each [3][H][W]) and first workgroup; the window taps.
+// Views of an image call (loss: 32 x 32 tiles; target blur: 16 x 16): per
+// view its size, tile grid, pixel offset (views concatenated, each [3][H][W])
+// and first workgroup; the loss window's taps.
+constexpr int kLossTile = 32;
+constexpr int kBlurTile = 16;
 struct LossView {
   int32_t W, H, TX, TY;
   int64_t pix_off;

@@ -7,9 +7,9 @@
 // (11 x 11 window = outer product of two 11-tap Gaussians of standard deviation
 // 1.5, as Sec. 3.2.5 describes; zero padding; C1 = 0.01^2, C2 = 0.03^2).
 //
-// Two passes over 16 x 16 output tiles, one workgroup per (view, plane, tile),
-// each staging the tile plus a 5-pixel halo in LDS and filtering it with two
-// 1-D passes:
+// Two passes over 32 x 32 output tiles, one workgroup per (view, plane, tile),
+// each staging the tile plus a 5-pixel halo in LDS (42 x 42: 1.7 reads per
+// pixel) and filtering it with two 1-D passes, 4 output pixels per thread:
 //   ssim_fwd: the five moments mu_x, mu_y, E[xx], E[yy], E[xy]; S and its
 //             partial derivatives dS/dmu_x, dS/dE[xx], dS/dE[xy] (written to
 //             the workspace); per-workgroup sums of S and |x - y|;
@@ -25,9 +25,10 @@
 
 namespace gs {
 
-constexpr int kLT = 16;              // output tile edge
+constexpr int kLT = kLossTile;       // output tile edge (32)
 constexpr int kLR = 5;               // window radius
-constexpr int kLS = kLT + 2 * kLR;   // staged edge (26)
+constexpr int kLS = kLT + 2 * kLR;   // staged edge (42)
+constexpr int kLQ = kLT * kLT / 256; // output pixels per thread (4)
 constexpr float kSsimC1 = 0.0001f;   // (0.01)^2
 constexpr float kSsimC2 = 0.0009f;   // (0.03)^2
 
@@ -37,6 +38,10 @@ __device__ __forceinline__ float staged(const float* plane, int W, int H, int x0
   const int x = x0 - kLR + c, y = y0 - kLR + r;
   return (x >= 0 && x < W && y >= 0 && y < H) ? plane[(int64_t)y * W + x] : 0.0f;
 }
+
+// Thread t owns column t % 32 of the tile, rows t / 32 + 8 k (k < 4).
+__device__ __forceinline__ int out_col(int t) { return t & (kLT - 1); }
+__device__ __forceinline__ int out_row(int t, int k) { return (t / kLT) + k * (256 / kLT); }
 
 __global__ __launch_bounds__(256) void ssim_fwd_kernel(const float* __restrict__ image,
                                                        const float* __restrict__ target, LossViews lv,
@@ -57,7 +62,7 @@ __global__ __launch_bounds__(256) void ssim_fwd_kernel(const float* __restrict__
     s_y[i] = staged(yp, W, H, x0, y0, i);
   }
   __syncthreads();
-  // horizontal pass: rows of the staged window, the tile's 16 columns
+  // horizontal pass: rows of the staged window, the tile's columns
   for (int i = t; i < kLS * kLT; i += 256) {
     const int r = i / kLT, c = i - r * kLT;
     float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f;
@@ -77,37 +82,41 @@ __global__ __launch_bounds__(256) void ssim_fwd_kernel(const float* __restrict__
     s_h[4][i] = a4;
   }
   __syncthreads();
-  // vertical pass: one output pixel per thread
-  const int oy = t / kLT, ox = t - oy * kLT;
-  float mx = 0.f, my = 0.f, exx = 0.f, eyy = 0.f, exy = 0.f;
-#pragma unroll
-  for (int k = 0; k < 11; ++k) {
-    const float g = lv.g[k];
-    const int i = (oy + k) * kLT + ox;
-    mx += g * s_h[0][i];
-    my += g * s_h[1][i];
-    exx += g * s_h[2][i];
-    eyy += g * s_h[3][i];
-    exy += g * s_h[4][i];
-  }
-  const int px = x0 + ox, py = y0 + oy;
+  // vertical pass: kLQ output pixels per thread
+  const int ox = out_col(t);
   float s_val = 0.f, l1 = 0.f;
-  if (px < W && py < H) {
-    const float sxx = exx - mx * mx, syy = eyy - my * my, sxy = exy - mx * my;
-    const float n1 = 2.f * mx * my + kSsimC1, n2 = 2.f * sxy + kSsimC2;
-    const float d1 = mx * mx + my * my + kSsimC1, d2 = sxx + syy + kSsimC2;
-    const float id = 1.0f / (d1 * d2);
-    const float S = n1 * n2 * id;
-    const float dmx = 2.f * my * (n2 - n1) * id - 2.f * mx * S * (1.0f / d1 - 1.0f / d2);
-    const float dexx = -S / d2;
-    const float dexy = 2.f * n1 * id;
-    const int64_t pix = (int64_t)py * W + px;
-    const int64_t o = 3 * (poff + pix);  // [pixel][3] partial-derivative triples
-    dmap[o + 0] = dmx;
-    dmap[o + 1] = dexx;
-    dmap[o + 2] = dexy;
-    s_val = S;
-    l1 = fabsf(s_x[(oy + kLR) * kLS + ox + kLR] - s_y[(oy + kLR) * kLS + ox + kLR]);
+#pragma unroll
+  for (int j = 0; j < kLQ; ++j) {
+    const int oy = out_row(t, j);
+    float mx = 0.f, my = 0.f, exx = 0.f, eyy = 0.f, exy = 0.f;
+#pragma unroll
+    for (int k = 0; k < 11; ++k) {
+      const float g = lv.g[k];
+      const int i = (oy + k) * kLT + ox;
+      mx += g * s_h[0][i];
+      my += g * s_h[1][i];
+      exx += g * s_h[2][i];
+      eyy += g * s_h[3][i];
+      exy += g * s_h[4][i];
+    }
+    const int px = x0 + ox, py = y0 + oy;
+    if (px < W && py < H) {
+      const float sxx = exx - mx * mx, syy = eyy - my * my, sxy = exy - mx * my;
+      const float n1 = 2.f * mx * my + kSsimC1, n2 = 2.f * sxy + kSsimC2;
+      const float d1 = mx * mx + my * my + kSsimC1, d2 = sxx + syy + kSsimC2;
+      const float id = 1.0f / (d1 * d2);
+      const float S = n1 * n2 * id;
+      const float dmx = 2.f * my * (n2 - n1) * id - 2.f * mx * S * (1.0f / d1 - 1.0f / d2);
+      const float dexx = -S / d2;
+      const float dexy = 2.f * n1 * id;
+      const int64_t pix = (int64_t)py * W + px;
+      const int64_t o = 3 * (poff + pix);  // [pixel][3] partial-derivative triples
+      dmap[o + 0] = dmx;
+      dmap[o + 1] = dexx;
+      dmap[o + 2] = dexy;
+      s_val += S;
+      l1 += fabsf(s_x[(oy + kLR) * kLS + ox + kLR] - s_y[(oy + kLR) * kLS + ox + kLR]);
+    }
   }
   // fixed-order block sums
   s_val = wave_sum_lane63(s_val);
@@ -119,8 +128,8 @@ __global__ __launch_bounds__(256) void ssim_fwd_kernel(const float* __restrict__
   }
   __syncthreads();
   if (t == 0) {
-    bsum[2 * blockIdx.x + 0] = ((s_red[0][0] + s_red[0][1]) + s_red[0][2]) + s_red[0][3];
-    bsum[2 * blockIdx.x + 1] = ((s_red[1][0] + s_red[1][1]) + s_red[1][2]) + s_red[1][3];
+    bsum[2 * blockIdx.x + 0] = (s_red[0][0] + s_red[0][1]) + (s_red[0][2] + s_red[0][3]);
+    bsum[2 * blockIdx.x + 1] = (s_red[1][0] + s_red[1][1]) + (s_red[1][2] + s_red[1][3]);
   }
 }
 
@@ -166,24 +175,28 @@ __global__ __launch_bounds__(256) void ssim_bwd_kernel(const float* __restrict__
     s_h[2][i] = a2;
   }
   __syncthreads();
-  const int oy = t / kLT, ox = t - oy * kLT;
-  const int px = x0 + ox, py = y0 + oy;
-  if (px >= W || py >= H) return;
-  float wa = 0.f, wb = 0.f, wc = 0.f;
-#pragma unroll
-  for (int k = 0; k < 11; ++k) {
-    const float g = lv.g[k];
-    const int i = (oy + k) * kLT + ox;
-    wa += g * s_h[0][i];
-    wb += g * s_h[1][i];
-    wc += g * s_h[2][i];
-  }
-  const int64_t gi = poff + (int64_t)py * W + px;
-  const float x = image[gi], y = target[gi];
-  const float dsdx = wa + 2.f * x * wb + y * wc;
-  const float sg = x > y ? 1.f : (x < y ? -1.f : 0.f);
+  const int ox = out_col(t);
   const float scale = 1.0f / ((float)lv.nviews * 3.0f * (float)plane_px);
-  dL[gi] = ((1.0f - lambda) * sg - lambda * dsdx) * scale;
+#pragma unroll
+  for (int j = 0; j < kLQ; ++j) {
+    const int oy = out_row(t, j);
+    const int px = x0 + ox, py = y0 + oy;
+    if (px >= W || py >= H) continue;
+    float wa = 0.f, wb = 0.f, wc = 0.f;
+#pragma unroll
+    for (int k = 0; k < 11; ++k) {
+      const float g = lv.g[k];
+      const int i = (oy + k) * kLT + ox;
+      wa += g * s_h[0][i];
+      wb += g * s_h[1][i];
+      wc += g * s_h[2][i];
+    }
+    const int64_t gi = poff + (int64_t)py * W + px;
+    const float x = image[gi], y = target[gi];
+    const float dsdx = wa + 2.f * x * wb + y * wc;
+    const float sg = x > y ? 1.f : (x < y ? -1.f : 0.f);
+    dL[gi] = ((1.0f - lambda) * sg - lambda * dsdx) * scale;
+  }
 }
 
 // Per-view loss from its workgroups' sums: one workgroup per view, each thread

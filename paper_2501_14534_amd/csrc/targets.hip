@@ -17,7 +17,7 @@
 
 namespace gs {
 
-constexpr int kBT = 16;                          // output tile edge
+constexpr int kBT = kBlurTile;                   // output tile edge
 constexpr int kBS = kBT + 2 * kMaxBlurRadius;    // largest staged edge
 
 __device__ __forceinline__ int mirror_index(int i, int n) {
