@@ -9,11 +9,12 @@
 // MFMA: the work per (pixel, splat) pair is ~20 VALU operations and one exp.
 //
 // Sub-tile culling (CULL): while staging a batch, each record's conservative
-// alpha >= 1/255 footprint (the ellipse q <= 2 ln(255 o') bounded by its
-// square, widened by rounding margins) is tested against the pixel box of
-// every wave; each wave then walks only the records whose bit it holds, taken
-// from a ballot in scalar registers.  Culled records fail a per-pixel test
-// for every pixel of that wave, so the result is unchanged.
+// alpha >= 1/255 footprint (the ellipse q <= 2 ln(255 o'), widened by
+// rounding margins) is tested against the live-pixel box of every wave: its
+// bounding box first, then the ellipse itself (the minimum of q over the
+// box); each wave then walks only the records whose bit it holds, taken from
+// a ballot in scalar registers.  Culled records fail a per-pixel test for
+// every pixel of that wave, so the result is unchanged.
 //
 // Forward: lanes whose pixels have terminated drop out of the walk through
 // the exec mask; a wave stops walking once all its pixels are done, and
@@ -116,19 +117,36 @@ __device__ __forceinline__ Box live_box(const float (&px)[PPT], const float (&py
 
 // Bit w set when record (u, v, conic, o', radius) may composite some pixel in
 // wave w's live box.
+// Minimum over the box dx in [X0, X1], dy in [Y0, Y1] (relative to the
+// centre) of q = A dx^2 + 2 B dx dy + C dy^2, positive definite: 0 when the
+// centre is inside, else on an edge, where the 1-D minimiser is clamped to
+// the edge (iA = 1 / A, iC = 1 / C).
+__device__ __forceinline__ float qmin_box(float A, float B, float C, float iA, float iC, float X0, float X1,
+                                          float Y0, float Y1) {
+  if (X0 <= 0.f && X1 >= 0.f && Y0 <= 0.f && Y1 >= 0.f) return 0.f;
+  auto qv = [&](float dx, float dy) { return A * dx * dx + 2.0f * B * dx * dy + C * dy * dy; };
+  const float dyx0 = fminf(fmaxf(-B * X0 * iC, Y0), Y1), dyx1 = fminf(fmaxf(-B * X1 * iC, Y0), Y1);
+  const float dxy0 = fminf(fmaxf(-B * Y0 * iA, X0), X1), dxy1 = fminf(fmaxf(-B * Y1 * iA, X0), X1);
+  return fminf(fminf(qv(X0, dyx0), qv(X1, dyx1)), fminf(qv(dxy0, Y0), qv(dxy1, Y1)));
+}
+
 __device__ __forceinline__ uint32_t footprint_mask(float4 ra, float4 rb, int nwaves, const Box* boxes) {
   const float u = ra.x, v = ra.y, A = ra.z, B = ra.w, C = rb.x, o = rb.y, r = rb.z;
   if (!(o >= kAlphaMin * 0.999f)) return 0u;  // alpha <= o' < 1/255 at every pixel
-  float ex = r, ey = r;
+  float ex = r, ey = r, qm = 0.f, iA = 0.f, iC = 0.f;
+  bool exact = false;
   const float det = A * C - B * B;
   if (det > 0.f) {
     const float tr = 0.5f * (A + C);
     const float lmax = tr + sqrtf(fmaxf(0.f, tr * tr - det));
     if (lmax * lmax <= 1e3f * det) {  // condition number <= 1e3: rounding of q stays far below the margins
-      const float qm = 2.0f * __logf(255.0f * o) * 1.002f + 0.002f;
+      qm = 2.0f * __logf(255.0f * o) * 1.002f + 0.002f;
       const float idet = 1.0f / det;
       ex = fminf(r, sqrtf(fmaxf(qm, 0.f) * C * idet) * 1.001f + 0.01f);
       ey = fminf(r, sqrtf(fmaxf(qm, 0.f) * A * idet) * 1.001f + 0.01f);
+      iA = 1.0f / A;
+      iC = 1.0f / C;
+      exact = true;
     }
   }
   ex += 0.5f;
@@ -136,7 +154,11 @@ __device__ __forceinline__ uint32_t footprint_mask(float4 ra, float4 rb, int nwa
   uint32_t m = 0u;
   for (int w = 0; w < nwaves; ++w) {
     const Box b = boxes[w];
-    const bool hit = (u + ex >= b.x0) && (u - ex <= b.x1) && (v + ey >= b.y0) && (v - ey <= b.y1);
+    bool hit = (u + ex >= b.x0) && (u - ex <= b.x1) && (v + ey >= b.y0) && (v - ey <= b.y1);
+    // the ellipse q <= qm against the box of pixel centres (widened by 1e-3 px):
+    // its bounding box can reach a corner of the box that the ellipse misses
+    if (hit && exact)
+      hit = qmin_box(A, B, C, iA, iC, b.x0 - 1e-3f - u, b.x1 + 1e-3f - u, b.y0 - 1e-3f - v, b.y1 + 1e-3f - v) <= qm;
     m |= hit ? (1u << w) : 0u;
   }
   return m;
