@@ -197,8 +197,7 @@ def main():
     dL = step.dL
     for _ in range(nrep):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
-        for g in step.grads.values():
-            g.zero_()
+        step.grads.zero_()
         ev[0].record(stream)
         r.project(params)
         ev[1].record(stream)

@@ -24,6 +24,18 @@ def to_device(scene, device="cuda") -> Dict[str, torch.Tensor]:
     return {k: torch.from_numpy(np.ascontiguousarray(v, np.float32)).to(device) for k, v in scene.arrays().items()}
 
 
+class Grads(dict):
+    """Gradient tensors by parameter name; `flat` is the buffer they are views of."""
+    flat: Optional[torch.Tensor] = None
+
+    def zero_(self) -> None:
+        if self.flat is not None:
+            self.flat.zero_()
+        else:
+            for g in self.values():
+                g.zero_()
+
+
 def _stream() -> int:
     return torch.cuda.current_stream().cuda_stream
 
@@ -203,7 +215,19 @@ class Rasterizer:
         return out
 
     def zero_grads(self, params) -> Dict[str, torch.Tensor]:
-        return {k: torch.zeros_like(v) for k, v in params.items() if v is not None}
+        """Zeroed gradient tensors shaped like params, views of one flat float32 buffer
+        (each starting on a 256-byte boundary), so that `.flat.zero_()` of the result
+        clears them all in one launch."""
+        items = [(k, v) for k, v in params.items() if v is not None]
+        offs, total = [], 0
+        for _, v in items:
+            offs.append(total)
+            total += (v.numel() + 63) // 64 * 64
+        dev = items[0][1].device if items else self.device
+        flat = torch.zeros(max(total, 1), dtype=torch.float32, device=dev)
+        out = Grads({k: flat[o:o + v.numel()].view(v.shape) for (k, v), o in zip(items, offs)})
+        out.flat = flat
+        return out
 
 
 def significance(params: Dict[str, torch.Tensor], hits: torch.Tensor, volume_quantile: float = 0.9,
@@ -264,6 +288,11 @@ def rasterize(rast: Rasterizer, params: Dict[str, torch.Tensor]) -> torch.Tensor
 def l2_loss_grad(image: torch.Tensor, target: torch.Tensor, views: int, out: torch.Tensor,
                  pixels_per_view: Sequence[int]) -> None:
     """dL/dimage of L = mean over views of mean over 3HW of (image - target)^2, written into `out`."""
+    if len(set(pixels_per_view)) == 1:  # one scale for every view: two launches in all
+        k = 3 * pixels_per_view[0] * len(pixels_per_view)
+        torch.sub(image[:k], target[:k], out=out[:k])
+        out[:k].mul_(2.0 / (3 * pixels_per_view[0] * views))
+        return
     off = 0
     for p in pixels_per_view:
         k = 3 * p
@@ -338,8 +367,7 @@ class Step:
             self.ploss(r.image, self.target, out=self.dL)
         else:
             l2_loss_grad(r.image, self.target, self.loss_views, self.dL, self.pix)
-        for g in self.grads.values():
-            g.zero_()
+        self.grads.zero_()
         grads = self.grads
         if not with_sh_rest:
             grads = {k: v for k, v in self.grads.items() if k != "sh_rest"}
