@@ -12,7 +12,10 @@
  *    its arguments on the host, enqueues kernels on `stream` and returns; no
  *    call reads device memory on the host, so every call may be captured in a
  *    HIP graph.  Scratch memory comes in through `ws` (size from
- *    gs_workspace_size) and is clobbered by the call.
+ *    gs_workspace_size) and is clobbered by the call.  The workspaces of
+ *    gs_bin_sort, gs_render_fwd, gs_render_bwd, gs_blend_bwd, gs_project_bwd
+ *    and gs_count_hits must be 256-byte aligned (hipMalloc and PyTorch
+ *    allocations are); a misaligned one is GS_E_INVALID.
  *  - Layouts are structure-of-arrays with the Gaussian index last: an array
  *    documented [3][n] holds component k of Gaussian i at [k*n + i].
  *  - A "record" is one (view, Gaussian) pair, r = view * n + gaussian.
@@ -234,7 +237,8 @@ int gs_render_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t V, const
 /* The two halves of gs_render_bwd, for callers that schedule or time them
  * separately.  gs_blend_bwd: the per-tile back-to-front walk only; WRITES
  * the per-pair splat gradients (u, v, A, B, C, o', r, g, b) of all K pairs
- * to grad_pair ([capacity][9], indexed by pair_index; no zeroing needed).
+ * to grad_pair ([capacity][9], indexed by pair_index; no zeroing needed;
+ * 16-byte aligned, else GS_E_INVALID).
  * gs_project_bwd: per Gaussian, the sum of its pairs' gradients in emission
  * order, then the chain rule to the raw parameters (the second half of
  * gs_render_bwd), accumulated into `grads`.  ws is the workspace of the

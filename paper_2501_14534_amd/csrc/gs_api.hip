@@ -142,6 +142,7 @@ SortPlan sort_plan(int64_t n, int32_t V, int32_t total_tiles, uint64_t capacity)
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+bool aligned(const void* p, uintptr_t a) { return ((uintptr_t)p & (a - 1)) == 0; }
 
 // Chunk length of the backward work items (2^31: one item per tile).
 int log2_chunk(const gs_opts* o) { return o->bwd_chunk ? ilog2(o->bwd_chunk) : 31; }
@@ -231,14 +232,12 @@ bool binning_ok(const gs_binning* b, int64_t nrec) {
   return true;
 }
 
-// Backward workspace: per-pair gradients [capacity][9] floats, then per-record
-// geometry sums [V*n][6] floats and colour terms [V*n][8] floats.
+// Backward workspace: per-pair gradients [capacity][9] floats, then the
+// per-record planes [kRecPlanes][round_up(V*n, 64)] floats.
 size_t grad_pair_bytes(uint64_t capacity) { return align256(sizeof(float) * GS_GRAD_FLOATS * (size_t)capacity); }
-size_t rec_geo_bytes(int64_t nrec) { return align256(sizeof(float) * 6 * (size_t)nrec); }
-size_t rec_mu_bytes(int64_t nrec) { return align256(sizeof(float) * 8 * (size_t)nrec); }
-size_t bwd_ws_bytes(uint64_t capacity, int64_t nrec) {
-  return grad_pair_bytes(capacity) + rec_geo_bytes(nrec) + rec_mu_bytes(nrec);
-}
+int64_t rec_stride(int64_t nrec) { return (nrec + 63) / 64 * 64; }
+size_t rec_bytes(int64_t nrec) { return sizeof(float) * kRecPlanes * (size_t)rec_stride(nrec); }
+size_t bwd_ws_bytes(uint64_t capacity, int64_t nrec) { return grad_pair_bytes(capacity) + rec_bytes(nrec); }
 
 // Bytes the forward and backward need: the backward's regions, then the chunk states.
 size_t render_ws_bytes(uint64_t capacity, int64_t nrec, const gs_opts* o) {
@@ -269,8 +268,8 @@ ProjectBwdArgs project_bwd_args(ProjectArgs pa, const gs_opts* opts, const gs_pr
   ProjectBwdArgs b;
   b.p = pa;
   b.grad_pair = grad_pair;
-  b.rec_geo = (float*)((char*)ws + grad_pair_bytes(bins->capacity));
-  b.rec_mu = (float*)((char*)ws + grad_pair_bytes(bins->capacity) + rec_geo_bytes(nrec));
+  b.rec = (float*)((char*)ws + grad_pair_bytes(bins->capacity));
+  b.rec_stride = rec_stride(nrec);
   b.tiles_touched = proj->tiles_touched;
   b.offsets = bins->offsets;
   b.status = bins->status;
@@ -345,7 +344,8 @@ int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int32_t V, int6
   if ((int64_t)V * n >= (1ll << 32)) return GS_E_INVALID;
   if (n > 0 && (!proj->splats || !proj->tiles_touched)) return GS_E_INVALID;
   if (!binning_ok(out, (int64_t)V * n)) return GS_E_INVALID;
-  if (ws_bytes < gs_workspace_size(n, V, cams, opts, out->capacity) || (!ws && ws_bytes > 0)) return GS_E_INVALID;
+  if (ws_bytes < gs_workspace_size(n, V, cams, opts, out->capacity) || (!ws && ws_bytes > 0) || !aligned(ws, 256))
+    return GS_E_INVALID;
   const int d = device_ok();
   if (d != GS_OK) return d;
   const SortPlan p = sort_plan(n, V, vt.total_tiles, out->capacity);
@@ -370,7 +370,8 @@ int gs_render_fwd(const gs_projected* proj, const gs_binning* bins, const gs_cam
   if (!proj || n < 0 || !view_table(cams, V, opts, &vt, nullptr)) return GS_E_INVALID;
   if (!image || !T_final || !last_contrib || !binning_ok(bins, (int64_t)V * n)) return GS_E_INVALID;
   if (n > 0 && !proj->splats) return GS_E_INVALID;
-  if (!ws || ws_bytes < render_ws_bytes(bins->capacity, (int64_t)V * n, opts)) return GS_E_INVALID;
+  if (!ws || ws_bytes < render_ws_bytes(bins->capacity, (int64_t)V * n, opts) || !aligned(ws, 256))
+    return GS_E_INVALID;
   const int d = device_ok();
   if (d != GS_OK) return d;
   RenderArgs a = render_args(proj, bins, opts);
@@ -390,7 +391,7 @@ int gs_render_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t V, const
   if (!binning_ok(bins, (int64_t)V * g->n)) return GS_E_INVALID;
   if (g->n > 0 && (!proj->splats || !proj->tiles_touched)) return GS_E_INVALID;
   const int64_t nrec = (int64_t)V * g->n;
-  if (!ws || ws_bytes < render_ws_bytes(bins->capacity, nrec, opts)) return GS_E_INVALID;
+  if (!ws || ws_bytes < render_ws_bytes(bins->capacity, nrec, opts) || !aligned(ws, 256)) return GS_E_INVALID;
   const int d = device_ok();
   if (d != GS_OK) return d;
   hipStream_t s = (hipStream_t)stream;
@@ -441,8 +442,9 @@ int gs_blend_bwd(const gs_camera* cams, int32_t V, int64_t n, const gs_opts* opt
   ViewTable vt;
   if (n < 0 || !view_table(cams, V, opts, &vt, nullptr)) return GS_E_INVALID;
   if (!proj || !T_final || !last_contrib || !dL_dimage || !binning_ok(bins, (int64_t)V * n)) return GS_E_INVALID;
-  if (n > 0 && (!proj->splats || !grad_pair)) return GS_E_INVALID;
-  if (!ws || ws_bytes < render_ws_bytes(bins->capacity, (int64_t)V * n, opts)) return GS_E_INVALID;
+  if (n > 0 && (!proj->splats || !grad_pair || !aligned(grad_pair, 16))) return GS_E_INVALID;
+  if (!ws || ws_bytes < render_ws_bytes(bins->capacity, (int64_t)V * n, opts) || !aligned(ws, 256))
+    return GS_E_INVALID;
   const int d = device_ok();
   if (d != GS_OK) return d;
   RenderArgs ra = render_args(proj, bins, opts);
@@ -461,7 +463,7 @@ int gs_project_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t V, cons
   if (g->n > 0 && (!grad_pair || !proj->tiles_touched)) return GS_E_INVALID;
   const int64_t nrec = (int64_t)V * g->n;
   const size_t need = bwd_ws_bytes(bins->capacity, nrec);
-  if (ws_bytes < need || (!ws && need > 0)) return GS_E_INVALID;
+  if (ws_bytes < need || (!ws && need > 0) || !aligned(ws, 256) || !aligned(grad_pair, 16)) return GS_E_INVALID;
   const int d = device_ok();
   if (d != GS_OK) return d;
   return launched(launch_project_bwd(project_bwd_args(pa, opts, proj, bins, grad_pair, grads, g->sh_degree, ws, nrec),

@@ -78,14 +78,17 @@ struct BinOut {
   int32_t* status;
 };
 
+constexpr int kRecPlanes = 9;
+
 struct ProjectBwdArgs {
   ProjectArgs p;                   // forward inputs (outputs unused)
   const float* grad_pair;          // [K][9], emission order
   const uint32_t* tiles_touched;   // [V*n]
   const uint32_t* offsets;         // [V*n] first emission position of each record
   const int32_t* status;
-  float* rec_geo;                  // [V*n][6] per-record sums of (u, v, A, B, C, o') gradients
-  float* rec_mu;                   // [V*n][4] per-record colour term of the mean gradient
+  float* rec;                      // [kRecPlanes][rec_stride] per record: sums of the (u, v, A, B, C, o')
+                                   // gradients, then the colour term of the mean gradient
+  int64_t rec_stride;              // V*n rounded up to 64
   float* g_means;
   float* g_log_scales;
   float* g_quats;

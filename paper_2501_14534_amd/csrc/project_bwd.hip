@@ -89,34 +89,65 @@ __device__ __forceinline__ float acc_mul_add(float t, float a, float b) {
   return t + p;
 }
 
-// Per record: sums of its pairs' 9 gradients in emission order, accumulated in
-// double and rounded once to float: rec_geo gets (u, v, A, B, C, o'),
-// rec_mu[0..2] the colour sums (8 floats per record: the colour kernel
-// replaces them with the gradient of the clamped colour and writes the colour
-// term of the mean gradient to rec_mu[4..6]).
-__global__ __launch_bounds__(256) void record_sum_kernel(ProjectBwdArgs b, int64_t nrec) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nrec) return;
-  if (*b.status != 0) return;  // binning overflowed: no lists, no gradients
-  const uint32_t cntp = b.tiles_touched[r];
-  if (cntp == 0) return;
+// Sums of the 9 pair gradients of each lane's record (cnt pairs from pair
+// index off; cnt = 0 gives zeros), in emission order, accumulated in double
+// and rounded once to float.  Called by all 64 lanes of a wave together, for
+// records of consecutive Gaussians in one view: their pairs form one
+// contiguous run of the [K][9] array (emission order is record order), which
+// the wave copies into LDS window by window with 16-byte loads of consecutive
+// addresses; each lane then adds its own pairs from LDS.  (Loading its pairs
+// directly would touch a separate cache line per lane and load.)
+constexpr int kSumWindow = 256;  // pairs per window (9 x 256 floats = 576 float4, 9 per lane)
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
+#pragma unroll
+  for (int m = 1; m < kWave; m <<= 1) x = min(x, (uint32_t)__shfl_xor((int)x, m));
+  return x;
+}
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
+#pragma unroll
+  for (int m = 1; m < kWave; m <<= 1) x = max(x, (uint32_t)__shfl_xor((int)x, m));
+  return x;
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ void record_sums(const float* __restrict__ grad_pair, uint32_t cnt, uint32_t off,
+                                            float4* win4, int lane, float out[GS_GRAD_FLOATS]) {
   double gsum[GS_GRAD_FLOATS] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  const float* gp = b.grad_pair + (size_t)b.offsets[r] * GS_GRAD_FLOATS;
-  for (uint32_t k = 0; k < cntp; ++k)
+  const uint32_t lo = wave_min_u32(cnt ? off : 0xffffffffu);
+  const uint32_t hi = wave_max_u32(cnt ? off + cnt : 0u);
+  float* win = (float*)win4;
+  for (uint32_t w0 = lo & ~3u; w0 < hi; w0 += kSumWindow) {  // window starts on 16 bytes
+    const uint32_t w1 = min(w0 + (uint32_t)kSumWindow, hi);
+    const int nfl = (int)(w1 - w0) * GS_GRAD_FLOATS, nf4 = nfl / 4;
+    const float* src = grad_pair + (size_t)w0 * GS_GRAD_FLOATS;
+    // loads straight into LDS, no registers in between: lane l of load j
+    // fills float4 64 j + l (lanes past the window are masked off), then
+    // lanes 0 .. nfl % 4 - 1 the floats after the last whole float4
+    constexpr int kPerLane = kSumWindow * GS_GRAD_FLOATS / 4 / kWave;
 #pragma unroll
-    for (int c = 0; c < GS_GRAD_FLOATS; ++c) gsum[c] += (double)gp[(size_t)k * GS_GRAD_FLOATS + c];
-  float* geo = b.rec_geo + r * 6;
+    for (int j = 0; j < kPerLane; ++j)
+      if (lane + j * kWave < nf4)
+        __builtin_amdgcn_global_load_lds((const void*)((const float4*)src + lane + j * kWave),
+                                         (__attribute__((address_space(3))) void*)(win4 + j * kWave), 16, 0, 0);
+    if (lane < nfl % 4)
+      __builtin_amdgcn_global_load_lds((const void*)(src + nf4 * 4 + lane),
+                                       (__attribute__((address_space(3))) void*)(win + nf4 * 4), 4, 0, 0);
+    __builtin_amdgcn_s_waitcnt(0);  // the LDS writes of the loads above have landed
+    wave_lds_sync();
+    const uint32_t k1 = min(off + cnt, w1);
+    for (uint32_t k = max(off, w0); k < k1; ++k)
 #pragma unroll
-  for (int c = 0; c < 6; ++c) geo[c] = (float)gsum[c];
-  if (b.g_mean2d) {
-    const int64_t n = b.p.n, v = r / n, i = r - v * n;
-    b.g_mean2d[(v * 2 + 0) * n + i] += (float)gsum[0];
-    b.g_mean2d[(v * 2 + 1) * n + i] += (float)gsum[1];
+      for (int c = 0; c < GS_GRAD_FLOATS; ++c) gsum[c] += (double)win[(k - w0) * GS_GRAD_FLOATS + c];
+    wave_lds_sync();  // every lane has read the window before the next one overwrites it
   }
-  float* cmu = b.rec_mu + r * 8;
-  cmu[0] = (float)gsum[6];
-  cmu[1] = (float)gsum[7];
-  cmu[2] = (float)gsum[8];
+#pragma unroll
+  for (int c = 0; c < GS_GRAD_FLOATS; ++c) out[c] = (float)gsum[c];
 }
 
 // Views (bit v) in which record (v, i) touches a tile.
@@ -147,120 +178,141 @@ __device__ __forceinline__ void view_dir(const ViewArgs& c, const float mu[3], f
   *dx = d0 * *il, *dy = d1 * *il, *dz = d2 * *il;
 }
 
-// Colour chain per Gaussian over the views: the gradient of the clamped
-// colour (gpre, kept in rec_mu[0..2] for the SH-rest kernel), the diffuse
-// colour and band-mask gradients, and the colour term of the mean gradient
-// (rec_mu[4..6], through the view direction).
-template <int DEG>
-__global__ __launch_bounds__(256) void project_bwd_color_kernel(ProjectBwdArgs b, ViewTable vt) {
+// Per Gaussian over the views: the record sums of each visible view
+// (record_sums), then the colour chain: the gradient of the clamped colour,
+// the diffuse colour and band-mask gradients, with REST the SH bands 1..DEG
+// (sum over the views of Y_k(d_v) times that gradient; bands whose hard mask
+// is off get nothing), and the colour term of the mean gradient (through the
+// view direction).  Every lane of a wave writes its record's planes in each
+// view the wave visits (zeros where the Gaussian is not visible), so the
+// record planes are written in whole cache lines.
+template <int DEG, bool REST>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void project_bwd_color_kernel(
+    ProjectBwdArgs b, ViewTable vt) {
+  __shared__ float4 s_win[256 / kWave][kSumWindow * GS_GRAD_FLOATS / 4];
+  if (*b.status != 0) return;  // binning overflowed: no lists, no gradients
   const ProjectArgs& a = b.p;
   const int64_t n = a.n;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  if (*b.status != 0) return;  // binning overflowed: no lists, no gradients
-  const uint32_t vis = visible_views(b, vt.nviews, n, i);
-  if (!vis) return;  // culled or off-screen in every view
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const bool valid = i < n;
+  const int V = vt.nviews;
+  const uint32_t vis = valid ? visible_views(b, V, n, i) : 0u;
+  if (__ballot(vis != 0u) == 0) return;  // the whole wave: culled or off-screen everywhere
 
-  float mu[3], dc[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    mu[k] = a.means[k * n + i];
-    dc[k] = a.sh_dc[k * n + i];
-  }
   constexpr int NR = DEG > 0 ? (DEG + 1) * (DEG + 1) - 1 : 1;
+  float mu[3] = {0.f, 0.f, 0.f}, dc[3] = {0.f, 0.f, 0.f};
   float rest[NR][3];
-  float bm[3];
-  bool band_on[4];
-  band_masks(a, n, i, bm, band_on);
-  if (DEG > 0) {
-    // every band's coefficients are read: the band-mask gradient needs them
-    // even when the band is off (straight-through estimator)
+  float bm[3] = {0.f, 0.f, 0.f};
+  bool band_on[4] = {true, true, true, true};
 #pragma unroll
-    for (int k = 1; k <= NR; ++k)
+  for (int k = 0; k < NR; ++k) rest[k][0] = rest[k][1] = rest[k][2] = 0.f;
+  if (vis) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) rest[k - 1][c] = a.sh_rest[((k - 1) * 3 + c) * n + i];
+    for (int k = 0; k < 3; ++k) {
+      mu[k] = a.means[k * n + i];
+      dc[k] = a.sh_dc[k * n + i];
+    }
+    band_masks(a, n, i, bm, band_on);
+    if (DEG > 0) {
+      // every band's coefficients are read: the band-mask gradient needs them
+      // even when the band is off (straight-through estimator)
+#pragma unroll
+      for (int k = 1; k <= NR; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) rest[k - 1][c] = a.sh_rest[((k - 1) * 3 + c) * n + i];
+    }
   }
   float tdc[3] = {0.f, 0.f, 0.f}, tbm[3] = {0.f, 0.f, 0.f};
+  float trest[REST ? NR : 1][3];
+#pragma unroll
+  for (int k = 0; k < (REST ? NR : 1); ++k) trest[k][0] = trest[k][1] = trest[k][2] = 0.f;
 
-  // the visible views in order; the next one's colour sums load while this one is processed
-  uint32_t pend = vis;
-  int v = __builtin_ctz(pend);
-  pend &= pend - 1;
-  float4 cur = *(const float4*)(b.rec_mu + ((size_t)v * n + i) * 8);
-  for (;;) {
-    const bool more = pend != 0;
-    const int vn = more ? __builtin_ctz(pend) : v;
-    pend &= pend - 1;
-    const float4 nxt = *(const float4*)(b.rec_mu + ((size_t)vn * n + i) * 8);
-    const size_t r = (size_t)v * n + i;
-    float* cmu = b.rec_mu + r * 8;  // colour sums of this record's pairs (record_sum_kernel)
-    const float grgb[3] = {cur.x, cur.y, cur.z};
-    if (grgb[0] == 0.f && grgb[1] == 0.f && grgb[2] == 0.f) {
-      cmu[4] = cmu[5] = cmu[6] = 0.f;
-      if (!more) break;
-      v = vn;
-      cur = nxt;
-      continue;
-    }
-    const ViewArgs& c = vt.v[v];
-    float pre[3] = {dc[0], dc[1], dc[2]};
-    float Y[15];
-    float dx = 0.f, dy = 0.f, dz = 0.f, il = 1.f;
-    if (DEG > 0) {
-      view_dir(c, mu, &dx, &dy, &dz, &il);
-      sh_basis15(dx, dy, dz, Y);
-      // flat loops with constant trip counts keep rest/Y in registers
-#pragma unroll
-      for (int k = 1; k < kShCoeffs; ++k) {
-        const int l = sh_band(k);
-        if (l > DEG || !band_on[l]) continue;
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) pre[ch] += Y[k - 1] * rest[k - 1][ch];
-      }
-    }
-    float gpre[3];
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-      gpre[ch] = pre[ch] < 0.f ? 0.f : grgb[ch];
-      tdc[ch] = acc_add(tdc[ch], gpre[ch]);
+  // v is the same in every lane: camera constants are scalar loads, and a
+  // wave's records in view v are consecutive
+  for (int v = 0; v < V; ++v) {
+    const bool on = (vis >> v) & 1u;
+    if (__ballot(on) == 0) continue;
+    const int64_t r = (int64_t)v * n + i;
+    const uint32_t cnt = on ? b.tiles_touched[r] : 0u;
+    const uint32_t off = on ? b.offsets[r] : 0u;
+    float g9[GS_GRAD_FLOATS];
+    record_sums(b.grad_pair, cnt, off, s_win[wave], lane, g9);
+    if (b.g_mean2d && on) {
+      b.g_mean2d[(v * 2 + 0) * n + i] += g9[0];
+      b.g_mean2d[(v * 2 + 1) * n + i] += g9[1];
     }
     float gmu_col[3] = {0.f, 0.f, 0.f};
-    if (DEG > 0) {
-      float wY[15];
+    const float grgb[3] = {g9[6], g9[7], g9[8]};
+    if (on && (grgb[0] != 0.f || grgb[1] != 0.f || grgb[2] != 0.f)) {
+      const ViewArgs& c = vt.v[v];
+      float pre[3] = {dc[0], dc[1], dc[2]};
+      float Y[15];
+      float dx = 0.f, dy = 0.f, dz = 0.f, il = 1.f;
+      if (DEG > 0) {
+        view_dir(c, mu, &dx, &dy, &dz, &il);
+        sh_basis15(dx, dy, dz, Y);
+        // flat loops with constant trip counts keep rest/Y in registers
 #pragma unroll
-      for (int k = 0; k < 15; ++k) wY[k] = 0.f;
-      float band[3] = {0.f, 0.f, 0.f};
+        for (int k = 1; k < kShCoeffs; ++k) {
+          const int l = sh_band(k);
+          if (l > DEG || !band_on[l]) continue;
 #pragma unroll
-      for (int k = 1; k < kShCoeffs; ++k) {
-        const int l = sh_band(k);
-        if (l > DEG) continue;
-        const float cg = rest[k - 1][0] * gpre[0] + rest[k - 1][1] * gpre[1] + rest[k - 1][2] * gpre[2];
-        band[l - 1] += Y[k - 1] * cg;
-        if (band_on[l]) wY[k - 1] = cg;
+          for (int ch = 0; ch < 3; ++ch) pre[ch] += Y[k - 1] * rest[k - 1][ch];
+        }
       }
+      float gpre[3];
 #pragma unroll
-      for (int l = 1; l <= DEG; ++l) {
-        const float sb = sigmoidf(bm[l - 1]);
-        tbm[l - 1] = acc_mul_add(tbm[l - 1], band[l - 1], sb * (1.f - sb));
+      for (int ch = 0; ch < 3; ++ch) {
+        gpre[ch] = pre[ch] < 0.f ? 0.f : grgb[ch];
+        tdc[ch] = acc_add(tdc[ch], gpre[ch]);
       }
-      float gdx, gdy, gdz;
-      sh_grad15(dx, dy, dz, wY, &gdx, &gdy, &gdz);
-      const float dot = dx * gdx + dy * gdy + dz * gdz;
-      gmu_col[0] = (gdx - dx * dot) * il;
-      gmu_col[1] = (gdy - dy * dot) * il;
-      gmu_col[2] = (gdz - dz * dot) * il;
+      if (DEG > 0) {
+        float wY[15];
+#pragma unroll
+        for (int k = 0; k < 15; ++k) wY[k] = 0.f;
+        float band[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k = 1; k < kShCoeffs; ++k) {
+          const int l = sh_band(k);
+          if (l > DEG) continue;
+          const float cg = rest[k - 1][0] * gpre[0] + rest[k - 1][1] * gpre[1] + rest[k - 1][2] * gpre[2];
+          band[l - 1] += Y[k - 1] * cg;
+          if (band_on[l]) wY[k - 1] = cg;
+        }
+#pragma unroll
+        for (int l = 1; l <= DEG; ++l) {
+          const float sb = sigmoidf(bm[l - 1]);
+          tbm[l - 1] = acc_mul_add(tbm[l - 1], band[l - 1], sb * (1.f - sb));
+        }
+        float gdx, gdy, gdz;
+        sh_grad15(dx, dy, dz, wY, &gdx, &gdy, &gdz);
+        const float dot = dx * gdx + dy * gdy + dz * gdz;
+        gmu_col[0] = (gdx - dx * dot) * il;
+        gmu_col[1] = (gdy - dy * dot) * il;
+        gmu_col[2] = (gdz - dz * dot) * il;
+        if (REST && (gpre[0] != 0.f || gpre[1] != 0.f || gpre[2] != 0.f)) {  // else it adds exact zeros
+#pragma unroll
+          for (int k = 1; k < kShCoeffs; ++k) {
+            const int l = sh_band(k);
+            if (l > DEG || !band_on[l]) continue;
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch)
+              trest[k - 1][ch] = acc_mul_add(trest[k - 1][ch], Y[k - 1], gpre[ch]);
+          }
+        }
+      }
     }
-    cmu[0] = gpre[0];
-    cmu[1] = gpre[1];
-    cmu[2] = gpre[2];
-    cmu[4] = gmu_col[0];
-    cmu[5] = gmu_col[1];
-    cmu[6] = gmu_col[2];
-    if (!more) break;
-    v = vn;
-    cur = nxt;
+    if (valid) {
+      float* rp = b.rec + r;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) rp[k * b.rec_stride] = on ? g9[k] : 0.f;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) rp[(6 + k) * b.rec_stride] = gmu_col[k];
+    }
   }
 
+  if (!vis) return;
 #pragma unroll
   for (int k = 0; k < 3; ++k)
     if (b.g_sh_dc) b.g_sh_dc[k * n + i] += tdc[k];
@@ -268,62 +320,12 @@ __global__ __launch_bounds__(256) void project_bwd_color_kernel(ProjectBwdArgs b
 #pragma unroll
     for (int l = 1; l <= DEG; ++l) b.g_sh_mask_logits[(l - 1) * n + i] += tbm[l - 1];
   }
-}
-
-// SH bands 1..DEG of the colour gradient: sum over the views of Y_k(d_v) times
-// the clamped colour's gradient (bands whose hard mask is off get nothing),
-// added to the SH-rest gradient.  Not launched when that gradient is not
-// asked for (the steps between sparse SH-rest updates).
-template <int DEG>
-__global__ __launch_bounds__(256) void project_bwd_shrest_kernel(ProjectBwdArgs b, ViewTable vt) {
-  const ProjectArgs& a = b.p;
-  const int64_t n = a.n;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  if (*b.status != 0) return;
-  const uint32_t vis = visible_views(b, vt.nviews, n, i);
-  if (!vis) return;
-  float mu[3];
+  if (REST) {
 #pragma unroll
-  for (int k = 0; k < 3; ++k) mu[k] = a.means[k * n + i];
-  float bm[3];
-  bool band_on[4];
-  band_masks(a, n, i, bm, band_on);
-  constexpr int NR = (DEG + 1) * (DEG + 1) - 1;
-  float trest[NR][3];
+    for (int k = 1; k <= NR; ++k)
 #pragma unroll
-  for (int k = 0; k < NR; ++k) trest[k][0] = trest[k][1] = trest[k][2] = 0.f;
-  // the visible views in order; the next one's gradient loads while this one is processed
-  uint32_t pend = vis;
-  int v = __builtin_ctz(pend);
-  pend &= pend - 1;
-  float4 cur = *(const float4*)(b.rec_mu + ((size_t)v * n + i) * 8);  // the clamped colour's gradient
-  for (;;) {
-    const bool more = pend != 0;
-    const int vn = more ? __builtin_ctz(pend) : v;
-    pend &= pend - 1;
-    const float4 nxt = *(const float4*)(b.rec_mu + ((size_t)vn * n + i) * 8);
-    const float gpre[3] = {cur.x, cur.y, cur.z};
-    if (gpre[0] != 0.f || gpre[1] != 0.f || gpre[2] != 0.f) {  // else it adds exact zeros
-      float dx, dy, dz, il, Y[15];
-      view_dir(vt.v[v], mu, &dx, &dy, &dz, &il);
-      sh_basis15(dx, dy, dz, Y);
-#pragma unroll
-      for (int k = 1; k < kShCoeffs; ++k) {
-        const int l = sh_band(k);
-        if (l > DEG || !band_on[l]) continue;
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) trest[k - 1][ch] = acc_mul_add(trest[k - 1][ch], Y[k - 1], gpre[ch]);
-      }
-    }
-    if (!more) break;
-    v = vn;
-    cur = nxt;
+      for (int c = 0; c < 3; ++c) b.g_sh_rest[((k - 1) * 3 + c) * n + i] += trest[k - 1][c];
   }
-#pragma unroll
-  for (int k = 1; k <= NR; ++k)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) b.g_sh_rest[((k - 1) * 3 + c) * n + i] += trest[k - 1][c];
 }
 
 __global__ __launch_bounds__(256) void project_bwd_geom_kernel(ProjectBwdArgs b, ViewTable vt) {
@@ -374,15 +376,16 @@ __global__ __launch_bounds__(256) void project_bwd_geom_kernel(ProjectBwdArgs b,
 
   float tmu[3] = {0.f, 0.f, 0.f}, tls[3] = {0.f, 0.f, 0.f}, tq[4] = {0.f, 0.f, 0.f, 0.f};
   float top = 0.f, tmask = 0.f;
-  for (uint32_t pend = vis; pend != 0; pend &= pend - 1) {  // the visible views in order
-    const int v = __builtin_ctz(pend);
-    const size_t r = (size_t)v * n + i;
-    const float* geo = b.rec_geo + r * 6;
-    const float* cmu = b.rec_mu + r * 8 + 4;  // colour term of the mean gradient
-    const double gu = geo[0], gv = geo[1], gA = geo[2], gB = geo[3], gC = geo[4], go = geo[5];
-    const float cm0 = cmu[0], cm1 = cmu[1], cm2 = cmu[2];
-    if (gu == 0.0 && gv == 0.0 && gA == 0.0 && gB == 0.0 && gC == 0.0 && go == 0.0 && cm0 == 0.f && cm1 == 0.f &&
-        cm2 == 0.f)
+  // the views in order, v wave-uniform as in the colour kernel
+  const int V = vt.nviews;
+  for (int v = 0; v < V; ++v) {
+    if (!((vis >> v) & 1u)) continue;
+    const float* rp = b.rec + (size_t)v * n + i;
+    const int64_t rs = b.rec_stride;
+    const double gu = rp[0], gv = rp[rs], gA = rp[2 * rs], gB = rp[3 * rs], gC = rp[4 * rs], go = rp[5 * rs];
+    const float cmu[3] = {rp[6 * rs], rp[7 * rs], rp[8 * rs]};  // colour term of the mean gradient
+    if (gu == 0.0 && gv == 0.0 && gA == 0.0 && gB == 0.0 && gC == 0.0 && go == 0.0 && cmu[0] == 0.f &&
+        cmu[1] == 0.f && cmu[2] == 0.f)
       continue;
     const ViewArgs& c = vt.v[v];
     const double fx = c.fx, fy = c.fy;
@@ -505,20 +508,21 @@ __global__ __launch_bounds__(256) void project_bwd_geom_kernel(ProjectBwdArgs b,
 hipError_t launch_project_bwd(const ProjectBwdArgs& a, const ViewTable& vt, int deg, hipStream_t s) {
   if (a.p.n == 0) return hipSuccess;
   const dim3 block(256), grid((unsigned)((a.p.n + 255) / 256));
-  const int64_t nrec = (int64_t)vt.nviews * a.p.n;
-  hipLaunchKernelGGL(record_sum_kernel, dim3((unsigned)((nrec + 255) / 256)), block, 0, s, a, nrec);
+  const bool rest = a.g_sh_rest != nullptr && deg > 0;
   switch (deg) {
-    case 0: hipLaunchKernelGGL(project_bwd_color_kernel<0>, grid, block, 0, s, a, vt); break;
-    case 1: hipLaunchKernelGGL(project_bwd_color_kernel<1>, grid, block, 0, s, a, vt); break;
-    case 2: hipLaunchKernelGGL(project_bwd_color_kernel<2>, grid, block, 0, s, a, vt); break;
-    default: hipLaunchKernelGGL(project_bwd_color_kernel<3>, grid, block, 0, s, a, vt); break;
-  }
-  if (a.g_sh_rest && deg > 0) {
-    switch (deg) {
-      case 1: hipLaunchKernelGGL(project_bwd_shrest_kernel<1>, grid, block, 0, s, a, vt); break;
-      case 2: hipLaunchKernelGGL(project_bwd_shrest_kernel<2>, grid, block, 0, s, a, vt); break;
-      default: hipLaunchKernelGGL(project_bwd_shrest_kernel<3>, grid, block, 0, s, a, vt); break;
-    }
+    case 0: hipLaunchKernelGGL((project_bwd_color_kernel<0, false>), grid, block, 0, s, a, vt); break;
+    case 1:
+      if (rest) hipLaunchKernelGGL((project_bwd_color_kernel<1, true>), grid, block, 0, s, a, vt);
+      else hipLaunchKernelGGL((project_bwd_color_kernel<1, false>), grid, block, 0, s, a, vt);
+      break;
+    case 2:
+      if (rest) hipLaunchKernelGGL((project_bwd_color_kernel<2, true>), grid, block, 0, s, a, vt);
+      else hipLaunchKernelGGL((project_bwd_color_kernel<2, false>), grid, block, 0, s, a, vt);
+      break;
+    default:
+      if (rest) hipLaunchKernelGGL((project_bwd_color_kernel<3, true>), grid, block, 0, s, a, vt);
+      else hipLaunchKernelGGL((project_bwd_color_kernel<3, false>), grid, block, 0, s, a, vt);
+      break;
   }
   hipLaunchKernelGGL(project_bwd_geom_kernel, grid, block, 0, s, a, vt);
   return hipGetLastError();

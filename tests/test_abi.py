@@ -148,6 +148,13 @@ def test_other_entry_points_reject_null_buffers(lib):
                             4096, 1 << 30, None) == gs.GS_E_INVALID
     assert lib.gs_blend_bwd(cams, 1, 64, C.byref(o), C.byref(proj), C.byref(bins), 4096, 4096, 4096, 4096,
                             None, 1 << 30, None) == gs.GS_E_INVALID  # workspace missing
+    # alignment: workspaces on 256 bytes, the pair gradients on 16
+    assert lib.gs_bin_sort(C.byref(proj), cams, 1, 64, C.byref(o), C.byref(bins), 4096 + 16, 1 << 30, None) == \
+        gs.GS_E_INVALID
+    assert lib.gs_blend_bwd(cams, 1, 64, C.byref(o), C.byref(proj), C.byref(bins), 4096, 4096, 4096, 4100,
+                            4096, 1 << 30, None) == gs.GS_E_INVALID
+    assert lib.gs_blend_bwd(cams, 1, 64, C.byref(o), C.byref(proj), C.byref(bins), 4096, 4096, 4096, 4096,
+                            4096 + 64, 1 << 30, None) == gs.GS_E_INVALID
 
 
 def test_loss_entry_points_validate_on_the_host(lib):
