@@ -44,6 +44,18 @@ __device__ __forceinline__ uint32_t effective_count(const uint32_t* count, const
   return *status != 0 ? 0u : *count;
 }
 
+// Data block of workgroup p among the first `nact` workgroups: workgroups are
+// dealt round-robin to the 8 XCDs, so p % 8 is p's XCD; the remap gives each
+// XCD a contiguous stretch of data blocks.  Neighbouring blocks share the
+// cache lines at the ends of their output runs (the scatter) and the lines
+// of their histogram column (32 blocks per line), which are then completed in
+// one L2 and written back whole.
+__device__ __forceinline__ int64_t xcd_block(int64_t p, int64_t nact) {
+  constexpr int kXcds = 8;
+  const int64_t q = nact / kXcds;
+  return p < q * kXcds ? (p % kXcds) * q + p / kXcds : p;
+}
+
 // Exclusive scan of one value per thread over a 256-thread block.
 __device__ __forceinline__ uint32_t block_exclusive_scan_256(uint32_t x, uint32_t* total, uint32_t* s_wave) {
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
@@ -317,7 +329,8 @@ __global__ __launch_bounds__(kSortThreads) void radix_hist(const KT* __restrict_
   const uint32_t K = effective_count(count, status);
   h[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  const int64_t blk = xcd_block((int64_t)blockIdx.x, ((int64_t)K + kSortTile - 1) / kSortTile);
+  const int64_t base = blk * kSortTile;
   if (base < K) {
 #pragma unroll 4
     for (int k = 0; k < kSortItems; ++k) {
@@ -326,7 +339,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_hist(const KT* __restrict_
     }
   }
   __syncthreads();
-  hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+  hist[(int64_t)threadIdx.x * nblk + blk] = h[threadIdx.x];
 }
 
 // One block per digit: exclusive scan of that digit's counts over the sort
@@ -392,8 +405,10 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter(const uint32_t* __
   __shared__ uint32_t s_v[kSortTile];
   __shared__ uint32_t s_v2[NV == 2 ? kSortTile : 1];
   const uint32_t K = effective_count(count, status);
-  const int64_t base = (int64_t)blockIdx.x * kSortTile;
-  if (base >= K) return;  // uniform across the block
+  const int64_t nact = ((int64_t)K + kSortTile - 1) / kSortTile;
+  if ((int64_t)blockIdx.x >= nact) return;  // uniform across the block
+  const int64_t blk = xcd_block((int64_t)blockIdx.x, nact);
+  const int64_t base = blk * kSortTile;
   const int nvalid = (int)min((int64_t)kSortTile, (int64_t)K - base);
   const int t = threadIdx.x, lane = t & (kWave - 1), wave = t / kWave;
 #pragma unroll
@@ -436,7 +451,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter(const uint32_t* __
     const uint32_t lb = block_exclusive_scan_256(run, &tot, s_wave);
     const uint32_t dbase = block_exclusive_scan_256(digit_total[t], &tot, s_wave);
     s_lbase[t] = lb;
-    s_gbase[t] = dbase + hist[(int64_t)t * nblk + blockIdx.x];
+    s_gbase[t] = dbase + hist[(int64_t)t * nblk + blk];
   }
   __syncthreads();
 #pragma unroll

@@ -3,19 +3,16 @@
 // call and added (+=) to the caller's gradient arrays.  Straight-through
 // estimator for the hard masks (Eq. 3, Eq. 5): d(mask)/d(logit) = sigmoid'.
 //
-// Four kernels (no atomics):
-//   sums:     one thread per (view, Gaussian) record: its pairs' gradients
-//             summed in emission order (double), rounded once to float (adjacent
-//             records' pairs are adjacent, so a wave reads one contiguous stretch);
-//   colour:   one thread per Gaussian: the SH chain (diffuse colour,
-//             band-mask logits, and the view-direction term of the mean) in
-//             single precision;
-//   SH rest:  one thread per Gaussian: bands 1..3 of the colour gradient (its
-//             own kernel, so neither half holds both the coefficients and
-//             their 45 accumulators; skipped when that gradient is not asked
-//             for);
-//   geometry: one thread per Gaussian: the EWA chain in double precision (this half is bound by
-//             memory traffic, and the 2x2 inverse amplifies rounding by the
+// Two kernels (no atomics):
+//   colour:   one thread per Gaussian, the views in order: first its record's
+//             pair gradients summed in emission order (double, rounded once to
+//             float; a wave's records in one view own one contiguous run of
+//             pairs, staged through LDS), then the SH chain in single
+//             precision (diffuse colour, band-mask logits, bands 1..3 when that
+//             gradient is asked for, and the view-direction term of the mean);
+//             the record sums and the colour term go to per-record planes;
+//   geometry: one thread per Gaussian, reading those planes: the EWA chain
+//             in double precision (the 2x2 inverse amplifies rounding by the
 //             condition number of Sigma'):
 //     dL/dSigma'  = -Q G_Q Q              (G_Q = [[gA, gB/2], [gB/2, gC]], Q = conic)
 //     dL/dSigma   = T^T dL/dSigma' T,     dL/dT = 2 dL/dSigma' T Sigma,  T = J W
@@ -99,17 +96,6 @@ __device__ __forceinline__ float acc_mul_add(float t, float a, float b) {
 // directly would touch a separate cache line per lane and load.)
 constexpr int kSumWindow = 256;  // pairs per window (9 x 256 floats = 576 float4, 9 per lane)
 
-__device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
-#pragma unroll
-  for (int m = 1; m < kWave; m <<= 1) x = min(x, (uint32_t)__shfl_xor((int)x, m));
-  return x;
-}
-__device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
-#pragma unroll
-  for (int m = 1; m < kWave; m <<= 1) x = max(x, (uint32_t)__shfl_xor((int)x, m));
-  return x;
-}
-
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -119,8 +105,11 @@ __device__ __forceinline__ void wave_lds_sync() {
 __device__ __forceinline__ void record_sums(const float* __restrict__ grad_pair, uint32_t cnt, uint32_t off,
                                             float4* win4, int lane, float out[GS_GRAD_FLOATS]) {
   double gsum[GS_GRAD_FLOATS] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  const uint32_t lo = wave_min_u32(cnt ? off : 0xffffffffu);
-  const uint32_t hi = wave_max_u32(cnt ? off + cnt : 0u);
+  // offsets grow with the lane (consecutive records), so the run starts at
+  // the first lane with pairs and ends after the last one's
+  const uint64_t act = __ballot(cnt != 0u);
+  const uint32_t lo = act ? (uint32_t)__builtin_amdgcn_readlane((int)off, __builtin_ctzll(act)) : 0u;
+  const uint32_t hi = act ? (uint32_t)__builtin_amdgcn_readlane((int)(off + cnt), 63 - __builtin_clzll(act)) : 0u;
   float* win = (float*)win4;
   for (uint32_t w0 = lo & ~3u; w0 < hi; w0 += kSumWindow) {  // window starts on 16 bytes
     const uint32_t w1 = min(w0 + (uint32_t)kSumWindow, hi);
@@ -230,12 +219,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void p
 
   // v is the same in every lane: camera constants are scalar loads, and a
   // wave's records in view v are consecutive
+  // (the next view's pair counts and offsets load while this view is processed)
+  uint32_t cnt_next = (vis & 1u) ? b.tiles_touched[i] : 0u, off_next = (vis & 1u) ? b.offsets[i] : 0u;
   for (int v = 0; v < V; ++v) {
     const bool on = (vis >> v) & 1u;
-    if (__ballot(on) == 0) continue;
     const int64_t r = (int64_t)v * n + i;
-    const uint32_t cnt = on ? b.tiles_touched[r] : 0u;
-    const uint32_t off = on ? b.offsets[r] : 0u;
+    const uint32_t cnt = cnt_next, off = off_next;
+    if (v + 1 < V) {
+      const bool on1 = (vis >> (v + 1)) & 1u;
+      cnt_next = on1 ? b.tiles_touched[r + n] : 0u;
+      off_next = on1 ? b.offsets[r + n] : 0u;
+    }
+    if (__ballot(on) == 0) continue;
     float g9[GS_GRAD_FLOATS];
     record_sums(b.grad_pair, cnt, off, s_win[wave], lane, g9);
     if (b.g_mean2d && on) {
