@@ -342,24 +342,36 @@ __global__ __launch_bounds__(kSortThreads) void radix_hist(const KT* __restrict_
   hist[(int64_t)threadIdx.x * nblk + blk] = h[threadIdx.x];
 }
 
-// One block per digit: exclusive scan of that digit's counts over the sort
-// blocks (in place) and the digit's total.
+// One block per digit: exclusive scan of that digit's counts over the first
+// nact sort blocks, the ones holding keys (in place), and the digit's total.
+// Each thread takes 4 consecutive columns per step of 1024.
 __global__ __launch_bounds__(256) void radix_digit_scan(uint32_t* __restrict__ hist, int64_t nblk,
+                                                        const uint32_t* __restrict__ count,
+                                                        const int32_t* __restrict__ status,
                                                         uint32_t* __restrict__ digit_total) {
   __shared__ uint32_t s_wave[4];
   __shared__ uint32_t s_carry;
+  const int64_t nact = ((int64_t)effective_count(count, status) + kSortTile - 1) / kSortTile;
   uint32_t* row = hist + (int64_t)blockIdx.x * nblk;
   if (threadIdx.x == 0) s_carry = 0;
   __syncthreads();
-  for (int64_t base = 0; base < nblk; base += 256) {
-    const int64_t i = base + threadIdx.x;
-    const uint32_t x = i < nblk ? row[i] : 0u;
+  for (int64_t base = 0; base < nact; base += 4 * 256) {
+    const int64_t i0 = base + 4 * (int64_t)threadIdx.x;
+    uint32_t x[4], sum = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      x[j] = i0 + j < nact ? row[i0 + j] : 0u;
+      sum += x[j];
+    }
     uint32_t tot;
-    const uint32_t ex = block_exclusive_scan_256(x, &tot, s_wave);
-    const uint32_t carry = s_carry;
-    if (i < nblk) row[i] = carry + ex;
+    uint32_t ex = block_exclusive_scan_256(sum, &tot, s_wave) + s_carry;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (i0 + j < nact) row[i0 + j] = ex;
+      ex += x[j];
+    }
     __syncthreads();
-    if (threadIdx.x == 0) s_carry = carry + tot;
+    if (threadIdx.x == 0) s_carry += tot;
     __syncthreads();
   }
   if (threadIdx.x == 0) digit_total[blockIdx.x] = s_carry;
@@ -628,7 +640,7 @@ static void radix_sort(KT* k0, uint32_t* v0, uint32_t* u0, KT* k1, uint32_t* v1,
     const int shift = 8 * p;
     hipLaunchKernelGGL((radix_hist<KT>), dim3((unsigned)nblk), dim3(kSortThreads), 0, s, kb[cur], count, status,
                        shift, nblk, w.hist);
-    hipLaunchKernelGGL(radix_digit_scan, dim3(kRadix), dim3(256), 0, s, w.hist, nblk, w.digit_total);
+    hipLaunchKernelGGL(radix_digit_scan, dim3(kRadix), dim3(256), 0, s, w.hist, nblk, count, status, w.digit_total);
     hipLaunchKernelGGL((radix_scatter<NV>), dim3((unsigned)nblk), dim3(kSortThreads), 0, s, kb[cur], vb[cur],
                        ub[cur], kb[cur ^ 1], vb[cur ^ 1], ub[cur ^ 1], count, status, shift, nblk, w.hist,
                        w.digit_total);
