@@ -106,15 +106,21 @@ __global__ __launch_bounds__(kScanThreads) void count_reduce(const uint32_t* __r
 __global__ __launch_bounds__(1024) void scan_top(const uint32_t* __restrict__ sums, int64_t nb,
                                                  uint32_t* __restrict__ offsets, uint64_t capacity,
                                                  uint32_t* total_out, int32_t* status) {
+  constexpr int kItems = 8;  // consecutive sums per thread: 8192 per step, one step up to 8M records
   __shared__ uint32_t s_wave[16];
   __shared__ unsigned long long s_carry;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   if (threadIdx.x == 0) s_carry = 0;
   __syncthreads();
-  for (int64_t base = 0; base < nb; base += 1024) {
-    const int64_t i = base + threadIdx.x;
-    const uint32_t x = i < nb ? sums[i] : 0u;
-    uint32_t incl = x;
+  for (int64_t base = 0; base < nb; base += kItems * 1024) {
+    const int64_t i0 = base + (int64_t)kItems * threadIdx.x;
+    uint32_t x[kItems], sum = 0;
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      x[j] = i0 + j < nb ? sums[i0 + j] : 0u;
+      sum += x[j];
+    }
+    uint32_t incl = sum;
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) {
       const uint32_t y = __shfl_up(incl, o, kWave);
@@ -129,7 +135,12 @@ __global__ __launch_bounds__(1024) void scan_top(const uint32_t* __restrict__ su
       tot += c;
     }
     const unsigned long long carry = s_carry;
-    if (i < nb) offsets[i] = (uint32_t)(carry + off + incl - x);
+    unsigned long long ex = carry + off + incl - sum;
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      if (i0 + j < nb) offsets[i0 + j] = (uint32_t)ex;
+      ex += x[j];
+    }
     __syncthreads();
     if (threadIdx.x == 0) s_carry = carry + tot;
     __syncthreads();
