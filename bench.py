@@ -197,7 +197,6 @@ def main():
     dL = step.dL
     for _ in range(nrep):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
-        step.grads.zero_()
         ev[0].record(stream)
         r.project(params)
         ev[1].record(stream)
@@ -207,7 +206,7 @@ def main():
         ev[3].record(stream)
         r.blend_bwd(dL, grad_pair)
         ev[4].record(stream)
-        r.project_bwd(params, grad_pair, step.grads)
+        r.project_bwd(params, grad_pair, step.grads, assign=True)
         ev[5].record(stream)
         torch.cuda.synchronize()
         for i, k in enumerate(names):

@@ -157,9 +157,14 @@ typedef struct gs_binning {
   int32_t* status;   /* device, 1 word */
 } gs_binning;
 
-/* Gradients, ACCUMULATED (+=) into caller-zeroed arrays shaped like the
- * parameters.  Any member may be NULL to skip it.  mean2d, if given, is
- * [V][2][n] and receives dL/d(u, v) (densification statistics).            */
+/* Gradients, arrays shaped like the parameters.  Any member may be NULL to
+ * skip it.  assign = 0: ACCUMULATED (+=) into the arrays (zero them first for
+ * a plain gradient); assign = 1: WRITTEN, every Gaussian's entry (zeros where
+ * it gets no gradient), so no zeroing is needed.  Either way a member the call
+ * does not compute is left as it is: sh_rest and sh_mask_logits at SH degree
+ * 0, mask_logits when the Gaussians have no volume-mask logits.  mean2d, if
+ * given, is [V][2][n], receives dL/d(u, v) (densification statistics) and is
+ * always accumulated; gs_mask_loss always accumulates.                     */
 typedef struct gs_grads {
   float* means;
   float* log_scales;
@@ -170,6 +175,7 @@ typedef struct gs_grads {
   float* mask_logits;
   float* sh_mask_logits;
   float* mean2d;
+  int32_t assign;
 } gs_grads;
 
 /* Number of tiles and pixels of V views under `opts` (host only). */
@@ -227,7 +233,7 @@ int gs_render_fwd(const gs_projected* proj, const gs_binning* bins, const gs_cam
  * emission order and the chain rule runs to the raw parameters including the
  * straight-through mask gradients (Eq. 3, Eq. 5).  No atomics: the result is
  * bitwise reproducible, and a batched call equals the sum of per-view calls
- * made in view order.  Gradients are accumulated into `grads`.
+ * made in view order.  Gradients go to `grads` (added or written, see gs_grads).
  * Needs ws_bytes >= gs_workspace_size(...). */
 int gs_render_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t V, const gs_opts* opts,
                   const gs_projected* proj, const gs_binning* bins, const float* T_final,
@@ -241,7 +247,7 @@ int gs_render_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t V, const
  * 16-byte aligned, else GS_E_INVALID).
  * gs_project_bwd: per Gaussian, the sum of its pairs' gradients in emission
  * order, then the chain rule to the raw parameters (the second half of
- * gs_render_bwd), accumulated into `grads`.  ws is the workspace of the
+ * gs_render_bwd), added to or written into `grads`.  ws is the workspace of the
  * step's gs_render_fwd (ws_bytes >= gs_workspace_size(...)); grad_pair may
  * point at its start, as it does inside gs_render_bwd.                      */
 int gs_blend_bwd(const gs_camera* cams, int32_t V, int64_t n, const gs_opts* opts, const gs_projected* proj,

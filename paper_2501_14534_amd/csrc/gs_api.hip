@@ -281,6 +281,7 @@ ProjectBwdArgs project_bwd_args(ProjectArgs pa, const gs_opts* opts, const gs_pr
   b.g_sh_rest = deg > 0 ? grads->sh_rest : nullptr;
   b.g_mask_logits = grads->mask_logits;
   b.g_sh_mask_logits = deg > 0 ? grads->sh_mask_logits : nullptr;
+  b.assign = grads->assign != 0;
   b.g_mean2d = grads->mean2d;
   return b;
 }

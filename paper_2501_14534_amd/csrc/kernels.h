@@ -98,6 +98,7 @@ struct ProjectBwdArgs {
   float* g_mask_logits;
   float* g_sh_mask_logits;
   float* g_mean2d;
+  int32_t assign;                  // 1: write the parameter gradients (zeros where none), 0: add them
 };
 
 // Views of an image call (loss: 32 x 32 tiles; target blur: 16 x 16): per

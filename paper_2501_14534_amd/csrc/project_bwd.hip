@@ -139,6 +139,30 @@ __device__ __forceinline__ void record_sums(const float* __restrict__ grad_pair,
   for (int c = 0; c < GS_GRAD_FLOATS; ++c) out[c] = (float)gsum[c];
 }
 
+// A parameter gradient: written (assign) or added.
+__device__ __forceinline__ void grad_out(float* g, bool assign, float t) { *g = assign ? t : *g + t; }
+
+// Colour-kernel outputs of Gaussian i.
+template <int DEG, bool REST>
+__device__ __forceinline__ void colour_grads_out(const ProjectBwdArgs& b, int64_t n, int64_t i, const float tdc[3],
+                                                 const float tbm[3], const float (*trest)[3]) {
+  const bool as = b.assign != 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    if (b.g_sh_dc) grad_out(&b.g_sh_dc[k * n + i], as, tdc[k]);
+  if (DEG > 0 && b.g_sh_mask_logits && b.p.sh_mask_logits) {
+#pragma unroll
+    for (int l = 1; l <= DEG; ++l) grad_out(&b.g_sh_mask_logits[(l - 1) * n + i], as, tbm[l - 1]);
+  }
+  if (REST) {
+    constexpr int NR = (DEG + 1) * (DEG + 1) - 1;
+#pragma unroll
+    for (int k = 1; k <= NR; ++k)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) grad_out(&b.g_sh_rest[((k - 1) * 3 + c) * n + i], as, trest[k - 1][c]);
+  }
+}
+
 // Views (bit v) in which record (v, i) touches a tile.
 __device__ __forceinline__ uint32_t visible_views(const ProjectBwdArgs& b, int V, int64_t n, int64_t i) {
   uint32_t vis = 0;
@@ -179,15 +203,24 @@ template <int DEG, bool REST>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void project_bwd_color_kernel(
     ProjectBwdArgs b, ViewTable vt) {
   __shared__ float4 s_win[256 / kWave][kSumWindow * GS_GRAD_FLOATS / 4];
-  if (*b.status != 0) return;  // binning overflowed: no lists, no gradients
   const ProjectArgs& a = b.p;
   const int64_t n = a.n;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const bool valid = i < n;
   const int V = vt.nviews;
-  const uint32_t vis = valid ? visible_views(b, V, n, i) : 0u;
-  if (__ballot(vis != 0u) == 0) return;  // the whole wave: culled or off-screen everywhere
+  constexpr int NRT = REST ? (DEG + 1) * (DEG + 1) - 1 : 1;
+  const float zero3[3] = {0.f, 0.f, 0.f};
+  float trest[NRT][3];
+#pragma unroll
+  for (int k = 0; k < NRT; ++k) trest[k][0] = trest[k][1] = trest[k][2] = 0.f;
+  // binning overflowed (no lists, no gradients), or the whole wave culled or
+  // off-screen everywhere: zeros when the gradients are written, else nothing
+  const uint32_t vis = valid && *b.status == 0 ? visible_views(b, V, n, i) : 0u;
+  if (__ballot(vis != 0u) == 0) {
+    if (b.assign && valid) colour_grads_out<DEG, REST>(b, n, i, zero3, zero3, trest);
+    return;
+  }
 
   constexpr int NR = DEG > 0 ? (DEG + 1) * (DEG + 1) - 1 : 1;
   float mu[3] = {0.f, 0.f, 0.f}, dc[3] = {0.f, 0.f, 0.f};
@@ -213,9 +246,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void p
     }
   }
   float tdc[3] = {0.f, 0.f, 0.f}, tbm[3] = {0.f, 0.f, 0.f};
-  float trest[REST ? NR : 1][3];
-#pragma unroll
-  for (int k = 0; k < (REST ? NR : 1); ++k) trest[k][0] = trest[k][1] = trest[k][2] = 0.f;
 
   // v is the same in every lane: camera constants are scalar loads, and a
   // wave's records in view v are consecutive
@@ -307,20 +337,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void p
     }
   }
 
-  if (!vis) return;
+  if (!valid || (!vis && !b.assign)) return;
+  colour_grads_out<DEG, REST>(b, n, i, tdc, tbm, trest);
+}
+
+// Geometry-kernel outputs of Gaussian i (null arrays: zeros).
+__device__ __forceinline__ void geom_grads_out(const ProjectBwdArgs& b, int64_t n, int64_t i, const float* tmu,
+                                               const float* tls, const float* tq, float top, float tmask) {
+  const bool as = b.assign != 0;
 #pragma unroll
-  for (int k = 0; k < 3; ++k)
-    if (b.g_sh_dc) b.g_sh_dc[k * n + i] += tdc[k];
-  if (DEG > 0 && b.g_sh_mask_logits && a.sh_mask_logits) {
-#pragma unroll
-    for (int l = 1; l <= DEG; ++l) b.g_sh_mask_logits[(l - 1) * n + i] += tbm[l - 1];
+  for (int k = 0; k < 3; ++k) {
+    if (b.g_means) grad_out(&b.g_means[k * n + i], as, tmu ? tmu[k] : 0.f);
+    if (b.g_log_scales) grad_out(&b.g_log_scales[k * n + i], as, tls ? tls[k] : 0.f);
   }
-  if (REST) {
 #pragma unroll
-    for (int k = 1; k <= NR; ++k)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) b.g_sh_rest[((k - 1) * 3 + c) * n + i] += trest[k - 1][c];
-  }
+  for (int k = 0; k < 4; ++k)
+    if (b.g_quats) grad_out(&b.g_quats[k * n + i], as, tq ? tq[k] : 0.f);
+  if (b.g_opacity_logits) grad_out(&b.g_opacity_logits[i], as, top);
+  if (b.g_mask_logits && b.p.mask_logits) grad_out(&b.g_mask_logits[i], as, tmask);
 }
 
 __global__ __launch_bounds__(256) void project_bwd_geom_kernel(ProjectBwdArgs b, ViewTable vt) {
@@ -328,9 +362,11 @@ __global__ __launch_bounds__(256) void project_bwd_geom_kernel(ProjectBwdArgs b,
   const int64_t n = a.n;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  if (*b.status != 0) return;
-  const uint32_t vis = visible_views(b, vt.nviews, n, i);
-  if (!vis) return;
+  const uint32_t vis = *b.status == 0 ? visible_views(b, vt.nviews, n, i) : 0u;
+  if (!vis) {  // no gradient (culled, off-screen, or the binning overflowed)
+    if (b.assign) geom_grads_out(b, n, i, nullptr, nullptr, nullptr, 0.f, 0.f);
+    return;
+  }
 
   float mu[3], ls[3], q[4];
 #pragma unroll
@@ -488,16 +524,7 @@ __global__ __launch_bounds__(256) void project_bwd_geom_kernel(ProjectBwdArgs b,
       tmask = acc_add(tmask, (float)((go * op + gsc[0] * s[0] + gsc[1] * s[1] + gsc[2] * s[2]) * sm * (1.0 - sm)));
   }
 
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    if (b.g_means) b.g_means[k * n + i] += tmu[k];
-    if (b.g_log_scales) b.g_log_scales[k * n + i] += tls[k];
-  }
-#pragma unroll
-  for (int k = 0; k < 4; ++k)
-    if (b.g_quats) b.g_quats[k * n + i] += tq[k];
-  if (b.g_opacity_logits) b.g_opacity_logits[i] += top;
-  if (b.g_mask_logits && a.mask_logits) b.g_mask_logits[i] += tmask;
+  geom_grads_out(b, n, i, tmu, tls, tq, top, tmask);
 }
 
 hipError_t launch_project_bwd(const ProjectBwdArgs& a, const ViewTable& vt, int deg, hipStream_t s) {

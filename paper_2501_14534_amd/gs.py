@@ -56,7 +56,7 @@ class GsBinning(C.Structure):
 
 class GsGrads(C.Structure):
     _fields_ = [("means", vp), ("log_scales", vp), ("quats", vp), ("opacity_logits", vp), ("sh_dc", vp),
-                ("sh_rest", vp), ("mask_logits", vp), ("sh_mask_logits", vp), ("mean2d", vp)]
+                ("sh_rest", vp), ("mask_logits", vp), ("sh_mask_logits", vp), ("mean2d", vp), ("assign", C.c_int32)]
 
 
 _lib = None

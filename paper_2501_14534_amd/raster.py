@@ -122,11 +122,12 @@ class Rasterizer:
                  "gs_render_fwd")
 
     def render_bwd(self, params, dL_dimage: torch.Tensor, grads: Dict[str, torch.Tensor],
-                   mean2d: Optional[torch.Tensor] = None) -> None:
+                   mean2d: Optional[torch.Tensor] = None, assign: bool = False) -> None:
+        """Gradients into `grads`: added, or with assign=True written (no zeroing needed)."""
         g = self.gaussians(params)
         if dL_dimage.numel() != self.image.numel() or not dL_dimage.is_contiguous():
             raise ValueError("dL_dimage must be contiguous and shaped like the image")
-        gr = gs.GsGrads(*[gs.ptr(grads.get(k)) for k in PARAM_NAMES], gs.ptr(mean2d))
+        gr = gs.GsGrads(*[gs.ptr(grads.get(k)) for k in PARAM_NAMES], gs.ptr(mean2d), int(assign))
         gs.check(gs.render_bwd(g, self.cams_arr, self.V, self.opts_s, self.proj, self.bins, gs.ptr(self.T_final),
                                gs.ptr(self.last), gs.ptr(dL_dimage), gr, gs.ptr(self.ws), self.ws_bytes, _stream()),
                  "gs_render_bwd")
@@ -139,9 +140,10 @@ class Rasterizer:
                               gs.ptr(self.last), gs.ptr(dL_dimage), gs.ptr(grad_pair), gs.ptr(self.ws),
                               self.ws_bytes, _stream()), "gs_blend_bwd")
 
-    def project_bwd(self, params, grad_pair: torch.Tensor, grads: Dict[str, torch.Tensor], mean2d=None) -> None:
+    def project_bwd(self, params, grad_pair: torch.Tensor, grads: Dict[str, torch.Tensor], mean2d=None,
+                    assign: bool = False) -> None:
         g = self.gaussians(params)
-        gr = gs.GsGrads(*[gs.ptr(grads.get(k)) for k in PARAM_NAMES], gs.ptr(mean2d))
+        gr = gs.GsGrads(*[gs.ptr(grads.get(k)) for k in PARAM_NAMES], gs.ptr(mean2d), int(assign))
         gs.check(gs.project_bwd(g, self.cams_arr, self.V, self.opts_s, self.proj, self.bins, gs.ptr(grad_pair), gr,
                                 gs.ptr(self.ws), self.ws_bytes, _stream()), "gs_project_bwd")
 
@@ -367,11 +369,15 @@ class Step:
             self.ploss(r.image, self.target, out=self.dL)
         else:
             l2_loss_grad(r.image, self.target, self.loss_views, self.dL, self.pix)
-        self.grads.zero_()
+        # the gradients are written, not added: only the ones this step does not write are
+        # cleared (the SH-rest gradient on sparse steps; the SH gradients at degree 0)
         grads = self.grads
         if not with_sh_rest:
             grads = {k: v for k, v in self.grads.items() if k != "sh_rest"}
-        r.render_bwd(self.params, self.dL, grads)
+        for k in self.grads:
+            if (k == "sh_rest" and not with_sh_rest) or (r.deg == 0 and k in ("sh_rest", "sh_mask_logits")):
+                self.grads[k].zero_()
+        r.render_bwd(self.params, self.dL, grads, assign=True)
         if self.mask_loss is not None:
             g = r.gaussians(self.params)
             gr = gs.GsGrads(*[gs.ptr(grads.get(k)) for k in PARAM_NAMES], None)

@@ -344,3 +344,31 @@ def test_full_size_sampled_parity(P, cfg):
     print(" ", bad)
     for k, (nb, worst) in bad.items():
         assert nb == 0, (k, nb, worst)
+
+
+@pytest.mark.parametrize("deg,masks", [(3, True), (1, False)])
+def test_assign_mode_writes_what_accumulate_adds(P, deg, masks):
+    """Gradients written (assign) over arrays of garbage equal zeroed-then-accumulated ones, bit for
+    bit, with culled and off-screen Gaussians among them; accumulate mode adds onto what is there."""
+    wl = scenes.tiny(n=300, seed=7, deg=deg, masks=masks, band_masks=masks)
+    print(f"[edge] assign mode deg={deg} masks={masks}", flush=True)
+    r, params = P.gpu_forward(wl)
+    rng = np.random.default_rng(11)
+    dL = torch.from_numpy(rng.standard_normal(3 * r.total_pixels).astype(np.float32) * 1e-3).cuda()
+    ref = r.zero_grads(params)
+    r.backward(params, dL, ref)
+    got = r.zero_grads(params)
+    for g in got.values():
+        g.copy_(torch.from_numpy(rng.standard_normal(g.numel()).astype(np.float32)).cuda().view(g.shape))
+    base = {k: v.clone() for k, v in got.items()}
+    r.render_bwd(params, dL, got, assign=True)
+    torch.cuda.synchronize()
+    for k in ref:
+        if deg == 0 and k in ("sh_rest", "sh_mask_logits"):
+            continue
+        assert torch.equal(got[k], ref[k]), k
+    acc = {k: v.clone() for k, v in base.items()}
+    r.render_bwd(params, dL, acc)
+    torch.cuda.synchronize()
+    for k in ref:
+        assert torch.equal(acc[k], base[k] + ref[k]), k
