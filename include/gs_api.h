@@ -242,9 +242,11 @@ int gs_render_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t V, const
 
 /* The two halves of gs_render_bwd, for callers that schedule or time them
  * separately.  gs_blend_bwd: the per-tile back-to-front walk only; WRITES
- * the per-pair splat gradients (u, v, A, B, C, o', r, g, b) of all K pairs
- * to grad_pair ([capacity][9], indexed by pair_index; no zeroing needed;
- * 16-byte aligned, else GS_E_INVALID).
+ * the per-pair splat gradients (u, v, A, B, C, o', r, g, b) of the pairs the
+ * walk reaches to grad_pair ([capacity][9], indexed by pair_index; 16-byte
+ * aligned, else GS_E_INVALID) and marks them in ws; the rows of the pairs
+ * behind every pixel's last contributor are left as they are and count as
+ * zero (no zeroing needed).
  * gs_project_bwd: per Gaussian, the sum of its pairs' gradients in emission
  * order, then the chain rule to the raw parameters (the second half of
  * gs_render_bwd), added to or written into `grads`.  ws is the workspace of the

@@ -184,6 +184,7 @@ RenderArgs render_args(const gs_projected* p, const gs_binning* b, const gs_opts
   a.splats = (const float4*)p->splats;
   a.ids = b->ids;
   a.pair_index = b->pair_index;
+  a.pair_live = nullptr;
   a.ranges = b->ranges;
   a.order = b->order;
   a.status = b->status;
@@ -232,12 +233,19 @@ bool binning_ok(const gs_binning* b, int64_t nrec) {
   return true;
 }
 
-// Backward workspace: per-pair gradients [capacity][9] floats, then the
-// per-record planes [kRecPlanes][round_up(V*n, 64)] floats.
+// Backward workspace: per-pair gradients [capacity][9] floats, the per-record
+// planes [kRecPlanes][round_up(V*n, 64)] floats, then one byte per pair (row
+// written this step), padded so that whole words can be read past the end.
 size_t grad_pair_bytes(uint64_t capacity) { return align256(sizeof(float) * GS_GRAD_FLOATS * (size_t)capacity); }
 int64_t rec_stride(int64_t nrec) { return (nrec + 63) / 64 * 64; }
 size_t rec_bytes(int64_t nrec) { return sizeof(float) * kRecPlanes * (size_t)rec_stride(nrec); }
-size_t bwd_ws_bytes(uint64_t capacity, int64_t nrec) { return grad_pair_bytes(capacity) + rec_bytes(nrec); }
+size_t live_bytes(uint64_t capacity) { return align256((size_t)capacity + 256); }
+size_t bwd_ws_bytes(uint64_t capacity, int64_t nrec) {
+  return grad_pair_bytes(capacity) + rec_bytes(nrec) + live_bytes(capacity);
+}
+uint8_t* pair_live_ptr(const void* ws, uint64_t capacity, int64_t nrec) {
+  return (uint8_t*)ws + grad_pair_bytes(capacity) + rec_bytes(nrec);
+}
 
 // Bytes the forward and backward need: the backward's regions, then the chunk states.
 size_t render_ws_bytes(uint64_t capacity, int64_t nrec, const gs_opts* o) {
@@ -245,6 +253,7 @@ size_t render_ws_bytes(uint64_t capacity, int64_t nrec, const gs_opts* o) {
 }
 
 void attach_state(RenderArgs* a, uint64_t capacity, int64_t nrec, const gs_opts* o, const void* ws) {
+  a->pair_live = pair_live_ptr(ws, capacity, nrec);
   char* base = (char*)ws + bwd_ws_bytes(capacity, nrec);
   a->slot_owner = (uint32_t*)base;
   a->state = (float4*)(base + state_owner_bytes(capacity, o));
@@ -270,6 +279,7 @@ ProjectBwdArgs project_bwd_args(ProjectArgs pa, const gs_opts* opts, const gs_pr
   b.grad_pair = grad_pair;
   b.rec = (float*)((char*)ws + grad_pair_bytes(bins->capacity));
   b.rec_stride = rec_stride(nrec);
+  b.pair_live = pair_live_ptr(ws, bins->capacity, nrec);
   b.tiles_touched = proj->tiles_touched;
   b.offsets = bins->offsets;
   b.status = bins->status;
@@ -399,7 +409,8 @@ int gs_render_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t V, const
   float* grad_pair = (float*)ws;
   RenderArgs ra = render_args(proj, bins, opts);
   attach_state(&ra, bins->capacity, nrec, opts, ws);
-  hipError_t e = launch_render_bwd(ra, vt, T_final, last_contrib, dL_dimage, grad_pair, s);
+  hipError_t e = launch_fill_u32((uint32_t*)ra.pair_live, (int64_t)(live_bytes(bins->capacity) / 4), 0u, s);
+  if (e == hipSuccess) e = launch_render_bwd(ra, vt, T_final, last_contrib, dL_dimage, grad_pair, s);
   if (e != hipSuccess) return GS_E_HIP;
   return launched(launch_project_bwd(project_bwd_args(pa, opts, proj, bins, grad_pair, grads, g->sh_degree, ws, nrec),
                                      vt, g->sh_degree, s));
@@ -450,6 +461,9 @@ int gs_blend_bwd(const gs_camera* cams, int32_t V, int64_t n, const gs_opts* opt
   if (d != GS_OK) return d;
   RenderArgs ra = render_args(proj, bins, opts);
   attach_state(&ra, bins->capacity, (int64_t)V * n, opts, ws);
+  const hipError_t e =
+      launch_fill_u32((uint32_t*)ra.pair_live, (int64_t)(live_bytes(bins->capacity) / 4), 0u, (hipStream_t)stream);
+  if (e != hipSuccess) return GS_E_HIP;
   return launched(launch_render_bwd(ra, vt, T_final, last_contrib, dL_dimage, grad_pair, (hipStream_t)stream));
 }
 

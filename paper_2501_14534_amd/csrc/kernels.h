@@ -30,6 +30,7 @@ struct RenderArgs {
   const float4* splats;
   const uint32_t* ids;
   const uint32_t* pair_index;
+  uint8_t* pair_live;     // backward: [capacity] 1 where the pair's gradient row was written
   const uint32_t* ranges;
   const uint32_t* order;  // tile schedule (NULL: tile-id order)
   const int32_t* status;
@@ -85,6 +86,7 @@ struct ProjectBwdArgs {
   const float* grad_pair;          // [K][9], emission order
   const uint32_t* tiles_touched;   // [V*n]
   const uint32_t* offsets;         // [V*n] first emission position of each record
+  const uint8_t* pair_live;        // [K] 1 where the walk wrote the pair's row (others count as zero)
   const int32_t* status;
   float* rec;                      // [kRecPlanes][rec_stride] per record: sums of the (u, v, A, B, C, o')
                                    // gradients, then the colour term of the mean gradient

@@ -102,8 +102,9 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ void record_sums(const float* __restrict__ grad_pair, uint32_t cnt, uint32_t off,
-                                            float4* win4, int lane, float out[GS_GRAD_FLOATS]) {
+__device__ __forceinline__ void record_sums(const float* __restrict__ grad_pair, const uint8_t* __restrict__ live,
+                                            uint32_t cnt, uint32_t off, float4* win4, uint32_t* livew, int lane,
+                                            float out[GS_GRAD_FLOATS]) {
   double gsum[GS_GRAD_FLOATS] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   // offsets grow with the lane (consecutive records), so the run starts at
   // the first lane with pairs and ends after the last one's
@@ -127,12 +128,19 @@ __device__ __forceinline__ void record_sums(const float* __restrict__ grad_pair,
     if (lane < nfl % 4)
       __builtin_amdgcn_global_load_lds((const void*)(src + nf4 * 4 + lane),
                                        (__attribute__((address_space(3))) void*)(win + nf4 * 4), 4, 0, 0);
+    // the pairs' live bytes, a word per lane (w0 is a multiple of 4; the array
+    // is padded past the last pair)
+    if (lane < (int)(w1 - w0 + 3) / 4)
+      __builtin_amdgcn_global_load_lds((const void*)(live + w0 + 4 * lane),
+                                       (__attribute__((address_space(3))) void*)livew, 4, 0, 0);
     __builtin_amdgcn_s_waitcnt(0);  // the LDS writes of the loads above have landed
     wave_lds_sync();
     const uint32_t k1 = min(off + cnt, w1);
+    const uint8_t* lv = (const uint8_t*)livew;
     for (uint32_t k = max(off, w0); k < k1; ++k)
+      if (lv[k - w0])  // rows of pairs the walk did not reach are not written: they count as zero
 #pragma unroll
-      for (int c = 0; c < GS_GRAD_FLOATS; ++c) gsum[c] += (double)win[(k - w0) * GS_GRAD_FLOATS + c];
+        for (int c = 0; c < GS_GRAD_FLOATS; ++c) gsum[c] += (double)win[(k - w0) * GS_GRAD_FLOATS + c];
     wave_lds_sync();  // every lane has read the window before the next one overwrites it
   }
 #pragma unroll
@@ -203,6 +211,7 @@ template <int DEG, bool REST>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void project_bwd_color_kernel(
     ProjectBwdArgs b, ViewTable vt) {
   __shared__ float4 s_win[256 / kWave][kSumWindow * GS_GRAD_FLOATS / 4];
+  __shared__ uint32_t s_live[256 / kWave][kSumWindow / 4];
   const ProjectArgs& a = b.p;
   const int64_t n = a.n;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -262,7 +271,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void p
     }
     if (__ballot(on) == 0) continue;
     float g9[GS_GRAD_FLOATS];
-    record_sums(b.grad_pair, cnt, off, s_win[wave], lane, g9);
+    record_sums(b.grad_pair, b.pair_live, cnt, off, s_win[wave], s_live[wave], lane, g9);
     if (b.g_mean2d && on) {
       b.g_mean2d[(v * 2 + 0) * n + i] += g9[0];
       b.g_mean2d[(v * 2 + 1) * n + i] += g9[1];

@@ -201,15 +201,17 @@ class Rasterizer:
     def splat_records(self) -> torch.Tensor:
         return self.splats[: self.V * self.n * gs.SPLAT_FLOATS].view(self.V * self.n, gs.SPLAT_FLOATS)
 
-    def grad_pairs(self) -> torch.Tensor:
-        """Per-pair splat gradients (emission order) left in the workspace by the last backward."""
-        k = self.pairs() * gs.GRAD_FLOATS
-        return self.ws[: 4 * k].view(torch.float32).view(-1, gs.GRAD_FLOATS)
+    def grad_pairs(self, dL_dimage: torch.Tensor) -> torch.Tensor:
+        """Per-pair splat gradients [K, 9] (emission order) of the current lists for dL_dimage, zero
+        for the pairs the walk does not reach (for inspection: a separate backward walk)."""
+        gp = torch.zeros(max(self.capacity, 1) * gs.GRAD_FLOATS, dtype=torch.float32, device=self.device)
+        self.blend_bwd(dL_dimage, gp)
+        return gp[: self.pairs() * gs.GRAD_FLOATS].view(-1, gs.GRAD_FLOATS)
 
-    def grad_records(self) -> torch.Tensor:
-        """Per-record sums of the last backward's pair gradients [V*n, 9] (float64, for inspection)."""
+    def grad_records(self, dL_dimage: torch.Tensor) -> torch.Tensor:
+        """Per-record sums of the pair gradients for dL_dimage [V*n, 9] (float64, for inspection)."""
         nrec = self.V * self.n
-        gp = self.grad_pairs().double()
+        gp = self.grad_pairs(dL_dimage).double()
         tt = self.tiles_touched[:nrec].long()
         owner = torch.repeat_interleave(torch.arange(nrec, device=gp.device), tt)
         out = torch.zeros(nrec, gs.GRAD_FLOATS, dtype=torch.float64, device=gp.device)

@@ -140,7 +140,7 @@ def check_backward(wl, opts, r, params, flagged, seed=0) -> dict:
         n = wl.scene.n
         O.project_bwd(wl.scene, c, opts, grad_rec[v * n:(v + 1) * n], og)
     res = {}
-    gpu_rec = r.grad_records().cpu().numpy()
+    gpu_rec = r.grad_records(dL).cpu().numpy()
     res["grad_rec"] = r24_violations(gpu_rec, grad_rec)
     for k, ref in og.items():
         res[k] = r24_violations(grads[k].cpu().numpy(), ref)
