@@ -4,7 +4,7 @@
       per-kernel call count and average/total duration from a
       `rocprofv3 --kernel-trace --stats --output-format csv` run.
   python -m paper_2501_14534_amd.profiling traffic FETCH_DIR WRITE_DIR --kernel K --workload W
-      --copy-bytes B --cmd "..." [--json profiles/pmc_traffic.json] [--out profiles/NAME.md]
+      --copy-bytes B --cmd "..." [--json profiles/pmc_traffic.json] [--key NAME] [--out profiles/NAME.md]
       HBM bytes per launch of kernel K from two `--pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs
       (KiB per dispatch), each scaled by what the same counter reads for the plain copy kernel
       of B bytes that `bench.py --calibration-copy-bytes B` launches (an elementwise multiply
@@ -128,7 +128,7 @@ def cmd_traffic(a):
                  hbm_bytes_per_launch=byts, dispatches=len(kf), command=a.cmd)
     if a.json:
         d = json.load(open(a.json)) if os.path.exists(a.json) else {}
-        d[f"{a.kernel}@{a.workload}"] = entry
+        d[f"{a.key or a.kernel}@{a.workload}"] = entry
         with open(a.json, "w") as f:
             json.dump(d, f, indent=1, sort_keys=True)
     text = "\n".join([
@@ -156,6 +156,7 @@ def main(argv=None):
     t.add_argument("fetch_dir")
     t.add_argument("write_dir")
     t.add_argument("--kernel", required=True)
+    t.add_argument("--key", default=None, help="name under which --json files the entry (default: --kernel)")
     t.add_argument("--workload", required=True)
     t.add_argument("--copy-bytes", type=int, required=True)
     t.add_argument("--copy-pattern", default="elementwise")
