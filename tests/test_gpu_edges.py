@@ -372,3 +372,29 @@ def test_assign_mode_writes_what_accumulate_adds(P, deg, masks):
     torch.cuda.synchronize()
     for k in ref:
         assert torch.equal(acc[k], base[k] + ref[k]), k
+
+
+def test_unreached_pair_rows_are_never_read(P):
+    """The backward walk writes the rows of the pairs it reaches and marks them; rows of the
+    others keep whatever they held (here NaN) and must not reach the parameter gradients."""
+    wl = scenes.config(1, n=4000, seed=3)
+    print("[edge] unreached rows (NaN-filled pair buffer)", flush=True)
+    r, params = P.gpu_forward(wl)
+    rng = np.random.default_rng(2)
+    dL = torch.from_numpy(rng.standard_normal(3 * r.total_pixels).astype(np.float32) * 1e-3).cuda()
+    out = []
+    for fill in (0.0, float("nan")):
+        gp = torch.full((max(r.capacity, 1) * 9,), fill, dtype=torch.float32, device="cuda")
+        g = r.zero_grads(params)
+        r.blend_bwd(dL, gp)
+        r.project_bwd(params, gp, g, assign=True)
+        torch.cuda.synchronize()
+        out.append(g)
+    for k in out[0]:
+        assert torch.isfinite(out[1][k]).all(), k
+        assert torch.equal(out[0][k], out[1][k]), k
+    ref = r.zero_grads(params)
+    r.backward(params, dL, ref)
+    torch.cuda.synchronize()
+    for k in ref:
+        assert torch.equal(out[0][k], ref[k]), k
