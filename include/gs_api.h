@@ -259,6 +259,17 @@ int gs_project_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t V, cons
                    const gs_projected* proj, const gs_binning* bins, const float* grad_pair, gs_grads* grads,
                    void* ws, size_t ws_bytes, gs_stream_t stream);
 
+/* Gradient of the mean squared error over the V views of a rendered image
+ * (layout of gs_render_fwd's image), averaged over mean_views views:
+ *   L = (1 / mean_views) sum_v mean over 3 H_v W_v of (image - target)^2,
+ *   dL/dimage = 2 (image - target) / (3 H_v W_v mean_views).
+ * image, target, dL_dimage: device, [sum_v 3 H_v W_v] (dL_dimage WRITTEN; it may
+ * alias neither input).  Only the cameras' width and height are read;
+ * mean_views >= 1 (V for a plain mean; a per-view call of a V-view batch
+ * passes the batch's V).  One elementwise pass, no workspace.               */
+int gs_l2_grad(const float* image, const float* target, const gs_camera* cams, int32_t V, int32_t mean_views,
+               float* dL_dimage, gs_stream_t stream);
+
 /* Photometric loss of Eq. 7, its L1 and D-SSIM terms, over the V views of a
  * rendered image (layout of gs_render_fwd's image), and its gradient:
  *   L_v = (1 - lambda) mean|x - y| + lambda (1 - mean SSIM),  L = mean_v L_v

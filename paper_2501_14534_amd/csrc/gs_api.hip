@@ -554,6 +554,26 @@ int gs_loss_l1_dssim(const float* image, const float* target, const gs_camera* c
                               (hipStream_t)stream));
 }
 
+int gs_l2_grad(const float* image, const float* target, const gs_camera* cams, int32_t V, int32_t mean_views,
+               float* dL_dimage, gs_stream_t stream) {
+  if (!cams || V < 1 || V > GS_MAX_VIEWS || mean_views < 1 || !image || !target || !dL_dimage) return GS_E_INVALID;
+  if (dL_dimage == image || dL_dimage == target) return GS_E_INVALID;
+  L2Args a;
+  a.nviews = V;
+  int64_t end = 0;
+  for (int v = 0; v < V; ++v) {
+    if (cams[v].width <= 0 || cams[v].height <= 0) return GS_E_INVALID;
+    const int64_t k = 3 * (int64_t)cams[v].width * cams[v].height;
+    end += k;
+    a.end[v] = end;
+    a.scale[v] = (float)(2.0 / ((double)k * (double)mean_views));
+  }
+  if (end >= ((int64_t)1 << 31) * 256) return GS_E_INVALID;
+  const int d = device_ok();
+  if (d != GS_OK) return d;
+  return launched(launch_l2_grad(image, target, dL_dimage, a, (hipStream_t)stream));
+}
+
 int gs_blur_views(const float* in, float* out, const gs_camera* cams, int32_t V, int32_t ksize, float sigma,
                   gs_stream_t stream) {
   BlurArgs b;

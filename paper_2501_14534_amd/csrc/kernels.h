@@ -148,6 +148,14 @@ struct BlurArgs {
   float g[2 * kMaxBlurRadius + 1];
 };
 
+// Mean squared error gradient: per view the end of its elements and the scale.
+struct L2Args {
+  int64_t end[GS_MAX_VIEWS];  // exclusive end of view v's 3 H W elements
+  float scale[GS_MAX_VIEWS];  // 2 / (3 H W mean_views)
+  int32_t nviews;
+};
+hipError_t launch_l2_grad(const float* image, const float* target, float* dL, const L2Args& a, hipStream_t s);
+
 // Target resize: per view the input and output sizes and pixel offsets.
 struct ResizeView {
   int32_t W, H, Wo, Ho;

@@ -331,4 +331,22 @@ hipError_t launch_mask_loss(const float* m, const float* msh, int64_t n, int deg
   return hipGetLastError();
 }
 
+// One thread per element: dL = scale_v (image - target), v the element's view.
+__global__ __launch_bounds__(256) void l2_grad_kernel(const float* __restrict__ image,
+                                                      const float* __restrict__ target, float* __restrict__ dL,
+                                                      L2Args a) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.end[a.nviews - 1]) return;
+  int v = 0;
+  while (e >= a.end[v]) ++v;
+  dL[e] = a.scale[v] * (image[e] - target[e]);
+}
+
+hipError_t launch_l2_grad(const float* image, const float* target, float* dL, const L2Args& a, hipStream_t s) {
+  const int64_t total = a.nviews > 0 ? a.end[a.nviews - 1] : 0;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(l2_grad_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, image, target, dL, a);
+  return hipGetLastError();
+}
+
 }  // namespace gs

@@ -20,9 +20,9 @@ GRAD_FLOATS = 9
 MAX_BATCH = 1024
 
 EXPORTS = ("gs_view_sizes", "gs_workspace_size", "gs_project", "gs_bin_sort", "gs_render_fwd", "gs_render_bwd",
-           "gs_blend_bwd", "gs_project_bwd", "gs_loss_workspace_size", "gs_loss_l1_dssim", "gs_mask_loss_workspace_size", "gs_mask_loss",
-           "gs_count_hits", "gs_significance_workspace_size", "gs_significance", "gs_blur_views",
-           "gs_resize_views", "gs_strerror")
+           "gs_blend_bwd", "gs_project_bwd", "gs_loss_workspace_size", "gs_loss_l1_dssim", "gs_l2_grad",
+           "gs_mask_loss_workspace_size", "gs_mask_loss", "gs_count_hits", "gs_significance_workspace_size",
+           "gs_significance", "gs_blur_views", "gs_resize_views", "gs_strerror")
 
 vp = C.c_void_p
 
@@ -100,6 +100,8 @@ def load():
     L.gs_loss_workspace_size.restype = C.c_size_t
     L.gs_loss_l1_dssim.argtypes = [vp, vp, P(GsCamera), C.c_int32, C.c_float, vp, vp, vp, C.c_size_t, vp]
     L.gs_loss_l1_dssim.restype = C.c_int
+    L.gs_l2_grad.argtypes = [vp, vp, P(GsCamera), C.c_int32, C.c_int32, vp, vp]
+    L.gs_l2_grad.restype = C.c_int
     L.gs_mask_loss_workspace_size.argtypes = [C.c_int64]
     L.gs_mask_loss_workspace_size.restype = C.c_size_t
     L.gs_mask_loss.argtypes = [P(GsGaussians), C.c_float, C.c_float, vp, P(GsGrads), vp, C.c_size_t, vp]
@@ -207,6 +209,10 @@ def project_bwd(g, cams_arr, V, opts_s, proj, bins, grad_pair, grads, ws, ws_byt
 
 def loss_workspace_size(cams_arr, V) -> int:
     return int(load().gs_loss_workspace_size(cams_arr, V))
+
+
+def l2_grad(image, target, cams_arr, V, mean_views, dL_dimage, stream) -> int:
+    return load().gs_l2_grad(image, target, cams_arr, V, int(mean_views), dL_dimage, stream)
 
 
 def loss_l1_dssim(image, target, cams_arr, V, lambda_ssim, loss, dL_dimage, ws, ws_bytes, stream) -> int:

@@ -289,20 +289,14 @@ def rasterize(rast: Rasterizer, params: Dict[str, torch.Tensor]) -> torch.Tensor
     return RasterizeFn.apply(rast, names, *[params[k] for k in names])
 
 
-def l2_loss_grad(image: torch.Tensor, target: torch.Tensor, views: int, out: torch.Tensor,
-                 pixels_per_view: Sequence[int]) -> None:
-    """dL/dimage of L = mean over views of mean over 3HW of (image - target)^2, written into `out`."""
-    if len(set(pixels_per_view)) == 1:  # one scale for every view: two launches in all
-        k = 3 * pixels_per_view[0] * len(pixels_per_view)
-        torch.sub(image[:k], target[:k], out=out[:k])
-        out[:k].mul_(2.0 / (3 * pixels_per_view[0] * views))
-        return
-    off = 0
-    for p in pixels_per_view:
-        k = 3 * p
-        torch.sub(image[off:off + k], target[off:off + k], out=out[off:off + k])
-        out[off:off + k].mul_(2.0 / (k * views))
-        off += k
+def l2_loss_grad(rast: "Rasterizer", image: torch.Tensor, target: torch.Tensor, views: int,
+                 out: torch.Tensor) -> None:
+    """dL/dimage of L = mean over `views` views of mean over 3HW of (image - target)^2, written into
+    `out` by gs_l2_grad (one elementwise pass)."""
+    if target.numel() != image.numel() or out.numel() != image.numel():
+        raise ValueError("image, target and out must have the same size")
+    gs.check(gs.l2_grad(gs.ptr(image), gs.ptr(target), rast.cams_arr, rast.V, int(views), gs.ptr(out), _stream()),
+             "gs_l2_grad")
 
 
 class Step:
@@ -370,7 +364,7 @@ class Step:
         if self.ploss is not None:
             self.ploss(r.image, self.target, out=self.dL)
         else:
-            l2_loss_grad(r.image, self.target, self.loss_views, self.dL, self.pix)
+            l2_loss_grad(r, r.image, self.target, self.loss_views, self.dL)
         # the gradients are written, not added: only the ones this step does not write are
         # cleared (the SH-rest gradient on sparse steps; the SH gradients at degree 0)
         grads = self.grads

@@ -174,6 +174,12 @@ def test_loss_entry_points_validate_on_the_host(lib):
     assert f(4096, None, cams, V, C.c_float(0.2), 4096, 4096, 4096, need, None) == gs.GS_E_INVALID
     assert f(4096, 4096, cams, V, C.c_float(0.2), 4096, 4096, 4096, need - 1, None) == gs.GS_E_INVALID
     assert f(4096, 4096, cams, V, C.c_float(0.2), 4096, 4096, None, need, None) == gs.GS_E_INVALID
+    l2 = lib.gs_l2_grad
+    assert l2(None, 4096, cams, V, V, 8192, None) == gs.GS_E_INVALID
+    assert l2(4096, 4096, cams, V, 0, 8192, None) == gs.GS_E_INVALID  # mean over no views
+    assert l2(4096, 8192, cams, V, V, 4096, None) == gs.GS_E_INVALID  # output aliases the image
+    assert l2(4096, 8192, cams, 0, V, 12288, None) == gs.GS_E_INVALID
+    assert l2(4096, 8192, bad, 1, 1, 12288, None) == gs.GS_E_INVALID  # zero-width view
 
 
 def test_significance_entry_points_validate_on_the_host(lib):
