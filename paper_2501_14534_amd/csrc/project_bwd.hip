@@ -92,8 +92,10 @@ __device__ __forceinline__ float acc_mul_add(float t, float a, float b) {
 // records of consecutive Gaussians in one view: their pairs form one
 // contiguous run of the [K][9] array (emission order is record order), which
 // the wave copies into LDS window by window with 16-byte loads of consecutive
-// addresses; each lane then adds its own pairs from LDS.  (Loading its pairs
-// directly would touch a separate cache line per lane and load.)
+// addresses, with the pairs' live bytes; each lane then adds its own live
+// pairs from LDS (a pair the backward walk did not reach has no row this
+// step and counts as zero).  (Loading its pairs directly would touch a
+// separate cache line per lane and load.)
 constexpr int kSumWindow = 256;  // pairs per window (9 x 256 floats = 576 float4, 9 per lane)
 
 __device__ __forceinline__ void wave_lds_sync() {
