@@ -401,15 +401,50 @@ struct WalkResult {
   uint64_t hash;
 };
 
+// Near-threshold flags (the decision-consistency protocol; not part of the
+// function itself).  eps[0..5]: a decision is flagged when the compared
+// quantity lies within its window of the threshold, the window being the
+// rounding a single-precision evaluation of the same quantity can carry:
+//   alpha (skip, cap):  relative  eps[0] + eps[3] S, where S = |A| dx^2/2 +
+//                       |B dx dy| + |C| dy^2/2 bounds the exponent's terms;
+//   T (1 - alpha) (stop): relative eps[1] + e_T + the (1 - alpha) part, e_T
+//                       accumulating eps[4] + w_alpha alpha / (1 - alpha) per
+//                       composited Gaussian;
+//   square edge:        eps[2] + eps[5] |dx| pixels, but never when px - u
+//                       is exact in single precision (the test is then exact);
+//   radius (rec_flags bit 1, a record whose 3 sqrt(lambda) is near an
+//                       integer): the pixel is within one pixel of its square.
+// When the records themselves carry rounding (an independent run compared
+// with another precision's projection), rec_win[2 rec] is the record's
+// screen-position error in pixels, widening the square-edge window and the
+// alpha window by its effect on the exponent, and rec_win[2 rec + 1] its
+// conic's relative error, widening the alpha window by that fraction of S;
+// depth[rec] (with eps[6], a relative window) flags two consecutive records
+// that reach the pixel at depths within the window (their order may differ).
+// Flag bits per pixel: 1 square edge, 2 alpha skip, 4 termination, 8 alpha
+// cap, 16 near-integer radius, 32 near-equal depths.
+bool f32_exact(double x) { return (double)(float)x == x; }
+
+struct FlagInputs {
+  const double* eps;       // [7] or NULL: no flags
+  const uint8_t* rec;      // per record, bit 1: radius near an integer; or NULL
+  const double* rec_win;   // per record (position px, conic relative), or NULL
+  const double* depth;     // per record, or NULL
+};
+
 WalkResult walk_pixel(double px, double py, int64_t start, int64_t end, const uint32_t* ids, const double* uv,
                       const double* conic, const double* opacity, const double* rgb, const int32_t* radius,
-                      const double* eps, std::vector<Contrib>* list) {
+                      const FlagInputs& fi, std::vector<Contrib>* list) {
+  const double* eps = fi.eps;
+  const uint8_t* rec_flags = fi.rec;
   WalkResult r;
   r.C[0] = r.C[1] = r.C[2] = 0.0;
   r.T = 1.0;
   r.last = 0;
   r.flags = 0;
   r.hash = 1469598103934665603ull;
+  double eT = eps ? eps[1] : 0.0;  // relative window of the transmittance reached so far
+  double prev_depth = -1.0;        // depth of the last record that reached the pixel
   for (int64_t j = start; j < end; ++j) {
     const uint32_t rec = ids[j];
     const double dx = px - uv[2 * rec], dy = py - uv[2 * rec + 1];
@@ -420,18 +455,38 @@ WalkResult walk_pixel(double px, double py, int64_t start, int64_t end, const ui
     const double raw = opacity[rec] * G;
     const double alpha = std::min(kAlphaMax, raw);
     const bool inside = std::fabs(dx) <= rad && std::fabs(dy) <= rad;
+    double wa = 0.0, wq = 0.0;  // relative windows of alpha and of (1 - alpha)
     if (eps) {
-      const bool near_edge = std::fabs(std::fabs(dx) - rad) <= eps[2] || std::fabs(std::fabs(dy) - rad) <= eps[2];
-      if (near_edge && alpha >= kAlphaMin * (1.0 - eps[0])) r.flags |= 1;
+      const double S = 0.5 * std::fabs(A) * dx * dx + std::fabs(B * dx * dy) + 0.5 * std::fabs(Cc) * dy * dy;
+      const double ep = fi.rec_win ? fi.rec_win[2 * rec] : 0.0;
+      const double ec = fi.rec_win ? fi.rec_win[2 * rec + 1] : 0.0;
+      const double dq = ep * (std::fabs(A * dx + B * dy) + std::fabs(B * dx + Cc * dy)) + 0.5 * ep * ep * (std::fabs(A) + 2.0 * std::fabs(B) + std::fabs(Cc));
+      wa = eps[0] + eps[3] * S + ec * S + dq;
+      wa = wa < 0.5 ? wa : 0.5;
+      wq = alpha < 1.0 ? wa * alpha / (1.0 - alpha) : 0.0;
+      const bool reach = alpha >= kAlphaMin * (1.0 - wa);
+      const double edx = eps[2] + eps[5] * std::fabs(dx) + ep, edy = eps[2] + eps[5] * std::fabs(dy) + ep;
+      const bool ex = std::fabs(std::fabs(dx) - rad) <= edx && (ep > 0.0 || !f32_exact(dx));
+      const bool ey = std::fabs(std::fabs(dy) - rad) <= edy && (ep > 0.0 || !f32_exact(dy));
+      if ((ex || ey) && reach) r.flags |= 1;
+      if (rec_flags && (rec_flags[rec] & 1) && reach && std::fabs(dx) <= rad + 1.0 && std::fabs(dy) <= rad + 1.0 &&
+          (std::fabs(dx) >= rad - 1.0 || std::fabs(dy) >= rad - 1.0))
+        r.flags |= 16;
+      if (fi.depth && reach && std::fabs(dx) <= rad + ep + 1e-6 && std::fabs(dy) <= rad + ep + 1e-6) {
+        const double d = fi.depth[rec];
+        if (prev_depth >= 0.0 && std::fabs(d - prev_depth) <= eps[6] * d) r.flags |= 32;
+        prev_depth = d;
+      }
     }
     // Square test: the pixel centre must lie in the Gaussian's closed screen
     // square of half-side `radius` (keeps the result independent of tiling).
     if (!inside) continue;
-    if (eps && std::fabs(alpha - kAlphaMin) <= eps[0] * kAlphaMin) r.flags |= 2;
+    if (eps && std::fabs(alpha - kAlphaMin) <= wa * kAlphaMin) r.flags |= 2;
     if (alpha < kAlphaMin) continue;
     const double Tn = r.T * (1.0 - alpha);
-    if (eps && std::fabs(Tn - kTMin) <= eps[1] * kTMin) r.flags |= 4;
-    if (eps && std::fabs(raw - kAlphaMax) <= eps[0] * kAlphaMax) r.flags |= 8;
+    if (eps && std::fabs(Tn - kTMin) <= (eT + wq + eps[4]) * kTMin) r.flags |= 4;
+    if (eps && std::fabs(raw - kAlphaMax) <= wa * kAlphaMax) r.flags |= 8;
+    if (eps) eT += wq + eps[4];
     if (Tn < kTMin) {  // stop before compositing this Gaussian
       r.hash = (r.hash ^ (uint64_t)(j - start + 1) * 0x9E3779B97F4A7C15ull) * 1099511628211ull;
       break;
@@ -638,16 +693,20 @@ int64_t orc_bin(int32_t V, int64_t n, const OrcCamera* cams, const OrcOpts* o, c
 // by the ids of the sorted lists.  Outputs: image (per view [3][H][W] planar,
 // views concatenated), T_final and last_contrib (per view [H][W]; last_contrib
 // counts the list entries up to and including the last composited one).
-// Optional: eps[3] = relative alpha window, relative T window, pixel window
-// for flagging near-threshold decisions (flags per pixel: 1 square edge,
-// 2 alpha skip, 4 termination, 8 alpha cap), and a per-pixel hash of all
-// decisions taken.  tile_mask (per global tile, may be NULL) restricts the
-// work to the tiles marked 1; pixels of other tiles are left untouched.
+// Optional: eps[7] = the near-threshold windows of walk_pixel, with per-pixel
+// flags (1 square edge, 2 alpha skip, 4 termination, 8 alpha cap, 16 near a
+// record whose radius is near an integer, given by rec_flags bit 1 per
+// record, 32 near-equal depths; rec_flags, rec_win and depth may be NULL),
+// and a per-pixel hash of all decisions taken.  tile_mask (per global tile,
+// may be NULL) restricts the work to the tiles marked 1; pixels of other
+// tiles are left untouched.
 void orc_composite_fwd(int32_t V, int64_t n, const OrcCamera* cams, const OrcOpts* o, const double* uv,
                        const double* conic, const double* opacity, const double* rgb, const int32_t* radius,
                        const uint32_t* ids, const uint32_t* ranges, double* image, double* T_final,
                        int32_t* last_contrib, const double* eps, uint8_t* flags, uint64_t* hash,
-                       const uint8_t* tile_mask) {
+                       const uint8_t* tile_mask, const uint8_t* rec_flags, const double* rec_win,
+                       const double* depth) {
+  const FlagInputs fi{eps, rec_flags, rec_win, depth};
   (void)n;
   int64_t total_tiles = 0;
   std::vector<ViewGeom> vt = view_table(V, cams, *o, &total_tiles, nullptr);
@@ -665,7 +724,8 @@ void orc_composite_fwd(int32_t V, int64_t n, const OrcCamera* cams, const OrcOpt
     const int64_t plane = (int64_t)g.W * g.H;
     for (int yy = ty * o->tile_h; yy < std::min(g.H, (ty + 1) * o->tile_h); ++yy)
       for (int xx = tx * o->tile_w; xx < std::min(g.W, (tx + 1) * o->tile_w); ++xx) {
-        WalkResult r = walk_pixel(xx + 0.5, yy + 0.5, start, end, ids, uv, conic, opacity, rgb, radius, eps, nullptr);
+        WalkResult r =
+            walk_pixel(xx + 0.5, yy + 0.5, start, end, ids, uv, conic, opacity, rgb, radius, fi, nullptr);
         const int64_t p = (int64_t)yy * g.W + xx;
         for (int ch = 0; ch < 3; ++ch) image[3 * g.pix_off + ch * plane + p] = r.C[ch] + r.T * o->bg[ch];
         T_final[g.pix_off + p] = r.T;
@@ -705,7 +765,8 @@ void orc_hits(int32_t V, int64_t n, const OrcCamera* cams, const OrcOpts* o, con
     for (int yy = ty * o->tile_h; yy < std::min(g.H, (ty + 1) * o->tile_h); ++yy)
       for (int xx = tx * o->tile_w; xx < std::min(g.W, (tx + 1) * o->tile_w); ++xx) {
         list.clear();
-        WalkResult r = walk_pixel(xx + 0.5, yy + 0.5, start, end, ids, uv, conic, opacity, rgb, radius, eps, &list);
+        WalkResult r =
+            walk_pixel(xx + 0.5, yy + 0.5, start, end, ids, uv, conic, opacity, rgb, radius, FlagInputs{eps, nullptr, nullptr, nullptr}, &list);
         if (r.flags && uncertain) {
           // a near-threshold pixel: a walk in other arithmetic may count any record of the tile
           for (int64_t k = start; k < end; ++k) {
@@ -755,7 +816,8 @@ void orc_composite_bwd(int32_t V, int64_t n, const OrcCamera* cams, const OrcOpt
     for (int yy = ty * o->tile_h; yy < std::min(g.H, (ty + 1) * o->tile_h); ++yy)
       for (int xx = tx * o->tile_w; xx < std::min(g.W, (tx + 1) * o->tile_w); ++xx) {
         list.clear();
-        WalkResult r = walk_pixel(xx + 0.5, yy + 0.5, start, end, ids, uv, conic, opacity, rgb, radius, nullptr, &list);
+        WalkResult r =
+            walk_pixel(xx + 0.5, yy + 0.5, start, end, ids, uv, conic, opacity, rgb, radius, FlagInputs{}, &list);
         const int64_t p = (int64_t)yy * g.W + xx;
         double dLdC[3], R[3];
         for (int ch = 0; ch < 3; ++ch) {

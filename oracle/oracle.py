@@ -83,7 +83,7 @@ def lib():
         L.orc_bin.argtypes = [C.c_int32, C.c_int64, C.POINTER(OrcCamera), C.POINTER(OrcOpts), F, F, F, I32, I32,
                               U32, U64, U32, C.c_int64, U32]
         L.orc_composite_fwd.argtypes = [C.c_int32, C.c_int64, C.POINTER(OrcCamera), C.POINTER(OrcOpts), D, D, D, D,
-                                        I32, U32, U32, D, D, I32, D, U8, U64, U8]
+                                        I32, U32, U32, D, D, I32, D, U8, U64, U8, U8, D, D]
         L.orc_composite_bwd.argtypes = [C.c_int32, C.c_int64, C.POINTER(OrcCamera), C.POINTER(OrcOpts), D, D, D, D,
                                         I32, U32, U32, D, D, U8]
         L.orc_project_bwd.argtypes = [C.POINTER(OrcGaussians), C.POINTER(OrcCamera), C.POINTER(OrcOpts), D,
@@ -237,10 +237,28 @@ def _mask(tile_mask):
     return None if tile_mask is None else np.ascontiguousarray(tile_mask, np.uint8)
 
 
-def composite_fwd(cams, opts, n, splats, ids, ranges, eps=None, tile_mask=None) -> dict:
+def _eps(eps):
+    """The seven near-threshold windows of the walk (missing trailing entries are 0):
+    alpha relative (fixed part), T relative (fixed part), square edge in pixels
+    (fixed part), alpha relative per unit of the exponent's terms, T relative per
+    composited Gaussian, square edge relative to |dx|, depth relative (order of
+    consecutive records reaching a pixel)."""
+    if eps is None:
+        return None
+    e = np.zeros(7, np.float64)
+    a = np.asarray(eps, np.float64).reshape(-1)
+    e[:a.size] = a
+    return e
+
+
+def composite_fwd(cams, opts, n, splats, ids, ranges, eps=None, tile_mask=None, rec_flags=None, rec_win=None,
+                  depth=None) -> dict:
     """Eq. 2 per pixel.  Returns flat image (views concatenated, each [3,H,W]),
     T_final, last_contrib, and (if eps given) near-threshold flags + decision hashes.
-    tile_mask (uint8 per global tile) restricts the work to the marked tiles."""
+    tile_mask (uint8 per global tile) restricts the work to the marked tiles;
+    rec_flags (uint8 per record, bit 1: radius near an integer) adds flag 16;
+    rec_win ([records, 2]: screen-position error in pixels, conic relative error)
+    widens the windows; depth (per record) with eps[6] adds flag 32."""
     V = len(cams)
     P = sum(c.width * c.height for c in cams)
     uv, conic, op, rgb, rad = _splat_args(splats)
@@ -253,13 +271,16 @@ def composite_fwd(cams, opts, n, splats, ids, ranges, eps=None, tile_mask=None) 
     last = np.zeros(P, np.int32)
     flags = np.zeros(P, np.uint8)
     hsh = np.zeros(P, np.uint64)
-    e = None if eps is None else np.asarray(eps, np.float64)
+    e = _eps(eps)
     tm = _mask(tile_mask)
+    rf = None if rec_flags is None else np.ascontiguousarray(rec_flags, np.uint8)
+    rw = None if rec_win is None else np.ascontiguousarray(rec_win, np.float64).reshape(-1)
+    dp = None if depth is None else np.ascontiguousarray(depth, np.float64).reshape(-1)
     cs, o = _cams(cams), opts_struct(opts)
     lib().orc_composite_fwd(V, n, cs, C.byref(o), _p(uv, D), _p(conic, D), _p(op, D), _p(rgb, D), _p(rad, I32),
                             _p(ids, U32), _p(ranges, U32), _p(img, D), _p(T, D), _p(last, I32), _p(e, D),
                             _p(flags, U8) if e is not None else None,
-                            _p(hsh, U64) if e is not None else None, _p(tm, U8))
+                            _p(hsh, U64) if e is not None else None, _p(tm, U8), _p(rf, U8), _p(rw, D), _p(dp, D))
     return dict(image=img, T_final=T, last_contrib=last, flags=flags, hash=hsh)
 
 
@@ -274,7 +295,7 @@ def hits(cams, opts, n, splats, ids, ranges, eps=None) -> dict:
     ranges = np.ascontiguousarray(ranges, np.uint32)
     h = np.zeros(V * n, np.uint32)
     u = np.zeros(V * n, np.uint32)
-    e = None if eps is None else np.asarray(eps, np.float64)
+    e = _eps(eps)
     cs, o = _cams(cams), opts_struct(opts)
     lib().orc_hits(V, n, cs, C.byref(o), _p(uv, D), _p(conic, D), _p(op, D), _p(rgb, D), _p(rad, I32), _p(ids, U32),
                    _p(ranges, U32), _p(e, D), _p(h, U32), _p(u, U32) if e is not None else None)

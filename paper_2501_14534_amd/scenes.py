@@ -271,15 +271,21 @@ def config(k: int, n: Optional[int] = None, seed: Optional[int] = None) -> Workl
 
 def tiny(n=48, seed=0, deg=3, width=40, height=32, masks=False, band_masks=False, f=None,
          log_scale=(-2.6, 0.35), opacity=(0.5, 1.2), depth=(3.0, 5.0), spread=0.9,
-         unit_quats=False, mask_eps=0.5, sh_mask_eps=0.5) -> Workload:
+         unit_quats=False, mask_eps=0.5, sh_mask_eps=0.5, depth_levels: Optional[int] = None) -> Workload:
     """A small scene in front of one camera, for brute-force and FD tests.
 
     The camera sits at the origin looking down +y (world up +z); Gaussians lie
-    in a frustum-shaped slab at depths `depth`.
+    in a frustum-shaped slab at depths `depth`.  With `depth_levels` the depths
+    are drawn from that many evenly spaced values instead (the camera's depth
+    axis is world y exactly, so Gaussians of one level share the same float
+    depth: ties in the (tile, depth) order are common).
     """
     rng = np.random.default_rng(seed)
     f = float(width) if f is None else f
-    z = rng.uniform(depth[0], depth[1], n)
+    if depth_levels:
+        z = rng.choice(np.linspace(depth[0], depth[1], depth_levels).astype(F32).astype(np.float64), n)
+    else:
+        z = rng.uniform(depth[0], depth[1], n)
     x = rng.uniform(-spread, spread, n) * z * (width / 2.0) / f
     y = rng.uniform(-spread, spread, n) * z * (height / 2.0) / f
     # camera looks along +y with up +z: camera x = world x, camera y = -world z

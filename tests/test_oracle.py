@@ -215,6 +215,189 @@ def test_rotation_about_optical_axis_rotates_screen_covariance(orc):
         np.testing.assert_allclose(np.linalg.eigvalsh(S), np.linalg.eigvalsh(S0), rtol=1e-6)
 
 
+def _clamp_cam():
+    # camera at the origin looking along world +y: camera x = world x, camera y = -world z,
+    # camera z = world y (the rotation's entries are exactly 0 and +-1)
+    return scenes.make_camera((0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 40, 30, 50.0)
+
+
+@pytest.mark.parametrize("rx,ry", [(0.3, -0.2), (1.5, 0.0), (-1.5, 0.0), (0.0, 0.9), (0.0, -0.9), (2.0, -1.2)])
+def test_jacobian_guard_closed_form(orc, rx, ry):
+    """EWA with the lateral-ratio guard (reading R4 of Eq. 1's Jacobian): an isotropic Gaussian of
+    world std sigma at camera position (rx z, ry z, z) has J J^T sigma^2 = (f/z)^2 sigma^2
+    [[1 + rx'^2, rx' ry'], [rx' ry', 1 + ry'^2]] with rx' = clamp(rx, +-tan_clamp W/(2 f)) and
+    ry' = clamp(ry, +-tan_clamp H/(2 f)); the cases put the ratios inside and beyond the limits on
+    both sides of both axes."""
+    cam = _clamp_cam()
+    f, z, sig, tc = float(cam.fx), 3.0, 0.2, 1.3
+    limx, limy = tc * cam.width / (2 * f), tc * cam.height / (2 * f)   # 0.52, 0.39
+    sc = _single([rx * z, z, -ry * z], [math.log(sig)] * 3, [1, 0, 0, 0], 0.0, [0.5] * 3)
+    lp = 0.3
+    pr = orc.project(sc, cam, _opts(lowpass=lp, tan_clamp=tc))
+    assert pr["valid"][0] == 1
+    sig64 = math.exp(float(np.float32(math.log(sig))))  # exp of the stored float log-scale
+    mu = sc.means.astype(np.float64)[:, 0]
+    x, y, zz = mu[0], -mu[2], mu[1]                # camera coordinates
+    rxc, ryc = np.clip(x / zz, -limx, limx), np.clip(y / zz, -limy, limy)
+    k = (f / zz) ** 2 * sig64 ** 2
+    exp = [k * (1 + rxc ** 2) + lp, k * rxc * ryc, k * (1 + ryc ** 2) + lp]
+    np.testing.assert_allclose(pr["cov2d"][0], exp, rtol=1e-10, atol=1e-14)
+    # the screen position uses the unclamped ratios
+    np.testing.assert_allclose(pr["uv"][0], [f * x / zz + cam.cx, f * y / zz + cam.cy], rtol=1e-12)
+    if abs(rx) > limx or abs(ry) > limy:
+        # an unguarded Jacobian would give a different, larger covariance
+        unguarded = [k * (1 + (x / zz) ** 2) + lp, k * (x / zz) * (y / zz), k * (1 + (y / zz) ** 2) + lp]
+        assert not np.allclose(pr["cov2d"][0], unguarded, rtol=1e-6)
+
+
+def test_jacobian_guard_is_the_perspective_derivative_at_the_clamped_point(orc):
+    """Off-axis, rotated, anisotropic Gaussians beyond the guard: Sigma' = J~ Sigma J~^T + sI where
+    J~ is the derivative (central differences) of the world -> pixel map at the point whose camera
+    coordinates are (z rx', z ry', z), the mean moved laterally onto the clamp limit."""
+    cam = _clamp_cam()
+    R = cam.R.astype(np.float64)
+    t = cam.t.astype(np.float64)
+    limx = 1.3 * cam.width / (2 * float(cam.fx))
+    limy = 1.3 * cam.height / (2 * float(cam.fy))
+
+    def pix(xw):
+        c = R @ xw + t
+        return np.array([cam.fx * c[0] / c[2] + cam.cx, cam.fy * c[1] / c[2] + cam.cy])
+
+    rng = np.random.default_rng(17)
+    checked = 0
+    for rx, ry in ((0.9, 0.1), (-1.1, 0.2), (0.2, 0.7), (-0.1, -1.4), (1.6, 0.8)):
+        z = rng.uniform(2.0, 5.0)
+        mu = np.array([rx * z, z, -ry * z], np.float32)
+        q = rng.standard_normal(4).astype(np.float32)
+        ls = rng.uniform(-3, -1.5, 3).astype(np.float32)
+        sc = _single(mu, ls, q, 0.0, [0.5] * 3)
+        pr = orc.project(sc, cam, scenes.Opts())
+        assert pr["valid"][0]
+        cc = R @ mu.astype(np.float64) + t
+        moved_cam = np.array([cc[2] * np.clip(cc[0] / cc[2], -limx, limx),
+                              cc[2] * np.clip(cc[1] / cc[2], -limy, limy), cc[2]])
+        moved = R.T @ (moved_cam - t)
+        h = 1e-6
+        J = np.stack([(pix(moved + h * e) - pix(moved - h * e)) / (2 * h) for e in np.eye(3)], 1)
+        iu = orc.cov3d(sc)[0]
+        Sig = np.array([[iu[0], iu[1], iu[2]], [iu[1], iu[3], iu[4]], [iu[2], iu[4], iu[5]]])
+        S2 = J @ Sig @ J.T + 0.3 * np.eye(2)
+        np.testing.assert_allclose(pr["cov2d"][0], [S2[0, 0], S2[0, 1], S2[1, 1]], rtol=1e-6)
+        checked += 1
+    assert checked == 5
+
+
+def test_jacobian_guard_derivatives(orc):
+    """Beyond the guard the covariance no longer depends on the clamped lateral coordinate but
+    still on depth (the derivative of the implemented function, R17): central differences of the
+    oracle's projected covariance in camera x and z, against the closed form
+    d/dz [(f/z)^2 sigma^2 (1 + rx'^2)] = -2 (f/z)^2 sigma^2 (1 + rx'^2) / z."""
+    cam = _clamp_cam()
+    f, z, sig = float(cam.fx), 3.0, 0.2
+    limx = 1.3 * cam.width / (2 * f)
+
+    def cov(xc, zc):
+        sc = _single([xc, zc, 0.0], [math.log(sig)] * 3, [1, 0, 0, 0], 0.0, [0.5] * 3)
+        sc.means = sc.means.astype(np.float64)
+        sc.means[:, 0] = [xc, zc, 0.0]
+        return orc.project(sc, cam, _opts(lowpass=0.0))["cov2d"][0]
+
+    s2 = math.exp(2 * float(np.float32(math.log(sig))))
+    h = 1e-5
+    for x in (1.2 * z, -1.2 * z):     # beyond the guard on both sides
+        dx = (cov(x + h, z) - cov(x - h, z)) / (2 * h)
+        np.testing.assert_allclose(dx, 0.0, atol=1e-9)
+        dz = (cov(x, z + h) - cov(x, z - h)) / (2 * h)
+        np.testing.assert_allclose(dz[0], -2 * (f / z) ** 2 * s2 * (1 + limx ** 2) / z, rtol=1e-6)
+    x = 0.3 * z                        # inside: the lateral coordinate enters through rx
+    dx = (cov(x + h, z) - cov(x - h, z)) / (2 * h)
+    np.testing.assert_allclose(dx[0], 2 * (f / z) ** 2 * s2 * x / z ** 2, rtol=1e-6)
+
+
+def test_oracle_gradients_match_finite_differences_beyond_the_guard(orc):
+    """Gradients of a scene whose Gaussians sit beyond the Jacobian guard but still reach the
+    screen (large, near the edges): the oracle's analytic derivative of the composited image
+    against central differences of its own forward, which the closed forms above pin."""
+    cam = scenes.make_camera((0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 40, 30, 40.0)
+    rng = np.random.default_rng(41)
+    n = 12
+    z = rng.uniform(2.0, 3.0, n)
+    side = rng.choice([-1.0, 1.0], n)
+    axis = rng.integers(0, 2, n)
+    # ratio beyond the guard (0.65 in x, 0.49 in y) by up to 40 %
+    r = rng.uniform(1.05, 1.4, n)
+    rx = np.where(axis == 0, side * 0.65 * r, rng.uniform(-0.3, 0.3, n))
+    ry = np.where(axis == 1, side * 0.49 * r, rng.uniform(-0.2, 0.2, n))
+    means = np.stack([rx * z, z, -ry * z]).astype(np.float32)
+    sc = scenes.Scene(means=means, log_scales=rng.uniform(-1.6, -1.2, (3, n)).astype(np.float32),
+                      quats=rng.standard_normal((4, n)).astype(np.float32),
+                      opacity_logits=rng.normal(0.0, 0.5, n).astype(np.float32),
+                      sh_dc=rng.normal(0.5, 0.2, (3, n)).astype(np.float32), sh_rest=None, mask_logits=None,
+                      sh_mask_logits=None, sh_degree=0)
+    pr = orc.project(sc, cam, scenes.Opts())
+    lim = np.where(axis == 0, 0.65, 0.49)
+    assert pr["valid"].all() and np.all(np.abs(np.where(axis == 0, rx, ry)) > lim)
+    wl = scenes.Workload("beyond_guard", sc, [cam], scenes.Opts(), [np.zeros((3, 30, 40), np.float32)])
+    img = orc.render(sc, [cam], scenes.Opts())["images"][0]
+    assert np.abs(img).sum() > 1.0  # the guarded Gaussians do reach the screen
+    w = _loss_weights(wl, 9)
+    n_ok = _fd_check(orc, wl, w, ["means", "log_scales", "quats"], 8, 1)
+    assert n_ok >= 12
+
+
+def test_equal_depth_ties_are_ordered_by_index(orc):
+    """Reading R2: Gaussians at bit-equal depth composite in index order.  Three coincident
+    Gaussians on the axis pixel, all at depth 2 (same float bits), with distinct primary colours,
+    so every other order gives another colour; at the axis pixel G = 1, so the colour is the
+    closed form c_0 a_0 + c_1 a_1 (1 - a_0) + c_2 a_2 (1 - a_0)(1 - a_1)."""
+    cam = _axis_cam()
+    ops = [0.6, 0.5, 0.7]
+    cols = [[1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]]
+    sc = _concat([_single([0.0, 2.0, 0.0], [math.log(0.05)] * 3, [1, 0, 0, 0], _logit(ops[i]), cols[i])
+                  for i in range(3)])
+    o = orc.render(sc, [cam], scenes.Opts())
+    a = [1 / (1 + math.exp(-float(np.float32(_logit(p))))) for p in ops]
+    exp = (np.array(cols[0]) * a[0] + np.array(cols[1]) * a[1] * (1 - a[0])
+           + np.array(cols[2]) * a[2] * (1 - a[0]) * (1 - a[1]))
+    np.testing.assert_allclose(o["images"][0][:, 16, 16], exp, rtol=1e-12)
+    # the binning holds the equal keys in index order
+    pr = orc.project(sc, cam, scenes.Opts())
+    b = orc.bin([cam], scenes.Opts(), sc.n, pr["uv"][:, 0].astype(np.float32), pr["uv"][:, 1].astype(np.float32),
+                pr["depth"].astype(np.float32), pr["radius"], pr["valid"])
+    keys = b["keys"]
+    same = keys[1:] == keys[:-1]
+    assert same.sum() >= 2
+    assert np.all(b["ids"][1:][same] > b["ids"][:-1][same])
+
+
+def test_equal_depth_ties_match_brute_force(orc):
+    """Many Gaussians sharing a few exact depths (world y on a coarse grid, axis camera): the tiled
+    oracle's image equals the per-pixel brute-force renderer's, whose order is (depth, index)."""
+    rng = np.random.default_rng(43)
+    n = 80
+    means = np.stack([rng.uniform(-0.6, 0.6, n), rng.choice([2.0, 2.25, 2.5], n), rng.uniform(-0.6, 0.6, n)])
+    sc = scenes.Scene(means=means.astype(np.float32), log_scales=rng.normal(-2.6, 0.3, (3, n)).astype(np.float32),
+                      quats=rng.standard_normal((4, n)).astype(np.float32),
+                      opacity_logits=rng.normal(1.0, 1.0, n).astype(np.float32),
+                      sh_dc=rng.uniform(0.0, 1.0, (3, n)).astype(np.float32), sh_rest=None, mask_logits=None,
+                      sh_mask_logits=None, sh_degree=0)
+    cam = _axis_cam(37, 29, 30.0)
+    opts = scenes.Opts()
+    pr = orc.project(sc, cam, opts)
+    b = orc.bin([cam], opts, sc.n, pr["uv"][:, 0].astype(np.float32), pr["uv"][:, 1].astype(np.float32),
+                pr["depth"].astype(np.float32), pr["radius"], pr["valid"])
+    same = b["keys"][1:] == b["keys"][:-1]
+    assert same.sum() > 50  # ties are common, not incidental
+    o = orc.render(sc, [cam], opts)
+    bf = brute.render(sc, [cam], opts, grad=False)
+    np.testing.assert_allclose(o["images"][0], bf["images"][0], atol=1e-12)
+    # reversing the index order of the tied Gaussians changes the image: the pin is not vacuous
+    rev = sc.subset(np.arange(n)[::-1].copy())
+    o_rev = orc.render(rev, [cam], opts)["images"][0]
+    assert np.abs(o_rev - o["images"][0]).max() > 1e-3
+
+
 def test_near_plane_and_invalid_inputs_are_culled(orc):
     cam = scenes.make_camera((0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 32, 32, 32.0)
     good = _single([0, 2, 0], [-3] * 3, [1, 0, 0, 0], 0.0, [0.5] * 3)
