@@ -81,6 +81,9 @@ class Rasterizer:
         self.T_final = torch.zeros(self.total_pixels, dtype=torch.float32, device=dev)
         self.last = torch.zeros(self.total_pixels, dtype=torch.int32, device=dev)
         self.proj = gs.GsProjected(gs.ptr(self.splats), gs.ptr(self.tiles_touched))
+        # bumped by every projection: the records, lists and pixel states a backward
+        # reads belong to the forward of this generation only
+        self.generation = 0
         self.capacity = 0
         self.set_capacity(capacity if capacity is not None else max(1 << 16, 8 * nrec))
 
@@ -110,6 +113,7 @@ class Rasterizer:
     # -- calls -----------------------------------------------------------------------------------
     def project(self, params) -> None:
         g = self.gaussians(params)
+        self.generation += 1
         gs.check(gs.project(g, self.cams_arr, self.V, self.opts_s, self.proj, _stream()), "gs_project")
 
     def bin_sort(self) -> None:
@@ -262,25 +266,34 @@ def significance_scores(params: Dict[str, torch.Tensor], sh_degree: int, cams: S
 class RasterizeFn(torch.autograd.Function):
     """image = rasterize(params); backward through gs_render_bwd.
 
-    The Rasterizer keeps the forward state (records, lists, T_final,
-    last_contrib) until its next forward, so one forward may be in flight
-    per Rasterizer."""
+    The Rasterizer keeps one forward's state (records, lists, T_final,
+    last_contrib, pixel states) until its next projection.  The backward of an
+    image whose Rasterizer has projected again since raises instead of
+    returning another forward's gradients: use one Rasterizer per forward in
+    flight.  Gradients are written (assign mode) into fresh tensors."""
 
     @staticmethod
     def forward(ctx, rast: Rasterizer, names, *tensors):
         params = dict(zip(names, tensors))
         img = rast.forward(params).clone()
         ctx.rast = rast
+        ctx.generation = rast.generation
         ctx.names = names
         ctx.save_for_backward(*tensors)
         return img
 
     @staticmethod
     def backward(ctx, dL):
+        rast = ctx.rast
+        if rast.generation != ctx.generation:
+            raise RuntimeError("rasterize: the Rasterizer has run another forward since this image was rendered, "
+                               "so this image's backward state is gone; use one Rasterizer per forward in flight")
         tensors = ctx.saved_tensors
         params = dict(zip(ctx.names, tensors))
-        grads = {k: torch.zeros_like(v) for k, v in params.items()}
-        ctx.rast.backward(params, dL.contiguous(), grads)
+        # every gradient the call computes is written; at SH degree 0 the band masks get none
+        grads = {k: (torch.zeros_like(v) if rast.deg == 0 and k == "sh_mask_logits" else torch.empty_like(v))
+                 for k, v in params.items()}
+        rast.render_bwd(params, dL.contiguous(), grads, assign=True)
         return (None, None, *[grads[k] for k in ctx.names])
 
 
@@ -344,6 +357,7 @@ class Step:
             self.mask_ws = torch.zeros(max(b, 1), dtype=torch.uint8, device=rast.device)
         self.sh_rest_every = max(1, int(sh_rest_every))
         self.step_index = 0
+        self.carries_sh_rest = True
 
     @property
     def graph(self):
@@ -392,10 +406,17 @@ class Step:
             self._body(with_sh_rest)
         self.graphs[with_sh_rest] = g
 
-    def launch(self):
-        """Enqueue one step (no host synchronisation)."""
-        with_sh_rest = self.step_index % self.sh_rest_every == 0
-        self.step_index += 1
+    def launch(self, with_sh_rest: Optional[bool] = None):
+        """Enqueue one step (no host synchronisation).  with_sh_rest None: the schedule decides
+        (every sh_rest_every-th step carries the SH-rest gradient) and the step counts;
+        True/False repeats a step of that kind without counting it (a retry).  Afterwards
+        `carries_sh_rest` says whether this step wrote the SH-rest gradient: on the other
+        steps the caller leaves that parameter group out of its optimiser update (the
+        gradient array then holds zeros, which would still move an Adam state)."""
+        if with_sh_rest is None:
+            with_sh_rest = self.step_index % self.sh_rest_every == 0
+            self.step_index += 1
+        self.carries_sh_rest = bool(with_sh_rest)
         if self.graph_enabled:
             if with_sh_rest not in self.graphs:
                 self.capture(with_sh_rest)
@@ -412,5 +433,5 @@ class Step:
         if self.rast.overflowed() or self.rast.capacity > 2 * headroom * need + (1 << 20):
             self.rast.set_capacity(int(need * headroom) + 1024)
             self.graph = None
-            self.launch()
+            self.launch(self.carries_sh_rest)  # the same step again: the schedule does not advance
             assert not self.rast.overflowed()

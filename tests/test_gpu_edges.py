@@ -234,22 +234,58 @@ def test_graph_replay_matches_eager(P):
         del junk
 
 
-def test_autograd_function_matches_direct_backward(P):
+@pytest.mark.parametrize("case", ["tiny_masked", "cfg4_small"])
+def test_autograd_function_matches_oracle(P, case):
+    """rasterize() through torch.autograd: the leaves' gradients (the straight-through
+    mask-logit gradients of Eq. 3 and Eq. 5 included) against the oracle's composite
+    backward and FP64 projection backward on the same records and lists, every element
+    within the gradient tolerance; near-threshold pixels get zero loss weight."""
+    from oracle import oracle as O
     from paper_2501_14534_amd import raster
-    wl = scenes.tiny(n=150, seed=4, deg=3, masks=True, band_masks=True, width=48, height=40)
-    print("[edge] autograd", flush=True)
+    if case == "tiny_masked":
+        wl = scenes.tiny(n=150, seed=4, deg=3, masks=True, band_masks=True, width=48, height=40)
+    else:
+        wl = scenes.scaled(4, n=20000, shrink=4)
+    print(f"[edge] autograd vs oracle: {case}", flush=True)
     r = P.make_rasterizer(wl)
     params = raster.to_device(wl.scene)
     leaves = {k: v.clone().requires_grad_(True) for k, v in params.items()}
     img = raster.rasterize(r, leaves)
-    w = torch.randn_like(img)
-    (img * w).sum().backward()
-    r2, _ = P.gpu_forward(wl, params=params)
-    g = r2.zero_grads(params)
-    r2.backward(params, w.contiguous(), g)
     torch.cuda.synchronize()
-    for k in g:
-        assert _rel_close(leaves[k].grad, g[k], 1e-5), k
+    fwd = P.check_forward(wl, wl.opts, r)
+    rng = np.random.default_rng(9)
+    w = (rng.standard_normal(img.numel()) / np.sqrt(img.numel())).astype(np.float32)
+    w[P._per_channel(fwd["flagged"], wl.cams)] = 0.0
+    (img * torch.from_numpy(w).cuda()).sum().backward()
+    torch.cuda.synchronize()
+    sp = P.records(r)
+    gl = P.gpu_lists(r)
+    n = wl.scene.n
+    grad_rec = O.composite_bwd(wl.cams, wl.opts, n, sp, gl["ids"], gl["ranges"], w.astype(np.float64))
+    og, absparts = P.oracle_param_grads(wl, wl.opts, grad_rec)
+    assert "mask_logits" in og and "sh_mask_logits" in og
+    res = {k: P.r24_violations(leaves[k].grad.cpu().numpy(), ref, absparts=absparts[k]) for k, ref in og.items()}
+    print(" ", res)
+    for k, (nb, worst) in res.items():
+        assert nb == 0, (k, nb, worst)
+        assert np.any(og[k] != 0), k
+
+
+def test_autograd_second_forward_before_backward_raises(P):
+    """Two forwards through one Rasterizer, then the first image's backward: an error, not
+    the second forward's gradients.  The second image's backward still works."""
+    from paper_2501_14534_amd import raster
+    wl = scenes.tiny(n=80, seed=5, deg=1, width=32, height=32)
+    r = P.make_rasterizer(wl)
+    params = raster.to_device(wl.scene)
+    l1 = {k: v.clone().requires_grad_(True) for k, v in params.items()}
+    l2 = {k: v.clone().requires_grad_(True) for k, v in params.items()}
+    img1 = raster.rasterize(r, l1)
+    img2 = raster.rasterize(r, l2)
+    with pytest.raises(RuntimeError, match="another forward"):
+        img1.sum().backward()
+    img2.sum().backward()
+    assert all(torch.isfinite(l2[k].grad).all() for k in l2)
 
 
 def test_mask_metamorphic_identities(P):
@@ -288,28 +324,29 @@ def test_gaussian_order_does_not_matter(P):
     assert torch.equal(a.image, b.image)
 
 
-@pytest.mark.parametrize("cfg", [2, 3, 4])
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("cfg", [2, 3, 4, 5])
 def test_full_size_sampled_parity(P, cfg):
     """Full-size workload in the benchmark's launch configuration; binning bit-exact in full,
-    compositing and gradients on a random sample of tiles."""
+    compositing (with the excluded and flagged fractions of the sampled pixels bounded) and
+    gradients on a sample of tiles: the 24 longest lists and 40 random tiles."""
     from oracle import oracle as O
     from paper_2501_14534_amd import autotune
     wl = scenes.config(cfg)
     opts = autotune.best_opts(wl)
     print(f"[full] config {cfg}: n={wl.scene.n} views={len(wl.cams)} tile {opts.tile_w}x{opts.tile_h} "
-          f"batch {opts.batch_depth} ppt {opts.pixels_per_thread}", flush=True)
+          f"batch {opts.batch_depth} ppt {opts.pixels_per_thread} bwd_chunk {opts.bwd_chunk}", flush=True)
     r, params = P.gpu_forward(wl, opts)
     gl = P.check_binning(wl, opts, r)
+    print(f"  binning bit-exact: K={gl['K']}", flush=True)
     rng = np.random.default_rng(cfg)
     T = r.total_tiles
-    # the 24 longest lists (several backward chunks each) and 40 random tiles
     lens = np.diff(gl["ranges"].astype(np.int64), axis=1).reshape(-1)
     deep = np.argsort(-lens, kind="stable")[:min(T, 24)]
     sample = np.union1d(deep, rng.choice(T, size=min(T, 40), replace=False))
     mask = np.zeros(T, np.uint8)
     mask[sample] = 1
-    sp = P.records(r)
-    fw = O.composite_fwd(wl.cams, opts, wl.scene.n, sp, gl["ids"], gl["ranges"], eps=P.FLAG_EPS, tile_mask=mask)
+    print(f"  sampled tiles {sample.size}, deepest list {int(lens.max())}", flush=True)
     # pixels of the sampled tiles
     pix_mask = np.zeros(r.total_pixels, bool)
     off = 0
@@ -320,27 +357,22 @@ def test_full_size_sampled_parity(P, cfg):
         gt = t0 + (ys // opts.tile_h) * TX + xs // opts.tile_w
         pix_mask[off:off + c.pixels] = mask[gt.reshape(-1)] == 1
         off += c.pixels
-    ok = pix_mask & (fw["flags"] == 0)
-    img = r.image.cpu().numpy().reshape(-1)
-    ok3 = np.concatenate([np.tile(ok[o:o + c.pixels], 3) for o, c in
-                          zip(np.cumsum([0] + [c.pixels for c in wl.cams[:-1]]), wl.cams)])
-    err = np.abs(img[ok3] - fw["image"][ok3]).max()
-    print(f"  sampled {ok.sum()} pixels, max image err {err:.2e}, flagged {int((pix_mask & (fw['flags'] != 0)).sum())}")
-    assert err <= P.IMG_TOL
-    assert np.array_equal(r.last.cpu().numpy()[ok], fw["last_contrib"][ok])
+    fwd = P.check_forward(wl, opts, r, tile_mask=mask, pix_mask=pix_mask)
+    ok = pix_mask & ~fwd["flagged"]
     # gradients from the sampled, unflagged pixels only
+    ok3 = P._per_channel(ok, wl.cams)
     w = np.zeros(3 * r.total_pixels, np.float32)
     w[ok3] = (rng.standard_normal(int(ok3.sum())) * 1e-3).astype(np.float32)
     grads = r.zero_grads(params)
     r.backward(params, torch.from_numpy(w).cuda(), grads)
     torch.cuda.synchronize()
+    sp = P.records(r)
     grad_rec = O.composite_bwd(wl.cams, opts, wl.scene.n, sp, gl["ids"], gl["ranges"], w.astype(np.float64),
                                tile_mask=mask)
-    og = O.zero_grads(wl.scene)
-    n = wl.scene.n
-    for v, c in enumerate(wl.cams):
-        O.project_bwd(wl.scene, c, opts, grad_rec[v * n:(v + 1) * n], og)
-    bad = {k: P.r24_violations(grads[k].cpu().numpy(), ref) for k, ref in og.items()}
+    og, absparts = P.oracle_param_grads(wl, opts, grad_rec)
+    # most Gaussians lie outside the sampled tiles: the floor's rms is over the gradient's support
+    bad = {k: P.r24_violations(grads[k].cpu().numpy(), ref, support_rms=True, absparts=absparts[k])
+           for k, ref in og.items()}
     print(" ", bad)
     for k, (nb, worst) in bad.items():
         assert nb == 0, (k, nb, worst)

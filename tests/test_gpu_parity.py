@@ -30,6 +30,12 @@ def _cases():
 
 
 CASES = _cases()
+# workloads 1 and 2 (and the tiny scene): no pixel may be excluded from the image comparison
+NO_EXCLUSION = ("tiny_masked", "cfg1", "cfg2_small")
+
+
+def _max_excluded(P, case):
+    return 0.0 if case in NO_EXCLUSION else P.MAX_EXCLUDED
 
 
 @pytest.fixture(scope="module")
@@ -65,9 +71,7 @@ def test_render_fwd_parity(P, case, fchunk):
     wl = dataclasses.replace(wl, opts=dataclasses.replace(wl.opts, fwd_chunk=fchunk))
     print(f"[render_fwd] {case} fchunk {fchunk}", flush=True)
     r, _ = P.gpu_forward(wl)
-    res = P.check_forward(wl, wl.opts, r)
-    print({k: v for k, v in res.items() if k not in ("fw", "flagged")})
-    assert res["flagged_frac"] <= 1e-3
+    P.check_forward(wl, wl.opts, r, max_excluded=_max_excluded(P, case))
 
 
 @pytest.mark.parametrize("chunk,fchunk", [(1024, 0), (16, 0), (16, 64), (1024, 256)])
@@ -81,7 +85,7 @@ def test_render_bwd_parity(P, case, chunk, fchunk):
     wl = dataclasses.replace(wl, opts=dataclasses.replace(wl.opts, bwd_chunk=chunk, fwd_chunk=fchunk))
     print(f"[render_bwd] {case} chunk {chunk} fchunk {fchunk}", flush=True)
     r, params = P.gpu_forward(wl)
-    fwd = P.check_forward(wl, wl.opts, r)
+    fwd = P.check_forward(wl, wl.opts, r, max_excluded=_max_excluded(P, case))
     res = P.check_backward(wl, wl.opts, r, params, fwd["flagged"], seed=3)
     print(res)
     for k, (bad, worst) in res.items():
