@@ -12,7 +12,9 @@
  *    its arguments on the host, enqueues kernels on `stream` and returns; no
  *    call reads device memory on the host, so every call may be captured in a
  *    HIP graph.  Scratch memory comes in through `ws` (size from
- *    gs_workspace_size) and is clobbered by the call.  The workspaces of
+ *    gs_workspace_size) and is clobbered by the call; the one exception,
+ *    gs_mask_loss_noalloc, uses a static device array of the library
+ *    instead.  The workspaces of
  *    gs_bin_sort, gs_render_fwd, gs_render_bwd, gs_blend_bwd, gs_project_bwd
  *    and gs_count_hits must be 256-byte aligned (hipMalloc and PyTorch
  *    allocations are); a misaligned one is GS_E_INVALID.
@@ -44,7 +46,8 @@ enum {
   GS_E_INVALID = -1,     /* bad argument: null pointer, size, degree, tile shape ... */
   GS_E_CAPACITY = -2,    /* reported through gs_binning.status, never returned by a call */
   GS_E_HIP = -3,         /* a kernel launch failed; hipGetLastError() is left set */
-  GS_E_UNSUPPORTED = -4  /* the current device is not gfx950 */
+  GS_E_UNSUPPORTED = -4, /* the current device is not gfx950 */
+  GS_E_TOO_LARGE = -5    /* beyond the static scratch of an allocation-free entry point */
 };
 
 #define GS_MAX_VIEWS 16       /* views per call */
@@ -297,6 +300,19 @@ int gs_loss_l1_dssim(const float* image, const float* target, const gs_camera* c
 size_t gs_mask_loss_workspace_size(int64_t n);
 int gs_mask_loss(const gs_gaussians* g, float lambda_m, float lambda_sh, float* loss, gs_grads* grads, void* ws,
                  size_t ws_bytes, gs_stream_t stream);
+
+/* gs_mask_loss without the workspace argument, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): the partial sums live in a static device array of the
+ * library (512 KiB per device, held until the process ends) instead of `ws`.
+ * Same kernels, same results, bit for bit, as gs_mask_loss.  n at most 2^24
+ * Gaussians, else GS_E_TOO_LARGE (nothing enqueued).  The call allocates
+ * nothing (no hipMalloc, no library allocation); it reads the array's device
+ * address once per device.  Calls that overlap on one device (other streams or
+ * threads) share the array and race: serialise them.  Nothing in the array
+ * needs clearing between calls. */
+int gs_mask_loss_noalloc(const gs_gaussians* g, float lambda_m, float lambda_sh, float* loss, gs_grads* grads,
+                         gs_stream_t stream);
 
 /* Ray hits of the significance score (Eq. 4, Sec. 3.2.2): the walk of
  * gs_render_fwd over the same lists and with the same per-pixel decisions,

@@ -4,11 +4,21 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "gs_api.h"
 #include "kernels.h"
 
 using namespace gs;
+
+// Scratch of gs_mask_loss_noalloc, the entry point for callers that cannot
+// allocate: the per-workgroup partial sums of the mask terms, two floats per
+// 256 Gaussians, for at most kNoAllocMaxGaussians Gaussians (512 KiB).  Each
+// device holds its own copy for the life of the process; host code reaches it
+// only through the address hipGetSymbolAddress returns on that device.
+constexpr int64_t kNoAllocMaxGaussians = (int64_t)1 << 24;
+constexpr size_t kScratchFloats = 2 * (size_t)(kNoAllocMaxGaussians / 256);
+static __device__ __align__(256) float scratch[kScratchFloats];
 
 namespace {
 
@@ -30,6 +40,22 @@ int device_ok() {
     cached[dev] = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : -1;
   }
   return cached[dev] == 1 ? GS_OK : GS_E_UNSUPPORTED;
+}
+
+// Device address of `scratch` on the current device, looked up once per device
+// with that device current; NULL if the lookup fails.
+float* scratch_on_current_device() {
+  static std::mutex mu;
+  static float* addr[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+    addr[dev] = (float*)p;
+  }
+  return addr[dev];
 }
 
 // logit(eps) rounded down to a float, so that for every float m:
@@ -307,6 +333,8 @@ const char* gs_strerror(int code) {
     case GS_E_CAPACITY: return "binning capacity exceeded";
     case GS_E_HIP: return "HIP launch failure";
     case GS_E_UNSUPPORTED: return "device is not gfx950";
+    case GS_E_TOO_LARGE: return "input larger than the static scratch of the allocation-free entry point "
+                                "(gs_mask_loss_noalloc: at most 2^24 Gaussians)";
     default: return "unknown error";
   }
 }
@@ -637,6 +665,24 @@ int gs_mask_loss(const gs_gaussians* g, float lambda_m, float lambda_sh, float* 
   float* gsh = grads ? grads->sh_mask_logits : nullptr;
   return launched(launch_mask_loss(g->mask_logits, g->sh_mask_logits, g->n, g->sh_degree, lambda_m, lambda_sh, gm,
                                    gsh, loss, (float*)ws, (hipStream_t)stream));
+}
+
+int gs_mask_loss_noalloc(const gs_gaussians* g, float lambda_m, float lambda_sh, float* loss, gs_grads* grads,
+                         gs_stream_t stream) {
+  if (!g || g->n < 0 || g->sh_degree < 0 || g->sh_degree > 3) return GS_E_INVALID;
+  if (!std::isfinite(lambda_m) || !std::isfinite(lambda_sh)) return GS_E_INVALID;
+  if (g->n > kNoAllocMaxGaussians) return GS_E_TOO_LARGE;
+  static_assert(2 * ((kNoAllocMaxGaussians + 255) / 256) <= (int64_t)kScratchFloats, "scratch too small");
+  const int d = device_ok();
+  if (d != GS_OK) return d;
+  float* ws = scratch_on_current_device();
+  if (!ws) return GS_E_HIP;
+  float* gm = grads ? grads->mask_logits : nullptr;
+  float* gsh = grads ? grads->sh_mask_logits : nullptr;
+  // every partial sum the reduction reads is written first by the same call:
+  // nothing in the scratch needs clearing
+  return launched(launch_mask_loss(g->mask_logits, g->sh_mask_logits, g->n, g->sh_degree, lambda_m, lambda_sh, gm,
+                                   gsh, loss, ws, (hipStream_t)stream));
 }
 
 }  // extern "C"

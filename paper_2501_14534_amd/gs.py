@@ -13,7 +13,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libgs.so")
 
-GS_OK, GS_E_INVALID, GS_E_CAPACITY, GS_E_HIP, GS_E_UNSUPPORTED = 0, -1, -2, -3, -4
+GS_OK, GS_E_INVALID, GS_E_CAPACITY, GS_E_HIP, GS_E_UNSUPPORTED, GS_E_TOO_LARGE = 0, -1, -2, -3, -4, -5
 MAX_VIEWS = 16
 SPLAT_FLOATS = 12
 GRAD_FLOATS = 9
@@ -21,7 +21,7 @@ MAX_BATCH = 1024
 
 EXPORTS = ("gs_view_sizes", "gs_workspace_size", "gs_project", "gs_bin_sort", "gs_render_fwd", "gs_render_bwd",
            "gs_blend_bwd", "gs_project_bwd", "gs_loss_workspace_size", "gs_loss_l1_dssim", "gs_l2_grad",
-           "gs_mask_loss_workspace_size", "gs_mask_loss", "gs_count_hits", "gs_significance_workspace_size",
+           "gs_mask_loss_workspace_size", "gs_mask_loss", "gs_mask_loss_noalloc", "gs_count_hits", "gs_significance_workspace_size",
            "gs_significance", "gs_blur_views", "gs_resize_views", "gs_strerror")
 
 vp = C.c_void_p
@@ -106,6 +106,8 @@ def load():
     L.gs_mask_loss_workspace_size.restype = C.c_size_t
     L.gs_mask_loss.argtypes = [P(GsGaussians), C.c_float, C.c_float, vp, P(GsGrads), vp, C.c_size_t, vp]
     L.gs_mask_loss.restype = C.c_int
+    L.gs_mask_loss_noalloc.argtypes = [P(GsGaussians), C.c_float, C.c_float, vp, P(GsGrads), vp]
+    L.gs_mask_loss_noalloc.restype = C.c_int
     L.gs_count_hits.argtypes = [P(GsProjected), P(GsBinning), P(GsCamera), C.c_int32, C.c_int64, P(GsOpts), vp, vp]
     L.gs_count_hits.restype = C.c_int
     L.gs_significance_workspace_size.argtypes = []
@@ -247,3 +249,8 @@ def mask_loss_workspace_size(n) -> int:
 def mask_loss(g, lambda_m, lambda_sh, loss, grads, ws, ws_bytes, stream) -> int:
     return load().gs_mask_loss(C.byref(g), float(lambda_m), float(lambda_sh), loss,
                                C.byref(grads) if grads is not None else None, ws, ws_bytes, stream)
+
+
+def mask_loss_noalloc(g, lambda_m, lambda_sh, loss, grads, stream) -> int:
+    return load().gs_mask_loss_noalloc(C.byref(g), float(lambda_m), float(lambda_sh), loss,
+                                       C.byref(grads) if grads is not None else None, stream)
