@@ -27,17 +27,17 @@ if ROOT not in sys.path:
 
 import numpy as np  # noqa: E402
 
-PEAK_FP32_TFLOPS = 157.3   # MI355X published fp32 vector peak
+PEAK_FP32_TFLOPS = 157.3   # MI355X published fp32 vector peak (packed FP32: 256 CU x 4 SIMD x 16 lanes x 2 x 2 x 2.4 GHz)
+PEAK_FP32_ISSUE_TFLOPS = 78.6  # the same without packed FP32, which this build does not emit
 PEAK_HBM_GBS = 8000.0      # MI355X HBM3E
-# Algorithmic work per composited (pixel, splat) pair, counted from the
-# operations the method needs.  Forward: 2 (offset) + 9 (quadratic form) + 1
-# (exponent scale) + 1 (exp) + 2 (opacity product, cap) + 2 (T (1 - alpha)) +
-# 7 (colour update).  Backward: 15 (recompute) + 2 (T recovery) + 6 (colour
-# gradient) + 8 (dL/dalpha) + 19 (conic and position gradient) + 2 (opacity) +
-# 8 (bookkeeping).
-FWD_FLOP_PER_PAIR = 24.0
-BWD_FLOP_PER_PAIR = 60.0
-COUNT_FLOP_PER_PAIR = 17.0  # the forward walk without the 7 FLOP of the colour update
+# Algorithmic work per composited (pixel, splat) pair: the forward blend costs
+# about 20 vector operations and one exponential, the backward about 50 vector
+# operations, one exponential and one reciprocal.  Counted per composited pair
+# (sum of last_contrib over the pixels), each operation as one FLOP.
+FWD_FLOP_PER_PAIR = 21.0
+BWD_FLOP_PER_PAIR = 52.0
+COUNT_FLOP_PER_PAIR = 14.0  # the forward walk without the colour update (7 of its 20 operations)
+STAGE_REPS = 50             # stage timings: median over this many repetitions
 
 
 def parse():
@@ -69,6 +69,22 @@ def kernel_source_hash() -> str:
             h.update(f.encode())
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def load_counters(kernel: str, workload: str, src_hash: str):
+    """VALU and LDS utilisation of a kernel from committed rocprofv3 --pmc summaries, if taken on this
+    kernel source."""
+    p = os.path.join(ROOT, "profiles", "pmc_valu_lds.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        e = json.load(open(p)).get(f"{kernel}@{workload}")
+        if e and e.get("source_hash") == src_hash:
+            return {k: e[k] for k in ("valu_busy", "valu_utilization", "lds_util", "lds_bank_conflict_per_access",
+                                      "lds_bytes_per_launch") if k in e}
+    except (ValueError, KeyError, TypeError):
+        return None
+    return None
 
 
 def load_traffic(kernel: str, workload: str, src_hash: str):
@@ -189,13 +205,12 @@ def main():
 
     # ---------------- stage timing with HIP events on the launch stream ----------------
     r = step.rast
-    stream = torch.cuda.current_stream()
+    stream = torch.cuda.current_stream()  # every call below launches on it
     names = ["project", "bin_sort", "render_fwd", "blend_bwd", "project_bwd"]
-    acc = {k: 0.0 for k in names}
+    samples = {k: [] for k in names}
     grad_pair = torch.zeros(r.capacity * gs.GRAD_FLOATS, dtype=torch.float32, device=dev)
-    nrep = max(3, min(args.steps, 10))
     dL = step.dL
-    for _ in range(nrep):
+    for _ in range(STAGE_REPS):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
         ev[0].record(stream)
         r.project(params)
@@ -210,10 +225,21 @@ def main():
         ev[5].record(stream)
         torch.cuda.synchronize()
         for i, k in enumerate(names):
-            acc[k] += ev[i].elapsed_time(ev[i + 1])
-    stage_ms = {k: v / nrep for k, v in acc.items()}
+            samples[k].append(ev[i].elapsed_time(ev[i + 1]))
+    stage_ms = {k: float(np.median(v)) for k, v in samples.items()}
     K = r.pairs()
     useful_pairs = int(r.last.to(torch.int64).sum())
+    # list entries walked: per tile, the largest last_contrib of its pixels
+    walked = 0
+    off = 0
+    for c in wl.cams:
+        tw, th = opts.tile_w, opts.tile_h
+        TX, TY = -(-c.width // tw), -(-c.height // th)
+        lc = r.last[off:off + c.pixels].view(c.height, c.width)
+        pad = torch.zeros(TY * th, TX * tw, dtype=lc.dtype, device=lc.device)
+        pad[:c.height, :c.width] = lc
+        walked += int(pad.view(TY, th, TX, tw).amax(dim=(1, 3)).to(torch.int64).sum())
+        off += c.pixels
 
     # dominant single-kernel stage (project_bwd runs two kernels: colour, then geometry;
     # render_fwd's stage also holds a fill of the chunk-slot owners, ~5 us)
@@ -226,7 +252,10 @@ def main():
         flop = useful_pairs * (FWD_FLOP_PER_PAIR if dom == "render_fwd" else BWD_FLOP_PER_PAIR)
         achieved = flop / t_s / 1e12
         roof = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
-                    frac=round(achieved / PEAK_FP32_TFLOPS, 5))
+                    frac=round(achieved / PEAK_FP32_TFLOPS, 5),
+                    frac_of_unpacked_peak=round(achieved / PEAK_FP32_ISSUE_TFLOPS, 5),
+                    work=f"{FWD_FLOP_PER_PAIR if dom == 'render_fwd' else BWD_FLOP_PER_PAIR:g} FLOP per composited "
+                         f"pair x {useful_pairs} composited pairs")
     else:
         nrec = V * sc.n
         byts = 252.0 * sc.n + 52.0 * nrec  # project: parameters read once, 48 + 4 B per record
@@ -236,6 +265,10 @@ def main():
     roof["kernel"] = single[dom]
     roof["ms_per_launch"] = round(stage_ms[dom], 4)
     roof["traffic"] = load_traffic(single[dom], workload, src_hash)
+    roof["traffic_source"] = "profiles/pmc_traffic.json (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE of this kernel source)"
+    # VALU and LDS utilisation of the two blend walks (rocprofv3 --pmc, committed summaries)
+    walks = {k: load_counters(k, workload, src_hash) for k in ("render_fwd_kernel", "render_bwd_kernel")}
+    roof["valu_lds"] = {k: v for k, v in walks.items() if v is not None} or None
 
     # ---------------- L1 + D-SSIM loss (Eq. 7) on the rendered views ----------------
     from paper_2501_14534_amd.photometric import PhotometricLoss
@@ -290,6 +323,9 @@ def main():
     if not args.no_cpu_baseline:
         from oracle import baseline
         cpu = baseline.measure(wl, opts, target_seconds=args.cpu_seconds)
+        cpu["cpu_model"] = baseline.cpu_model()
+        cpu["host_threads"] = len(os.sched_getaffinity(0))
+        cpu["one_thread"] = baseline.measure_one_thread(wl, opts, target_seconds=max(4.0, args.cpu_seconds / 3))
 
     out = {
         "metric": "fwd+bwd rasterized Mpix/s at 1M Gaussians; batched-vs-per-view speedup at 1e-5",
@@ -313,7 +349,10 @@ def main():
         "per_view": per_view,
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "pairs": K,
+        "walked_entries": walked,
+        "evaluated_pairs": walked * opts.tile_w * opts.tile_h,
         "useful_pairs": useful_pairs,
+        "stage_timing": f"HIP events on the launch stream, median of {STAGE_REPS} eager repetitions",
         "roofline": roof,
         "cpu_baseline": cpu,
         "l1_dssim": l1_dssim,

@@ -12,6 +12,10 @@ run as it stands -- not tuned for speed -- on the host cores it was built for
     budget, else on a random subset of one view's records, scaled by the
     record fraction and the view count.
 The reported rate is total pixels / (sum of the scaled stage times).
+A second, smaller run on one thread (measure_one_thread) times each stage on a
+random sample -- projection and projection backward on a subset of the
+Gaussians, compositing on a subset of the tiles, binning in full -- and scales
+each by its sample fraction.
 """
 from __future__ import annotations
 
@@ -104,3 +108,61 @@ def measure(wl, opts, target_seconds: float = 20.0, seed: int = 0) -> dict:
                     "project_bwd_scaled": round(t_pbwd_full, 3)},
         "measured_s": round(t_proj + t_bin + tf + tb + tp, 3),
     }
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (the "model name" line of /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.lower().startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def measure_one_thread(wl, opts, target_seconds: float = 8.0, seed: int = 1) -> dict:
+    """The oracle on one thread, each stage on a sample scaled by its fraction."""
+    sc = wl.scene
+    n, V = sc.n, len(wl.cams)
+    rng = np.random.default_rng(seed)
+    prev = O.num_threads()
+    # lists of the whole workload (not timed, all threads)
+    sp = O.project_views(sc, wl.cams, opts)
+    O.set_threads(1)
+    try:
+        m = int(min(n, max(500, n // 200)))
+        sub = sc.subset(np.sort(rng.choice(n, size=m, replace=False)))
+        _, tp = _t(lambda: O.project_views(sub, wl.cams, opts))
+        t_proj = tp * n / m
+        lists, t_bin = _t(lambda: O.bin(wl.cams, opts, n, sp["uv"][:, 0].astype(np.float32),
+                                         sp["uv"][:, 1].astype(np.float32), sp["depth"].astype(np.float32),
+                                         sp["radius"], sp["valid"]))
+        T = lists["ranges"].shape[0]
+        P = wl.pixels
+        dl = rng.standard_normal(3 * P) / np.sqrt(3 * P)
+        order = rng.permutation(T)
+        budget = 0.5 * target_seconds
+        spent, k, tf, tb = 0.0, 0, 0.0, 0.0
+        step = max(1, T // 200)
+        while k < T and spent < budget:
+            mask = np.zeros(T, np.uint8)
+            mask[order[k:k + step]] = 1
+            _, a = _t(lambda: O.composite_fwd(wl.cams, opts, n, sp, lists["ids"], lists["ranges"], tile_mask=mask))
+            _, b = _t(lambda: O.composite_bwd(wl.cams, opts, n, sp, lists["ids"], lists["ranges"], dl,
+                                              tile_mask=mask))
+            tf, tb, spent, k = tf + a, tb + b, spent + a + b, k + step
+        ft = min(k, T) / T
+        grads = O.zero_grads(sub)
+        gr = np.ones((sub.n, 9))
+        _, tpb = _t(lambda: O.project_bwd(sub, wl.cams[0], opts, gr, grads))
+        t_pbwd = tpb * (n / m) * V
+    finally:
+        O.set_threads(prev)
+    total = t_proj + t_bin + (tf + tb) / ft + t_pbwd
+    return {"value": round(wl.pixels / total / 1e6, 5), "unit": "Mpix/s", "cores": 1,
+            "sample": f"one thread: projection and projection backward on {m} of {n} Gaussians, compositing on "
+                      f"{min(k, T)} of {T} tiles (each scaled by its fraction), binning in full",
+            "stage_s": {"project_scaled": round(t_proj, 3), "bin": round(t_bin, 3),
+                        "composite_scaled": round((tf + tb) / ft, 3), "project_bwd_scaled": round(t_pbwd, 3)}}

@@ -10,11 +10,13 @@
 //      8-bit passes; stable, so equal depths keep record order).
 //   4. gather_reduce gathers the descriptors into depth order once (the only
 //      random access of the emission) and sums the pairs per block;
+//      emit_prefix: each depth-sorted record's first output position;
 //      emit_pairs: the records, now in depth order, emit one (tile, canonical
 //      pair index, record id) per touched tile into a contiguous
-//      depth-ordered range; a block fills its range slot by slot (binary
-//      search of the owning record in LDS), so writes are coalesced and big
-//      Gaussians do not serialise a lane.
+//      depth-ordered range; each workgroup fills a fixed chunk of output
+//      positions slot by slot (binary search of the owning record in LDS), so
+//      writes are coalesced and neither a big Gaussian nor a block of them
+//      serialises the work.
 //   5. LSD radix sort of the pairs by tile id only (ceil(log2 #tiles) bits,
 //      two passes up to 65536 tiles), carrying pair index and record id.
 //      Stability keeps depth order, and record order among equal depths,
@@ -257,77 +259,105 @@ __global__ __launch_bounds__(kScanThreads) void gather_reduce(const uint4* __res
   if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
 }
 
-// Emission in depth order: sorted record m emits, at depth-ordered positions
-// [eoff(m), eoff(m) + w h), its tiles in row-major order of its tile
-// rectangle: tile id, the pair's canonical index offsets[r] + j, and r.  The
-// block's descriptors are staged in LDS with coalesced loads; each thread
-// then scans the pair counts of 4 consecutive records.
-__global__ __launch_bounds__(kScanThreads) void emit_pairs(const uint4* __restrict__ sdesc,
-                                                           const uint32_t* __restrict__ nvis,
-                                                           const uint32_t* __restrict__ eblock_offsets,
-                                                           const int32_t* __restrict__ status, ViewTable vt,
-                                                           uint32_t* __restrict__ tkey, uint32_t* __restrict__ tval,
-                                                           uint32_t* __restrict__ trec) {
+// Output positions per emission workgroup.
+constexpr int kEmitChunk = 1536;  // 5 staged words per record: 30 KB of LDS, 5 workgroups per CU
+
+// Emission offsets in depth order: epref[m] = the first output position of
+// depth-sorted record m (its block's offset plus the exclusive prefix of the
+// pair counts within the block of 1024), and for every chunk of kEmitChunk
+// output positions the record holding its first position (chunk_first).
+__global__ __launch_bounds__(kScanThreads) void emit_prefix(const uint4* __restrict__ sdesc,
+                                                            const uint32_t* __restrict__ nvis,
+                                                            const uint32_t* __restrict__ eblock_offsets,
+                                                            const int32_t* __restrict__ status,
+                                                            uint32_t* __restrict__ epref,
+                                                            uint32_t* __restrict__ chunk_first) {
   __shared__ uint32_t s_wave[kScanThreads / kWave];
-  __shared__ uint32_t s_pref[kScanTile];
-  __shared__ uint32_t s_base[kScanTile];
-  __shared__ uint32_t s_w[kScanTile];
-  __shared__ uint32_t s_tx[kScanTile];
-  __shared__ uint32_t s_rec[kScanTile];
-  __shared__ uint32_t s_off[kScanTile];
   const uint32_t N = effective_count(nvis, status);
   const int64_t blk = (int64_t)blockIdx.x * kScanTile;
   if (blk >= N) return;  // uniform
+  // thread t takes 4 consecutive records, so the block scan runs in record order
+  const int64_t m0 = blk + (int64_t)threadIdx.x * kScanItems;
+  uint32_t c[kScanItems], sum = 0;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    const int li = k * kScanThreads + threadIdx.x;
-    const int64_t m = blk + li;
-    uint32_t cnt = 0u;
-    if (m < N) {
-      const uint4 d = sdesc[m];
-      const uint32_t w = d.y & 0xffffu;
-      cnt = w * (d.y >> 16);
-      int v = 0;  // view of the record's first tile
-      while (v + 1 < vt.nviews && d.x >= (uint32_t)vt.v[v + 1].tile_off) ++v;
-      s_base[li] = d.x;
-      s_w[li] = w;
-      s_off[li] = d.z;
-      s_rec[li] = d.w;
-      s_tx[li] = (uint32_t)vt.v[v].TX;
+    c[k] = 0u;
+    if (m0 + k < N) {
+      const uint32_t wh = sdesc[m0 + k].y;
+      c[k] = (wh & 0xffffu) * (wh >> 16);
     }
-    s_pref[li] = cnt;
-  }
-  __syncthreads();
-  const int li0 = threadIdx.x * kScanItems;
-  uint32_t c[kScanItems];
-  uint32_t s = 0;
-#pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    c[k] = s_pref[li0 + k];
-    s += c[k];
+    sum += c[k];
   }
   uint32_t total;
-  uint32_t ex = block_exclusive_scan_256(s, &total, s_wave);  // its barriers order the reads above
+  uint32_t ex = block_exclusive_scan_256(sum, &total, s_wave) + eblock_offsets[blockIdx.x];
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    s_pref[li0 + k] = ex;
+    if (m0 + k < N) {
+      epref[m0 + k] = ex;
+      // chunks whose first position lies in [ex, ex + c)
+      for (uint32_t q = (ex + kEmitChunk - 1) / kEmitChunk; q * (uint64_t)kEmitChunk < (uint64_t)ex + c[k]; ++q)
+        chunk_first[q] = (uint32_t)(m0 + k);
+    }
     ex += c[k];
   }
+}
+
+// Emission in depth order: sorted record m emits, at output positions
+// [epref[m], epref[m] + w h), its tiles in row-major order of its tile
+// rectangle: tile id, the pair's canonical index offsets[r] + j, and r.
+// Workgroup c owns output positions [c C, (c + 1) C), C = kEmitChunk: it
+// stages the descriptors of the records from the one holding its first
+// position to the one holding the next chunk's (at most C + 1: every record
+// has a pair) and fills its slots in order (binary search of the owning
+// record in LDS).  Work per workgroup is bounded by C slots however many
+// pairs one record has (the nearest Gaussians cover thousands of tiles), and
+// consecutive threads write consecutive positions.
+__global__ __launch_bounds__(kScanThreads) void emit_pairs(const uint4* __restrict__ sdesc,
+                                                           const uint32_t* __restrict__ epref,
+                                                           const uint32_t* __restrict__ chunk_first,
+                                                           const uint32_t* __restrict__ nvis,
+                                                           const uint32_t* __restrict__ count,
+                                                           const int32_t* __restrict__ status, ViewTable vt,
+                                                           uint32_t* __restrict__ tkey, uint32_t* __restrict__ tval,
+                                                           uint32_t* __restrict__ trec) {
+  constexpr int kR = kEmitChunk + 1;
+  __shared__ uint32_t s_pref[kR];
+  __shared__ uint32_t s_base[kR];
+  __shared__ uint32_t s_wtx[kR];  // rect width | the view's tile columns << 16
+  __shared__ uint32_t s_rec[kR];
+  __shared__ uint32_t s_off[kR];
+  const uint32_t N = effective_count(nvis, status);
+  const uint32_t K = effective_count(count, status);
+  const uint32_t slot0 = blockIdx.x * (uint32_t)kEmitChunk;
+  if (N == 0 || slot0 >= K) return;  // uniform
+  const uint32_t slot1 = min(slot0 + (uint32_t)kEmitChunk, K);
+  const uint32_t m0 = chunk_first[blockIdx.x];
+  const uint32_t m_end = slot1 < K ? chunk_first[blockIdx.x + 1] + 1u : N;
+  const int nr = (int)(m_end - m0);  // records that may own slots of the chunk (<= kR)
+  for (int i = threadIdx.x; i < nr; i += kScanThreads) {
+    const uint4 d = sdesc[m0 + i];
+    int v = 0;  // view of the record's first tile
+    while (v + 1 < vt.nviews && d.x >= (uint32_t)vt.v[v + 1].tile_off) ++v;
+    s_pref[i] = epref[m0 + i];
+    s_base[i] = d.x;
+    s_wtx[i] = (d.y & 0xffffu) | ((uint32_t)vt.v[v].TX << 16);
+    s_off[i] = d.z;
+    s_rec[i] = d.w;
+  }
   __syncthreads();
-  const uint32_t out0 = eblock_offsets[blockIdx.x];
-  for (uint32_t slot = threadIdx.x; slot < total; slot += kScanThreads) {
-    // last record whose exclusive prefix is <= slot
-    int lo = 0, hi = kScanTile;  // invariant: s_pref[lo] <= slot < s_pref[hi] (virtual s_pref[kScanTile] = total)
+  for (uint32_t slot = slot0 + threadIdx.x; slot < slot1; slot += kScanThreads) {
+    // last staged record whose first position is <= slot
+    int lo = 0, hi = nr;  // invariant: s_pref[lo] <= slot, and slot < s_pref[hi] when hi < nr
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;
       if (s_pref[mid] <= slot) lo = mid; else hi = mid;
     }
     const uint32_t j = slot - s_pref[lo];
-    const uint32_t w = s_w[lo];
+    const uint32_t wtx = s_wtx[lo], w = wtx & 0xffffu;
     const uint32_t ty = j / w, tx = j - ty * w;
-    tkey[out0 + slot] = s_base[lo] + ty * s_tx[lo] + tx;
-    tval[out0 + slot] = s_off[lo] + j;  // canonical pair index
-    trec[out0 + slot] = s_rec[lo];
+    tkey[slot] = s_base[lo] + ty * (wtx >> 16) + tx;
+    tval[slot] = s_off[lo] + j;  // canonical pair index
+    trec[slot] = s_rec[lo];
   }
 }
 
@@ -598,6 +628,7 @@ struct SortWs {
   uint32_t* hist;           // [256][sort blocks]
   uint32_t* digit_total;    // [256]
   uint32_t* tile_hist;      // [128] tile schedule counters
+  uint32_t* chunk_first;    // [capacity / kEmitChunk + 1] first record of each emission chunk
   size_t bytes;
 };
 
@@ -632,6 +663,7 @@ static SortWs carve(const SortPlan& p, uint64_t capacity, void* ws) {
   w.hist = take(4 * (size_t)kRadix * (size_t)(p.sort_blocks > p.rec_sort_blocks ? p.sort_blocks : p.rec_sort_blocks));
   w.digit_total = take(4 * (size_t)kRadix);
   w.tile_hist = take(4 * 128);
+  w.chunk_first = take(4 * ((size_t)capacity / kEmitChunk + 2));
   w.bytes = o;
   return w;
 }
@@ -686,11 +718,17 @@ hipError_t launch_bin_sort(const SortPlan& plan, const float4* splats, const uin
                        w.sdesc, w.eblock_sums);
     hipLaunchKernelGGL(scan_top, dim3(1), dim3(1024), 0, s, w.eblock_sums, nb, w.eblock_offsets, (uint64_t)0,
                        w.nvis + 1, (int32_t*)nullptr);  // total unused (equals K)
+    // per-record emission offsets (in dkey_alt, free after the depth sort), then
     // emit so that the tile sort ends in (tkey, pair_index, ids)
+    uint32_t* epref = w.dkey_alt;
+    hipLaunchKernelGGL(emit_prefix, dim3((unsigned)nb), dim3(kScanThreads), 0, s, w.sdesc, w.nvis, w.eblock_offsets,
+                       status, epref, w.chunk_first);
     const bool even = plan.tile_passes % 2 == 0;
-    hipLaunchKernelGGL(emit_pairs, dim3((unsigned)nb), dim3(kScanThreads), 0, s, w.sdesc, w.nvis, w.eblock_offsets,
-                       status, vt, even ? w.tkey : w.tkey_alt, even ? out.pair_index : w.tval_alt,
-                       even ? out.ids : w.trec_alt);
+    const int64_t emit_blocks = ((int64_t)capacity + kEmitChunk - 1) / kEmitChunk;
+    if (emit_blocks > 0)
+      hipLaunchKernelGGL(emit_pairs, dim3((unsigned)emit_blocks), dim3(kScanThreads), 0, s, w.sdesc, epref,
+                         w.chunk_first, w.nvis, count, status, vt, even ? w.tkey : w.tkey_alt,
+                         even ? out.pair_index : w.tval_alt, even ? out.ids : w.trec_alt);
     if (even)
       radix_sort<uint32_t, 2>(w.tkey, out.pair_index, out.ids, w.tkey_alt, w.tval_alt, w.trec_alt, plan.tile_passes,
                               count, status, plan.sort_blocks, w, s);

@@ -87,16 +87,23 @@ __device__ __forceinline__ float acc_mul_add(float t, float a, float b) {
 }
 
 // Sums of the 9 pair gradients of each lane's record (cnt pairs from pair
-// index off; cnt = 0 gives zeros), in emission order, accumulated in double
-// and rounded once to float.  Called by all 64 lanes of a wave together, for
-// records of consecutive Gaussians in one view: their pairs form one
-// contiguous run of the [K][9] array (emission order is record order), which
-// the wave copies into LDS window by window with 16-byte loads of consecutive
-// addresses, with the pairs' live bytes; each lane then adds its own live
-// pairs from LDS (a pair the backward walk did not reach has no row this
-// step and counts as zero).  (Loading its pairs directly would touch a
-// separate cache line per lane and load.)
+// index off; cnt = 0 gives zeros), accumulated in double and rounded once to
+// float.  Called by all 64 lanes of a wave together, for records of
+// consecutive Gaussians in one view: their pairs form one contiguous run of
+// the [K][9] array (emission order is record order).  A pair the backward walk
+// did not reach has no row this step (its live byte is 0) and counts as zero.
+//  - Light records (at most kHeavyPairs pairs): the wave copies the run into
+//    LDS window by window with 16-byte loads of consecutive addresses, with the
+//    pairs' live bytes, and each lane adds its own pairs from LDS in emission
+//    order.  (Loading its pairs directly would touch a separate cache line per
+//    lane and load.)  Windows holding no light record's pairs are skipped.
+//  - Heavy records (the nearest Gaussians cover thousands of tiles, which one
+//    lane would add up alone) are summed beforehand by heavy_sums_kernel, the
+//    whole wave on one record, and are left at zero here.
+// Both orders depend only on the record's own pairs, not on where its run
+// starts, so a record's sums are the same in a batched and a per-view call.
 constexpr int kSumWindow = 256;  // pairs per window (9 x 256 floats = 576 float4, 9 per lane)
+constexpr uint32_t kHeavyPairs = 256;
 
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -108,14 +115,20 @@ __device__ __forceinline__ void record_sums(const float* __restrict__ grad_pair,
                                             uint32_t cnt, uint32_t off, float4* win4, uint32_t* livew, int lane,
                                             float out[GS_GRAD_FLOATS]) {
   double gsum[GS_GRAD_FLOATS] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  // offsets grow with the lane (consecutive records), so the run starts at
-  // the first lane with pairs and ends after the last one's
-  const uint64_t act = __ballot(cnt != 0u);
+  const uint32_t lcnt = cnt > kHeavyPairs ? 0u : cnt;
+  // offsets grow with the lane (consecutive records), so the light records'
+  // pairs lie between the first light lane's start and the last one's end
+  const uint64_t act = __ballot(lcnt != 0u);
   const uint32_t lo = act ? (uint32_t)__builtin_amdgcn_readlane((int)off, __builtin_ctzll(act)) : 0u;
-  const uint32_t hi = act ? (uint32_t)__builtin_amdgcn_readlane((int)(off + cnt), 63 - __builtin_clzll(act)) : 0u;
+  const uint32_t hi = act ? (uint32_t)__builtin_amdgcn_readlane((int)(off + lcnt), 63 - __builtin_clzll(act)) : 0u;
   float* win = (float*)win4;
-  for (uint32_t w0 = lo & ~3u; w0 < hi; w0 += kSumWindow) {  // window starts on 16 bytes
+  uint32_t w0 = lo & ~3u;  // windows start on 16 bytes
+  while (w0 < hi) {
     const uint32_t w1 = min(w0 + (uint32_t)kSumWindow, hi);
+    if (__ballot(lcnt != 0u && off < w1 && off + lcnt > w0) == 0) {  // only heavy records' pairs here
+      w0 += kSumWindow;
+      continue;
+    }
     const int nfl = (int)(w1 - w0) * GS_GRAD_FLOATS, nf4 = nfl / 4;
     const float* src = grad_pair + (size_t)w0 * GS_GRAD_FLOATS;
     // loads straight into LDS, no registers in between: lane l of load j
@@ -137,16 +150,58 @@ __device__ __forceinline__ void record_sums(const float* __restrict__ grad_pair,
                                        (__attribute__((address_space(3))) void*)livew, 4, 0, 0);
     __builtin_amdgcn_s_waitcnt(0);  // the LDS writes of the loads above have landed
     wave_lds_sync();
-    const uint32_t k1 = min(off + cnt, w1);
+    const uint32_t k1 = min(off + lcnt, w1);
     const uint8_t* lv = (const uint8_t*)livew;
     for (uint32_t k = max(off, w0); k < k1; ++k)
       if (lv[k - w0])  // rows of pairs the walk did not reach are not written: they count as zero
 #pragma unroll
         for (int c = 0; c < GS_GRAD_FLOATS; ++c) gsum[c] += (double)win[(k - w0) * GS_GRAD_FLOATS + c];
     wave_lds_sync();  // every lane has read the window before the next one overwrites it
+    w0 += kSumWindow;
   }
 #pragma unroll
   for (int c = 0; c < GS_GRAD_FLOATS; ++c) out[c] = (float)gsum[c];
+}
+
+__device__ __forceinline__ double wave_sum_f64(double x) {
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) x += __shfl_xor(x, o, kWave);
+  return x;
+}
+
+// Sums of the pair gradients of the heavy records (more than kHeavyPairs
+// pairs), written to the record planes (all nine) for the colour kernel to
+// read.  One thread per record finds them; each wave then takes its heavy
+// records one at a time: lane j adds pairs j, j + 64, ... of the record in
+// double, a butterfly in a fixed pattern adds the lanes, and the sum is
+// rounded once to float.
+__global__ __launch_bounds__(256) void heavy_sums_kernel(ProjectBwdArgs b, int64_t nrec) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1);
+  const uint32_t cnt = r < nrec && *b.status == 0 ? b.tiles_touched[r] : 0u;
+  uint64_t hv = __ballot(cnt > kHeavyPairs);
+  while (hv) {
+    const int L = __builtin_ctzll(hv);
+    hv &= hv - 1;
+    const int64_t hr = (int64_t)__builtin_amdgcn_readlane((int)(r - (int64_t)blockIdx.x * blockDim.x), L) +
+                       (int64_t)blockIdx.x * blockDim.x;
+    const uint32_t hcnt = (uint32_t)__builtin_amdgcn_readlane((int)cnt, L);
+    const uint32_t hoff = b.offsets[hr];
+    double part[GS_GRAD_FLOATS] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (uint32_t j = (uint32_t)lane; j < hcnt; j += kWave) {
+      const size_t k = (size_t)hoff + j;
+      if (b.pair_live[k]) {
+        const float* row = b.grad_pair + k * GS_GRAD_FLOATS;
+#pragma unroll
+        for (int c = 0; c < GS_GRAD_FLOATS; ++c) part[c] += (double)row[c];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < GS_GRAD_FLOATS; ++c) {
+      const double t = wave_sum_f64(part[c]);
+      if (lane == L) b.rec[c * b.rec_stride + hr] = (float)t;
+    }
+  }
 }
 
 // A parameter gradient: written (assign) or added.
@@ -274,6 +329,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void p
     if (__ballot(on) == 0) continue;
     float g9[GS_GRAD_FLOATS];
     record_sums(b.grad_pair, b.pair_live, cnt, off, s_win[wave], s_live[wave], lane, g9);
+    if (cnt > kHeavyPairs) {  // summed by heavy_sums_kernel
+#pragma unroll
+      for (int c = 0; c < GS_GRAD_FLOATS; ++c) g9[c] = b.rec[c * b.rec_stride + r];
+    }
     if (b.g_mean2d && on) {
       b.g_mean2d[(v * 2 + 0) * n + i] += g9[0];
       b.g_mean2d[(v * 2 + 1) * n + i] += g9[1];
@@ -541,6 +600,8 @@ __global__ __launch_bounds__(256) void project_bwd_geom_kernel(ProjectBwdArgs b,
 hipError_t launch_project_bwd(const ProjectBwdArgs& a, const ViewTable& vt, int deg, hipStream_t s) {
   if (a.p.n == 0) return hipSuccess;
   const dim3 block(256), grid((unsigned)((a.p.n + 255) / 256));
+  const int64_t nrec = (int64_t)vt.nviews * a.p.n;
+  hipLaunchKernelGGL(heavy_sums_kernel, dim3((unsigned)((nrec + 255) / 256)), block, 0, s, a, nrec);
   const bool rest = a.g_sh_rest != nullptr && deg > 0;
   switch (deg) {
     case 0: hipLaunchKernelGGL((project_bwd_color_kernel<0, false>), grid, block, 0, s, a, vt); break;

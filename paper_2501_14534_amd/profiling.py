@@ -3,6 +3,11 @@
   python -m paper_2501_14534_amd.profiling stats DIR --cmd "..." --out profiles/NAME.md
       per-kernel call count and average/total duration from a
       `rocprofv3 --kernel-trace --stats --output-format csv` run.
+  python -m paper_2501_14534_amd.profiling counters DIR --kernel K --workload W --cmd "..."
+      [--json profiles/pmc_valu_lds.json] [--out profiles/NAME.md]
+      VALU busy and utilisation, LDS utilisation, LDS bank conflicts and LDS bytes per launch of
+      kernel K from a `rocprofv3 --pmc VALUBusy VALUUtilization LdsUtil LdsBankConflict
+      SQ_INSTS_LDS_LOAD_BANDWIDTH SQ_INSTS_LDS_STORE_BANDWIDTH` run (median over dispatches).
   python -m paper_2501_14534_amd.profiling traffic FETCH_DIR WRITE_DIR --kernel K --workload W
       --copy-bytes B --cmd "..." [--json profiles/pmc_traffic.json] [--key NAME] [--out profiles/NAME.md]
       HBM bytes per launch of kernel K from two `--pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs
@@ -48,6 +53,22 @@ def launch_shapes(d):
             for r in csv.DictReader(fh):
                 grid = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
                 out[(r["Kernel_Name"], grid)].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    return out
+
+
+def counter_table(d):
+    """{kernel name: [{counter: value} per dispatch]} (values summed over a counter's instances)."""
+    per = defaultdict(lambda: defaultdict(float))
+    names = {}
+    for f in _csvs(d, "counter_collection.csv"):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                did = r.get("Dispatch_Id") or r.get("Correlation_Id")
+                names[did] = r.get("Kernel_Name") or r.get("Kernel-Name")
+                per[did][r["Counter_Name"]] += float(r["Counter_Value"])
+    out = defaultdict(list)
+    for did, cs in per.items():
+        out[names[did]].append(dict(cs))
     return out
 
 
@@ -107,6 +128,43 @@ def cmd_stats(a):
     print(text)
 
 
+def cmd_counters(a):
+    table = counter_table(a.dir)
+    rows = [r for k, rs in table.items() if a.kernel in k for r in rs]
+    if not rows:
+        sys.exit(f"no dispatches of {a.kernel} in {a.dir}")
+
+    def med(name):
+        vals = [r[name] for r in rows if name in r]
+        return statistics.median(vals) if vals else None
+
+    lds_units = [(r.get("SQ_INSTS_LDS_LOAD_BANDWIDTH", 0.0) + r.get("SQ_INSTS_LDS_STORE_BANDWIDTH", 0.0)) for r in rows]
+    entry = dict(kernel=a.kernel, workload=a.workload, source_hash=kernel_source_hash(), dispatches=len(rows),
+                 valu_busy=med("VALUBusy"), valu_utilization=med("VALUUtilization"), lds_util=med("LdsUtil"),
+                 lds_bank_conflict_per_access=med("LdsBankConflict"),
+                 lds_bytes_per_launch=64.0 * statistics.median(lds_units), command=a.cmd)
+    if a.json:
+        d = json.load(open(a.json)) if os.path.exists(a.json) else {}
+        d[f"{a.key or a.kernel}@{a.workload}"] = entry
+        with open(a.json, "w") as f:
+            json.dump(d, f, indent=1, sort_keys=True)
+    text = "\n".join([
+        f"# VALU and LDS counters of `{a.kernel}` ({a.workload})", "", "Command:", "", "```", a.cmd, "```", "",
+        f"Median over {len(rows)} dispatches (percentages as rocprofv3's derived metrics define them):", "",
+        f"- VALUBusy (share of the kernel's GPU cycles with VALU instructions issued, per CU): "
+        f"{entry['valu_busy']:.2f} %",
+        f"- VALUUtilization (active lanes per VALU instruction, of 64): {entry['valu_utilization']:.2f} %",
+        f"- LdsUtil (share of cycles the LDS serves indexed accesses, per CU): {entry['lds_util']:.2f} %",
+        f"- LdsBankConflict (bank-conflict cycles per LDS access cycle): {entry['lds_bank_conflict_per_access']:.4f}",
+        f"- LDS bytes per launch (load + store bandwidth counters x 64 B; a broadcast read counts once per "
+        f"active lane): {entry['lds_bytes_per_launch']:.4e}",
+        f"- kernel source hash: {entry['source_hash']}", ""])
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write(text)
+    print(text)
+
+
 def cmd_traffic(a):
     fetch = counter_values(a.fetch_dir)
     write = counter_values(a.write_dir)
@@ -152,6 +210,14 @@ def main(argv=None):
     s.add_argument("--title", default="")
     s.add_argument("--out")
     s.add_argument("--top", type=int, default=25)
+    c = sub.add_parser("counters")
+    c.add_argument("dir")
+    c.add_argument("--kernel", required=True, help="substring of the kernel name, e.g. 'render_fwd_kernel<1, true, 0>'")
+    c.add_argument("--key", default=None, help="name under which --json files the entry (default: --kernel)")
+    c.add_argument("--workload", required=True)
+    c.add_argument("--cmd", required=True)
+    c.add_argument("--json")
+    c.add_argument("--out")
     t = sub.add_parser("traffic")
     t.add_argument("fetch_dir")
     t.add_argument("write_dir")
@@ -164,7 +230,7 @@ def main(argv=None):
     t.add_argument("--json")
     t.add_argument("--out")
     a = ap.parse_args(argv)
-    {"stats": cmd_stats, "traffic": cmd_traffic}[a.what](a)
+    {"stats": cmd_stats, "traffic": cmd_traffic, "counters": cmd_counters}[a.what](a)
 
 
 if __name__ == "__main__":
