@@ -93,7 +93,9 @@ typedef struct gs_opts {
   float bg[3];       /* background colour added with the final transmittance              */
   int32_t tile_w;    /* tile width in pixels, power of two                                 */
   int32_t tile_h;    /* tile height in pixels, power of two; tile_w*tile_h in [64, 1024]   */
-  int32_t batch_depth;       /* splats staged per tile batch, 1..GS_MAX_BATCH              */
+  int32_t batch_depth;       /* splats staged per batch, 1..GS_MAX_BATCH: per workgroup in the
+                                backward (at most 512 / waves), per wave in the forward walks
+                                (at most 64); results do not depend on it                   */
   int32_t pixels_per_thread; /* 1, 2 or 4; tile_w*tile_h/ppt a multiple of 64, <= 256      */
   int32_t subtile_cull;      /* 1: each wave walks only the splats whose alpha >= 1/255
                                 footprint can reach its pixels (same result, less work); 0: off */

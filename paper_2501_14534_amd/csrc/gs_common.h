@@ -119,6 +119,14 @@ __device__ __forceinline__ float wave_sum_lane63(float v) {
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// The wave's earlier LDS writes are visible to all its lanes' later LDS
+// accesses (and its earlier reads are done before later writes).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Real SH basis constants (closed forms: 1/2 sqrt(15/pi) etc.), single precision.
 constexpr float kC1 = 0.48860251190291992f;   // sqrt(3/(4 pi))
 constexpr float kC2a = 1.09254843059207907f;  // 1/2 sqrt(15/pi)

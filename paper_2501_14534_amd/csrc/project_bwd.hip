@@ -105,12 +105,6 @@ __device__ __forceinline__ float acc_mul_add(float t, float a, float b) {
 constexpr int kSumWindow = 256;  // pairs per window (9 x 256 floats = 576 float4, 9 per lane)
 constexpr uint32_t kHeavyPairs = 256;
 
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 __device__ __forceinline__ void record_sums(const float* __restrict__ grad_pair, const uint8_t* __restrict__ live,
                                             uint32_t cnt, uint32_t off, float4* win4, uint32_t* livew, int lane,
                                             float out[GS_GRAD_FLOATS]) {

@@ -2,11 +2,14 @@
 //
 // One workgroup per tile (global tile ids span all views of the call),
 // launched in the heaviest-first order gs_bin_sort writes when the caller
-// asks for it.  The tile's sorted list is walked in batches of up to 256
-// splat records that the workgroup gathers into LDS; every lane then walks
-// the batch for its pixel(s), reading each record as a wave-uniform LDS
-// broadcast, the next record loaded while the current one is blended.  No
-// MFMA: the work per (pixel, splat) pair is ~20 VALU operations and one exp.
+// asks for it; each wave of it owns one sub-tile of pixels.  The backward
+// walks the tile's sorted list in batches of splat records that the
+// workgroup gathers into LDS together; the forward's waves walk the list
+// independently (no workgroup barrier), each staging groups of 64 records
+// into its own LDS with the gathers issued two groups ahead.  Every lane
+// walks the staged records for its pixel(s), reading each as a wave-uniform
+// LDS broadcast.  No MFMA: the work per (pixel, splat) pair is ~20 VALU
+// operations and one exp.
 //
 // Sub-tile culling (CULL): while staging a batch, each record's conservative
 // alpha >= 1/255 footprint (the ellipse q <= 2 ln(255 o'), widened by
@@ -17,9 +20,11 @@
 // every pixel of that wave, so the result is unchanged.
 //
 // Forward: lanes whose pixels have terminated drop out of the walk through
-// the exec mask; a wave stops walking once all its pixels are done, and
-// before each batch the waves vote and the workgroup leaves once every pixel
-// is done.  Long lists can be split into forward chunks walked in parallel
+// the exec mask, and a wave leaves once all its pixels are done; the
+// backward's waves vote before each batch and the workgroup leaves once every
+// pixel is done.  The forward evaluates four records' falloff and alpha
+// together (independent of the transmittance) before compositing them in
+// order.  Long lists can be split into forward chunks walked in parallel
 // (a product pass gives each chunk its starting transmittance; see
 // render_fwd_kernel), which shortens the critical path of the deepest tiles.
 //
@@ -305,15 +310,16 @@ __device__ __forceinline__ float reduce_scatter9(const float (&x)[GS_GRAD_FLOATS
 // fwd_combine_kernel adds them up.  The critical path of a deep tile becomes
 // about three chunks instead of its whole list.
 enum : int { kFull = 0, kCount = 1, kTPass = 2 };
+constexpr int kIlp = 4;  // records evaluated together by the forward walk
 
 template <int PPT, bool CULL, int MODE>
 __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable vt, float* __restrict__ image,
                                                          float* __restrict__ T_final, int32_t* __restrict__ last_out,
                                                          int64_t item_base) {
   constexpr bool COUNT = MODE == kCount, TPASS = MODE == kTPass;
-  extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ int s_alive[4];
-  __shared__ Box s_box[4];
+  // per wave: the staged group of records (a, b, c), and (COUNT) its hit counts
+  __shared__ float4 s_rec[4][3][kWave];
+  __shared__ uint32_t s_cnt[4][kWave];
   // Work items (blockIdx.x + item_base): [0, nfslots) are the forward chunks
   // that start at a forward boundary (slot order); the rest are each tile's
   // first chunk, in the tile schedule.  Counting launches have no chunk items.
@@ -343,16 +349,12 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable
   const uint32_t kf = (uint32_t)((cs64 - tc.start) >> lf);                           // this chunk
   if (TPASS && (kf == 0 || kf + 1 == nfc)) return;  // chunk 0 leaves its own; the last one is not needed
   const ViewArgs& va = vt.v[tc.view];
-  const int nthreads = blockDim.x;
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave, nwaves = nthreads / kWave;
-  const Lds L = lds_carve(smem, a.batch, nwaves, false);
-  float4* s_a = L.a;
-  float4* s_b = L.b;
-  float4* s_c = L.c;
-  uint8_t* s_mask = L.mask;
-  uint32_t* s_hits = (uint32_t*)L.c;  // COUNT only
-  if (COUNT)
-    for (int i = threadIdx.x; i < a.batch; i += blockDim.x) s_hits[i] = 0u;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  float4* s_a = s_rec[wave][0];
+  float4* s_b = s_rec[wave][1];
+  float4* s_c = s_rec[wave][2];
+  uint32_t* s_hits = s_cnt[wave];  // COUNT only
+  if (COUNT) s_hits[lane] = 0u;
 
   // C: colour composited so far (the image, summed in list order whatever
   // the tiling); S: colour composited since the last chunk boundary (kept
@@ -396,113 +398,106 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable
 #pragma unroll
     for (int p = 0; p < PPT; ++p) done[p] = done[p] || p0[threadIdx.x * PPT + p] < kTMin;
   }
-  int nbnd = 0;  // chunk boundaries recorded (uniform)
+  int nbnd = 0;  // chunk boundaries this wave recorded (uniform in the wave)
   // first backward boundary this walk can record: the first multiple of 2^lc
   // (relative to the list start) at or after cs, never the list start
   uint64_t b0 = (uint64_t)tc.start + ((((uint64_t)cs - tc.start) + ((1ull << lc) - 1)) >> lc << lc);
   if (b0 == (uint64_t)tc.start) b0 += 1ull << lc;
-  // batches never straddle a chunk boundary
-  auto batch_end = [&](uint32_t b) -> uint32_t {
+  // Each wave walks its own sub-tile independently (no workgroup barrier), in
+  // groups of up to 64 entries (batch_depth if smaller) that never straddle a
+  // chunk boundary: lane l stages entry l of the group into the wave's LDS,
+  // with its culling bit for the wave's live box.  Software-pipelined gather,
+  // two groups deep (late in a deep list most records are culled, and a
+  // group's walk is shorter than a gather's latency): while group g is walked,
+  // lane l holds the record of entry l of group g + 1 and has those of group
+  // g + 2 in flight, and the id of entry l of group g + 3.
+  const uint32_t G = (uint32_t)min(kWave, a.batch);
+  auto group_end = [&](uint32_t b) -> uint32_t {
     const uint64_t rel = b - tc.start;
     const uint64_t next = (uint64_t)tc.start + (((rel >> lc) + 1) << lc);
-    return (uint32_t)min(min((uint64_t)ce, (uint64_t)b + (uint64_t)a.batch), next);
+    return (uint32_t)min(min((uint64_t)ce, (uint64_t)b + G), next);
   };
-  // Software-pipelined gather: while a batch is walked, thread t holds the
-  // record of entry t of the next batch (loads in flight) and the id of entry
-  // t of the batch after it.
-  const int t = threadIdx.x;
-  uint32_t bs = cs;
-  uint32_t be = bs < ce ? batch_end(bs) : bs;
-  uint32_t be2 = be < ce ? batch_end(be) : be;
-  float4 pa = make_float4(0.f, 0.f, 0.f, 0.f), pb = pa, pc = pa;
-  uint32_t nid = 0;
-  if (bs + t < be) {
-    const uint32_t rec = a.ids[bs + t];
-    pa = a.splats[(size_t)rec * 3 + 0];
-    pb = a.splats[(size_t)rec * 3 + 1];
-    if (!COUNT) pc = a.splats[(size_t)rec * 3 + 2];
+  uint32_t gs = cs;                                // group g: [gs, ge)
+  uint32_t ge = gs < ce ? group_end(gs) : gs;      // g + 1: [ge, ge2)
+  uint32_t ge2 = ge < ce ? group_end(ge) : ge;     // g + 2: [ge2, ge3)
+  uint32_t ge3 = ge2 < ce ? group_end(ge2) : ge2;  // g + 3: [ge3, ge4)
+  const float4 zf4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  float4 pa = zf4, pb = zf4, pc = zf4, qa = zf4, qb = zf4, qc = zf4;
+  uint32_t cid = 0, qid = 0, nid = 0;  // ids of entry `lane` of groups g, g + 1, g + 2 (then g + 3)
+  if (gs + lane < ge) {
+    cid = a.ids[gs + lane];
+    pa = a.splats[(size_t)cid * 3 + 0];
+    pb = a.splats[(size_t)cid * 3 + 1];
+    if (!COUNT) pc = a.splats[(size_t)cid * 3 + 2];
   }
-  if (be + t < be2) nid = a.ids[be + t];
-  while (bs < ce) {
+  if (ge + lane < ge2) {
+    qid = a.ids[ge + lane];
+    qa = a.splats[(size_t)qid * 3 + 0];
+    qb = a.splats[(size_t)qid * 3 + 1];
+    if (!COUNT) qc = a.splats[(size_t)qid * 3 + 2];
+  }
+  if (ge2 + lane < ge3) nid = a.ids[ge2 + lane];
+  while (gs < ce) {
     bool alive = false, live[PPT];
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
       live[p] = !done[p];
       alive |= live[p];
     }
-    const uint64_t vote = __ballot(alive);
-    if (CULL) {
-      const Box b = live_box<PPT>(px, py, live);
-      if (lane == 0) s_box[wave] = b;
-    }
-    if (lane == 0) s_alive[wave] = vote != 0;
-    __syncthreads();  // also: every wave has finished walking the previous batch
-    int any = 0;
-    for (int w = 0; w < nwaves; ++w) any |= s_alive[w];
-    if (!any) break;
-    const uint64_t rel = bs - tc.start;
+    if (__ballot(alive) == 0) break;  // every pixel of this wave has stopped
+    const uint64_t rel = gs - tc.start;
     if (MODE == kFull && rel != 0 && (rel & ((1ull << lc) - 1)) == 0) {
       // a chunk boundary of the backward: record each pixel's transmittance
       // here and the colour of the chunk that ends here, then start a new chunk
-      const int64_t slot = (int64_t)(bs >> lc);
+      const int64_t slot = (int64_t)(gs >> lc);
       float4* st = a.state + slot * tpx;
 #pragma unroll
       for (int p = 0; p < PPT; ++p) {
         st[threadIdx.x * PPT + p] = make_float4(T[p], S0[p], S1[p], S2[p]);
         S0[p] = S1[p] = S2[p] = 0.0f;
       }
-      if (threadIdx.x == 0) a.slot_owner[slot] = (uint32_t)gtile;
+      if (lane == 0) a.slot_owner[slot] = (uint32_t)gtile;  // every wave that gets here writes the same
       ++nbnd;
     }
-    const int cnt = (int)(be - bs);
-    if (t < cnt) {  // entry t from the registers
-      s_a[t] = staged_a(pa);
-      s_b[t] = staged_b(pb);
-      if (!COUNT) s_c[t] = pc;
-      if (CULL) s_mask[t] = (uint8_t)footprint_mask(pa, pb, nwaves, s_box);
+    const int cnt = (int)(ge - gs);
+    Box box;
+    if (CULL) box = live_box<PPT>(px, py, live);  // all lanes: a cross-lane reduction
+    bool bit = lane < cnt;
+    if (bit) {  // entry `lane` from the registers
+      s_a[lane] = staged_a(pa);
+      s_b[lane] = staged_b(pb);
+      if (!COUNT) s_c[lane] = pc;
+      if (CULL) bit = footprint_mask(pa, pb, 1, &box) != 0u;
     }
-    for (int i = t + nthreads; i < cnt; i += nthreads) {  // batches deeper than the workgroup
-      const uint32_t rec = a.ids[bs + i];
-      const float4 ra = a.splats[(size_t)rec * 3 + 0];
-      const float4 rb = a.splats[(size_t)rec * 3 + 1];
-      s_a[i] = staged_a(ra);
-      s_b[i] = staged_b(rb);
-      if (!COUNT) s_c[i] = a.splats[(size_t)rec * 3 + 2];
-      if (CULL) s_mask[i] = (uint8_t)footprint_mask(ra, rb, nwaves, s_box);
+    const uint32_t gid = cid;
+    // rotate: group g + 1 moves up; issue group g + 2's record loads and
+    // group g + 3's id loads
+    const uint32_t ge4 = ge3 < ce ? group_end(ge3) : ge3;
+    pa = qa, pb = qb, pc = qc, cid = qid;
+    qid = nid;
+    if (ge2 + lane < ge3) {
+      qa = a.splats[(size_t)qid * 3 + 0];
+      qb = a.splats[(size_t)qid * 3 + 1];
+      if (!COUNT) qc = a.splats[(size_t)qid * 3 + 2];
     }
-    // issue the next batch's record loads and the following batch's id loads
-    const uint32_t be3 = be2 < ce ? batch_end(be2) : be2;
-    if (be + t < be2) {
-      pa = a.splats[(size_t)nid * 3 + 0];
-      pb = a.splats[(size_t)nid * 3 + 1];
-      if (!COUNT) pc = a.splats[(size_t)nid * 3 + 2];
-    }
-    nid = be2 + t < be3 ? a.ids[be2 + t] : 0u;
-    __syncthreads();
-    const int nchunks = (cnt + kWave - 1) / kWave;
-    for (int c = 0; c < nchunks; ++c) {
-      bool live = false;
-#pragma unroll
-      for (int p = 0; p < PPT; ++p) live |= !done[p];
-      if (__ballot(live) == 0) break;  // every pixel of this wave has stopped
-      uint64_t m = chunk_bits<CULL>(s_mask, c, cnt, wave, lane);
-      if (m == 0) continue;
-      // blend one staged record into this lane's pixel(s); branch-free: a lane
-      // that skips the splat adds exact zeros
-      auto blend = [&](int j, const float4& ra, const float4& rb, const float4& rc) {
-        const int idx = (int)(bs + j - tc.start) + 1;
+    nid = ge3 + lane < ge4 ? a.ids[ge3 + lane] : 0u;
+    wave_lds_sync();  // the staged group is visible to the whole wave
+    uint64_t m = __ballot(bit);
+    if (m != 0) {
+      // composite one evaluated record into this lane's pixel(s); branch-free: a
+      // lane that skips the splat adds exact zeros
+      auto composite = [&](int j, const Eval (&e)[PPT], const bool (&inside)[PPT], const float4& rc) {
+        const int idx = (int)(gs + j - tc.start) + 1;
         uint32_t taken = 0;  // COUNT: pixels of this wave that composite record j
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
-          Eval e;
-          const bool inside = eval_splat_all(px[p], py[p], ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, &e);
-          const bool use = !done[p] && inside && !(e.alpha < kAlphaMin);
-          const float Tn = T[p] * (1.0f - e.alpha);
+          const bool use = !done[p] && inside[p] && !(e[p].alpha < kAlphaMin);
+          const float Tn = T[p] * (1.0f - e[p].alpha);
           const bool stop = use && Tn < kTMin;  // stop before this splat
           done[p] = done[p] || stop;
           // the product pass multiplies the stopping splat in as well
           const bool take = TPASS ? use : use && !stop;
-          const float w = take ? e.alpha * T[p] : 0.0f;
+          const float w = take ? e[p].alpha * T[p] : 0.0f;
           C0[p] += rc.x * w;
           C1[p] += rc.y * w;
           C2[p] += rc.z * w;
@@ -513,43 +508,51 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable
           last[p] = take ? idx : last[p];
           if (COUNT) taken += (uint32_t)__popcll(__ballot(take));
         }
-        if (COUNT && lane == 0 && taken != 0) atomicAdd(s_hits + j, taken);
+        if (COUNT && lane == 0 && taken != 0) s_hits[j] += taken;
       };
-      // two register sets in turn: the next record loads while this one blends
+      // Four records at a time (in list order): their falloff and alpha do not
+      // depend on the transmittance, so the four evaluations run as independent
+      // chains before the four dependent compositing steps.
       const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
-      int j0 = c * kWave + __builtin_ctzll(m);
-      m &= m - 1;
-      float4 a0 = s_a[j0], b0 = s_b[j0], c0 = COUNT ? zero4 : s_c[j0];
-      for (;;) {
-        const bool more1 = m != 0;
-        const int j1 = more1 ? c * kWave + __builtin_ctzll(m) : j0;
-        m &= m - 1;
-        const float4 a1 = s_a[j1], b1 = s_b[j1], c1 = COUNT ? zero4 : s_c[j1];
-        blend(j0, a0, b0, c0);
-        if (!more1) break;
-        const bool more2 = m != 0;
-        j0 = more2 ? c * kWave + __builtin_ctzll(m) : j1;
-        m &= m - 1;
-        a0 = s_a[j0], b0 = s_b[j0], c0 = COUNT ? zero4 : s_c[j0];
-        blend(j1, a1, b1, c1);
-        if (!more2) break;
+      while (m != 0) {
+        int jq[kIlp];
+        bool vq[kIlp];
+#pragma unroll
+        for (int q = 0; q < kIlp; ++q) {
+          vq[q] = m != 0;
+          jq[q] = vq[q] ? __builtin_ctzll(m) : jq[0];
+          m &= m - 1;
+        }
+        float4 rcq[kIlp];
+        Eval eq[kIlp][PPT];
+        bool iq[kIlp][PPT];
+#pragma unroll
+        for (int q = 0; q < kIlp; ++q) {
+          const float4 ra = s_a[jq[q]], rb = s_b[jq[q]];
+          rcq[q] = COUNT ? zero4 : s_c[jq[q]];
+#pragma unroll
+          for (int p = 0; p < PPT; ++p)
+            iq[q][p] = eval_splat_all(px[p], py[p], ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, &eq[q][p]);
+        }
+#pragma unroll
+        for (int q = 0; q < kIlp; ++q)
+          if (vq[q]) composite(jq[q], eq[q], iq[q], rcq[q]);  // wave-uniform
       }
-    }
-    if (COUNT) {
-      // flush the batch's counters (each thread clears the ones it reads; the
-      // next batch's additions start after the next loop-top barrier)
-      __syncthreads();
-      for (int i = t; i < cnt; i += nthreads) {
-        const uint32_t h = s_hits[i];
+      if (COUNT) {
+        // flush the group's counters: lane l adds entry l's hits to its Gaussian
+        wave_lds_sync();
+        const uint32_t h = lane < cnt ? s_hits[lane] : 0u;
         if (h != 0) {
-          atomicAdd(a.hits + ((int64_t)a.ids[bs + i] - (int64_t)tc.view * a.n), h);
-          s_hits[i] = 0u;
+          atomicAdd(a.hits + ((int64_t)gid - (int64_t)tc.view * a.n), h);
+          s_hits[lane] = 0u;
         }
       }
     }
-    bs = be;
-    be = be2;
-    be2 = be3;
+    wave_lds_sync();  // every lane has read the group before the next one overwrites it
+    gs = ge;
+    ge = ge2;
+    ge2 = ge3;
+    ge3 = ge4;
   }
 
   if (COUNT) return;
@@ -874,12 +877,14 @@ __global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs a, ViewTable
         const int j1 = more1 ? c * kWave + (63 - __builtin_clzll(m)) : j0;
         m &= ~(1ull << (j1 - c * kWave));
         const float4 a1 = s_a[j1], b1 = s_b[j1], c1 = s_c[j1];
+        __builtin_amdgcn_sched_barrier(0);  // keep those loads ahead of this record's work
         grad(j0, a0, b0, c0);
         if (!more1) break;
         const bool more2 = m != 0;
         j0 = more2 ? c * kWave + (63 - __builtin_clzll(m)) : j1;
         m &= ~(1ull << (j0 - c * kWave));
         a0 = s_a[j0], b0 = s_b[j0], c0 = s_c[j0];
+        __builtin_amdgcn_sched_barrier(0);
         grad(j1, a1, b1, c1);
         if (!more2) break;
       }
@@ -907,12 +912,11 @@ static void walk(const RenderArgs& a, const ViewTable& vt, float* image, float* 
   if (items <= 0) return;
   const int nt = tile_threads(a);
   const dim3 grid((unsigned)items), block((unsigned)nt);
-  const size_t sh = lds_bytes(a.batch, nt / kWave, false);
   if (a.cull)
-    hipLaunchKernelGGL((render_fwd_kernel<PPT, true, MODE>), grid, block, sh, s, a, vt, image, T_final, last,
+    hipLaunchKernelGGL((render_fwd_kernel<PPT, true, MODE>), grid, block, 0, s, a, vt, image, T_final, last,
                        item_base);
   else
-    hipLaunchKernelGGL((render_fwd_kernel<PPT, false, MODE>), grid, block, sh, s, a, vt, image, T_final, last,
+    hipLaunchKernelGGL((render_fwd_kernel<PPT, false, MODE>), grid, block, 0, s, a, vt, image, T_final, last,
                        item_base);
 }
 
