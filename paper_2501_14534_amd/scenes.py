@@ -105,10 +105,10 @@ class Opts:
     bg: Tuple[float, float, float] = (0.0, 0.0, 0.0)
     tile_w: int = 16
     tile_h: int = 16
-    batch_depth: int = 256
+    batch_depth: int = 128
     pixels_per_thread: int = 1
     subtile_cull: int = 1
-    bwd_chunk: int = 1024  # list entries per backward work item (0: one per tile)
+    bwd_chunk: int = 512  # list entries per backward work item (0: one per tile)
     fwd_chunk: int = 0     # list entries per forward work item (0: one per tile)
     lowpass_progressive: int = 0  # 1: per view s = max(lowpass, H W / (9 pi N)) (Sec. 3.2.4)
 
