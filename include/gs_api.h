@@ -183,13 +183,20 @@ typedef struct gs_grads {
   int32_t assign;
 } gs_grads;
 
-/* Number of tiles and pixels of V views under `opts` (host only). */
+/* Number of tiles and pixels of V views under `opts` (host only): the tile
+ * grid of the binning rule (each view is cut into ceil(W / tile_w) x
+ * ceil(H / tile_h) tiles, views in call order), the sizes a caller needs for
+ * the ranges, order, image, T_final and last_contrib arrays.  GS_E_INVALID on
+ * a bad camera or option. */
 int gs_view_sizes(const gs_camera* cams, int32_t V, const gs_opts* opts, int64_t* total_tiles,
                   int64_t* total_pixels);
 
 /* Bytes of the one workspace buffer that gs_bin_sort, gs_render_fwd and
  * gs_render_bwd (or gs_blend_bwd + gs_project_bwd) share for n Gaussians, V
- * views and a list capacity (host only; 0 on invalid input).  gs_bin_sort
+ * views and a list capacity (host only; 0 on invalid input): the scratch of
+ * the depth sort and the tile sort that order each tile's list as Eq. 2's
+ * front-to-back composite needs, and the per-chunk pixel states and per-pair
+ * gradients of the backward of Eq. 2.  gs_bin_sort
  * uses it as scratch; gs_render_fwd writes the per-chunk pixel states there,
  * and the backward of the same step reads them, so the buffer must not be
  * reused for anything else between the forward and the backward. */
@@ -205,12 +212,22 @@ size_t gs_workspace_size(int64_t n, int32_t V, const gs_camera* cams, const gs_o
 int gs_project(const gs_gaussians* g, const gs_camera* cams, int32_t V, const gs_opts* opts,
                gs_projected* out, gs_stream_t stream);
 
-/* Tile binning and ordering of the records of a gs_project call: device-wide
- * scans of tiles_touched, a stable LSD radix sort of the visible records by
- * their depth bits, emission of one pair per touched tile in that order, a
- * stable LSD radix sort of the pairs by tile id (together: the order of keys
- * then ids described above), per-tile ranges and, if order is given, the
- * heaviest-first tile schedule.  Needs ws_bytes >= gs_workspace_size(...). */
+/* Tile binning and ordering of the records of a gs_project call, which gives
+ * every tile the depth-ordered list that the front-to-back composite of Eq. 2
+ * walks (Sec. 3.1).  Binning rule: a record touches the tiles of the rectangle
+ * [floor((u - r) / tile_w), floor((u + r) / tile_w)] x [same for v and tile_h],
+ * clipped to the view, with u - r and u + r single-precision operations; this
+ * rectangle holds every pixel centre inside the record's square (the square
+ * test of gs_render_fwd), so the lists do not change the image.  Order: by
+ * (global tile, depth) with ties in depth broken by record id, so the order is
+ * unique.  Implementation: device-wide scans of tiles_touched, a stable LSD
+ * radix sort of the visible records by their depth bits, emission of one pair
+ * per touched tile in that order, a stable LSD radix sort of the pairs by tile
+ * id (together: the order of keys then ids described above), per-tile ranges
+ * and, if order is given, the heaviest-first tile schedule.  Returns
+ * GS_E_INVALID (nothing enqueued) on null pointers, a misaligned or short
+ * workspace, V * n >= 2^32 or capacity >= 2^32; capacity overflow is reported
+ * through *status.  Needs ws_bytes >= gs_workspace_size(...). */
 int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int32_t V, int64_t n, const gs_opts* opts,
                 gs_binning* out, void* ws, size_t ws_bytes, gs_stream_t stream);
 

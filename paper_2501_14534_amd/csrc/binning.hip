@@ -529,18 +529,35 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter(const uint32_t* __
   }
 }
 
-// Per sorted pair: [start, end) of its tile's run and, if asked for, the 64-bit key.
+// Per sorted pair: [start, end) of its tile's run and, if asked for, the
+// 64-bit key.  Each thread takes 4 consecutive pairs (one 16-byte load; the
+// key arrays are 256-byte aligned) and compares them with their neighbours.
 __global__ void tile_ranges(const uint32_t* __restrict__ tkey, const uint32_t* __restrict__ ids,
                             const uint32_t* __restrict__ drec, const uint32_t* __restrict__ count,
                             const int32_t* __restrict__ status, uint64_t* __restrict__ keys,
                             uint32_t* __restrict__ ranges) {
   const uint32_t K = effective_count(count, status);
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= K) return;
-  const uint32_t t = tkey[i];
-  if (keys) keys[i] = ((uint64_t)t << 32) | drec[ids[i]];
-  if (i == 0 || tkey[i - 1] != t) ranges[2 * (int64_t)t] = (uint32_t)i;
-  if (i == (int64_t)K - 1 || tkey[i + 1] != t) ranges[2 * (int64_t)t + 1] = (uint32_t)(i + 1);
+  const int64_t i0 = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+  if (i0 >= K) return;
+  uint32_t t[6];  // pairs i0 - 1 .. i0 + 4 (outside [0, K): no tile)
+  if (i0 + 4 <= (int64_t)K) {
+    const uint4 q = *(const uint4*)(tkey + i0);
+    t[1] = q.x, t[2] = q.y, t[3] = q.z, t[4] = q.w;
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) t[1 + j] = i0 + j < (int64_t)K ? tkey[i0 + j] : 0xffffffffu;
+  }
+  t[0] = i0 > 0 ? tkey[i0 - 1] : 0xffffffffu;
+  t[5] = i0 + 4 < (int64_t)K ? tkey[i0 + 4] : 0xffffffffu;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int64_t i = i0 + j;
+    if (i >= (int64_t)K) break;
+    const uint32_t c = t[1 + j];
+    if (keys) keys[i] = ((uint64_t)c << 32) | drec[ids[i]];
+    if (t[j] != c) ranges[2 * (int64_t)c] = (uint32_t)i;
+    if (t[2 + j] != c) ranges[2 * (int64_t)c + 1] = (uint32_t)(i + 1);
+  }
 }
 
 // Heaviest-first tile schedule: tiles grouped by the bit length of their list
@@ -736,7 +753,7 @@ hipError_t launch_bin_sort(const SortPlan& plan, const float4* splats, const uin
       radix_sort<uint32_t, 2>(w.tkey_alt, w.tval_alt, w.trec_alt, w.tkey, out.pair_index, out.ids, plan.tile_passes,
                               count, status, plan.sort_blocks, w, s);
   }
-  const int64_t cap_blocks = ((int64_t)capacity + 255) / 256;
+  const int64_t cap_blocks = ((int64_t)capacity + 1023) / 1024;
   if (cap_blocks > 0 && nb > 0)
     hipLaunchKernelGGL(tile_ranges, dim3((unsigned)cap_blocks), dim3(256), 0, s, w.tkey, out.ids, w.drec, count,
                        status, out.keys, out.ranges);
