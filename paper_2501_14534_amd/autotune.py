@@ -29,6 +29,7 @@ CANDIDATES: List[Tuple[int, int, int, int, int]] = [
     (16, 16, 128, 1, 1), (16, 16, 128, 1, 0), (16, 16, 64, 1, 1), (16, 16, 32, 1, 1),
     (16, 16, 128, 2, 1), (16, 16, 64, 2, 1), (16, 16, 64, 4, 1),
     (8, 8, 64, 1, 1), (16, 8, 128, 1, 1), (16, 8, 64, 2, 1), (32, 8, 128, 1, 1), (32, 16, 128, 2, 1),
+    (32, 16, 64, 2, 1), (32, 16, 128, 4, 1), (32, 32, 128, 4, 1), (64, 16, 128, 4, 1),
 ]
 # list entries per backward work item (0: one item per tile)
 CHUNKS: List[int] = [256, 512, 1024, 2048, 0]

@@ -30,7 +30,9 @@ def test_tune_writes_a_winner_with_the_same_image(tmp_path):
     best = res["best"]
     assert best["source_hash"] == autotune.kernel_source_hash()
     assert len(res["results"]) >= 5
-    assert all(x["image_ok"] for x in res["results"] if x["fwd_chunk"] == 0)  # every tiling: the same bits
+    # every unchunked forward gives the same bits (forward chunks may round further off and be rejected)
+    assert all(x["image_ok"] for x in res["results"] if x["fwd_chunk"] == 0), \
+        [(x["tile_w"], x["tile_h"], x["bwd_chunk"], x["image_max_abs_diff"]) for x in res["results"]]
     opts = autotune.best_opts(wl, cache_path=cache)
     for k in ("tile_w", "tile_h", "batch_depth", "pixels_per_thread", "subtile_cull", "bwd_chunk", "fwd_chunk"):
         assert getattr(opts, k) == best[k], k

@@ -83,7 +83,8 @@ def test_tile_batch_and_ppt_do_not_change_the_image(P):
     for tw, th, bd, ppt, cull in [(8, 8, 64, 1, 1), (32, 8, 256, 1, 1), (16, 16, 17, 1, 1), (16, 16, 1, 1, 1),
                                   (16, 16, 256, 1, 0), (16, 16, 96, 1, 0), (16, 16, 256, 2, 1), (16, 16, 100, 4, 1),
                                   (16, 16, 64, 4, 0), (32, 16, 256, 2, 1), (16, 32, 128, 4, 1), (64, 4, 256, 1, 1),
-                                  (16, 16, 1024, 1, 1), (16, 16, 600, 1, 0)]:
+                                  (16, 16, 1024, 1, 1), (16, 16, 600, 1, 0), (32, 16, 128, 4, 1), (32, 32, 128, 4, 1),
+                                  (64, 16, 128, 4, 1)]:
         o = dataclasses.replace(wl.opts, tile_w=tw, tile_h=th, batch_depth=bd, pixels_per_thread=ppt,
                                 subtile_cull=cull)
         r, _, g = _run(P, wl, o)
