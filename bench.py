@@ -80,8 +80,8 @@ def load_counters(kernel: str, workload: str, src_hash: str):
     try:
         e = json.load(open(p)).get(f"{kernel}@{workload}")
         if e and e.get("source_hash") == src_hash:
-            return {k: e[k] for k in ("valu_busy", "valu_utilization", "lds_util", "lds_bank_conflict_per_access",
-                                      "lds_bytes_per_launch") if k in e}
+            return {k: e[k] for k in ("valu_insts_per_simd_cycle", "valu_issue_frac_fp32", "valu_insts_per_wave",
+                                      "lds_util", "lds_bank_conflict_per_access", "lds_bytes_per_launch") if k in e}
     except (ValueError, KeyError, TypeError):
         return None
     return None

@@ -3,11 +3,14 @@
   python -m paper_2501_14534_amd.profiling stats DIR --cmd "..." --out profiles/NAME.md
       per-kernel call count and average/total duration from a
       `rocprofv3 --kernel-trace --stats --output-format csv` run.
-  python -m paper_2501_14534_amd.profiling counters DIR --kernel K --workload W --cmd "..."
-      [--json profiles/pmc_valu_lds.json] [--out profiles/NAME.md]
-      VALU busy and utilisation, LDS utilisation, LDS bank conflicts and LDS bytes per launch of
-      kernel K from a `rocprofv3 --pmc VALUBusy VALUUtilization LdsUtil LdsBankConflict
-      SQ_INSTS_LDS_LOAD_BANDWIDTH SQ_INSTS_LDS_STORE_BANDWIDTH` run (median over dispatches).
+  python -m paper_2501_14534_amd.profiling counters DIR --issue-dir IDIR --stats-dir SDIR --kernel K
+      --workload W --cmd "..." [--json profiles/pmc_valu_lds.json] [--out profiles/NAME.md]
+      LDS utilisation, LDS bank conflicts and LDS bytes per launch of kernel K from a `rocprofv3 --pmc
+      VALUBusy VALUUtilization LdsUtil LdsBankConflict SQ_INSTS_LDS_LOAD_BANDWIDTH
+      SQ_INSTS_LDS_STORE_BANDWIDTH` run (DIR), and its VALU and LDS instruction issue from a raw
+      `--pmc SQ_INSTS_VALU SQ_INSTS_LDS SQ_WAVES ...` run (IDIR) over the kernel's average duration
+      in a `--kernel-trace --stats` run (SDIR); medians over dispatches.  rocprofv3's derived
+      VALUBusy and VALUUtilization read above 100 % on this chip and are not used.
   python -m paper_2501_14534_amd.profiling traffic FETCH_DIR WRITE_DIR --kernel K --workload W
       --copy-bytes B --cmd "..." [--json profiles/pmc_traffic.json] [--key NAME] [--out profiles/NAME.md]
       HBM bytes per launch of kernel K from two `--pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs
@@ -100,6 +103,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+CLOCK_HZ = 2.4e9  # MI355X peak engine clock
+SIMDS = 256 * 4  # 256 compute units of 4 SIMDs
+FP32_VALU_ISSUE_PER_SIMD_CYCLE = 0.25  # one wave64 FP32 FMA per 4 cycles on a 16-lane SIMD
+
+
 def _match(values, pattern):
     return {k: v for k, v in values.items() if pattern in k}
 
@@ -139,21 +147,41 @@ def cmd_counters(a):
         return statistics.median(vals) if vals else None
 
     lds_units = [(r.get("SQ_INSTS_LDS_LOAD_BANDWIDTH", 0.0) + r.get("SQ_INSTS_LDS_STORE_BANDWIDTH", 0.0)) for r in rows]
+    # raw issue counters over the kernel's average duration
+    irows = [r for k, rs in counter_table(a.issue_dir).items() if a.kernel in k for r in rs]
+    durs = [r["avg_ns"] for r in kernel_stats(a.stats_dir) if a.kernel in r["name"]]
+    if not irows or not durs:
+        sys.exit(f"no issue counters ({len(irows)}) or duration ({len(durs)}) for {a.kernel}")
+
+    def imed(name):
+        return statistics.median([r[name] for r in irows])
+
+    cycles = durs[0] * 1e-9 * CLOCK_HZ
+    waves, valu, lds = imed("SQ_WAVES"), imed("SQ_INSTS_VALU"), imed("SQ_INSTS_LDS")
+    valu_rate = valu / (cycles * SIMDS)
     entry = dict(kernel=a.kernel, workload=a.workload, source_hash=kernel_source_hash(), dispatches=len(rows),
-                 valu_busy=med("VALUBusy"), valu_utilization=med("VALUUtilization"), lds_util=med("LdsUtil"),
-                 lds_bank_conflict_per_access=med("LdsBankConflict"),
-                 lds_bytes_per_launch=64.0 * statistics.median(lds_units), command=a.cmd)
+                 waves=waves, valu_insts_per_wave=valu / waves, lds_insts_per_wave=lds / waves,
+                 ms_per_launch=durs[0] * 1e-6, valu_insts_per_simd_cycle=valu_rate,
+                 valu_issue_frac_fp32=valu_rate / FP32_VALU_ISSUE_PER_SIMD_CYCLE,
+                 lds_util=med("LdsUtil"), lds_bank_conflict_per_access=med("LdsBankConflict"),
+                 lds_bytes_per_launch=64.0 * statistics.median(lds_units), command=a.cmd,
+                 issue_command=a.issue_cmd)
     if a.json:
         d = json.load(open(a.json)) if os.path.exists(a.json) else {}
         d[f"{a.key or a.kernel}@{a.workload}"] = entry
         with open(a.json, "w") as f:
             json.dump(d, f, indent=1, sort_keys=True)
     text = "\n".join([
-        f"# VALU and LDS counters of `{a.kernel}` ({a.workload})", "", "Command:", "", "```", a.cmd, "```", "",
-        f"Median over {len(rows)} dispatches (percentages as rocprofv3's derived metrics define them):", "",
-        f"- VALUBusy (share of the kernel's GPU cycles with VALU instructions issued, per CU): "
-        f"{entry['valu_busy']:.2f} %",
-        f"- VALUUtilization (active lanes per VALU instruction, of 64): {entry['valu_utilization']:.2f} %",
+        f"# VALU and LDS counters of `{a.kernel}` ({a.workload})", "", "Commands (LDS pass, then raw issue pass):",
+        "", "```", a.cmd, a.issue_cmd, "```", "",
+        f"Medians over {len(rows)} dispatches; durations from the `--kernel-trace --stats` run of the same "
+        f"workload ({entry['ms_per_launch']:.4f} ms per launch), at {CLOCK_HZ / 1e9:.1f} GHz on {SIMDS} SIMDs:", "",
+        f"- waves per launch: {waves:.0f}; VALU instructions per wave: {entry['valu_insts_per_wave']:.0f}; "
+        f"LDS instructions per wave: {entry['lds_insts_per_wave']:.0f}",
+        f"- VALU instructions issued per SIMD per cycle: {valu_rate:.4f}; a wave64 FP32 FMA holds a 16-lane SIMD "
+        f"for 4 cycles, so full-rate FP32 issue is {FP32_VALU_ISSUE_PER_SIMD_CYCLE} per SIMD-cycle: "
+        f"{entry['valu_issue_frac_fp32']:.3f} of it (above 1 where part of the mix, such as moves, selects and "
+        f"compares, issues faster than a full-rate FP32 operation)",
         f"- LdsUtil (share of cycles the LDS serves indexed accesses, per CU): {entry['lds_util']:.2f} %",
         f"- LdsBankConflict (bank-conflict cycles per LDS access cycle): {entry['lds_bank_conflict_per_access']:.4f}",
         f"- LDS bytes per launch (load + store bandwidth counters x 64 B; a broadcast read counts once per "
@@ -212,6 +240,9 @@ def main(argv=None):
     s.add_argument("--top", type=int, default=25)
     c = sub.add_parser("counters")
     c.add_argument("dir")
+    c.add_argument("--issue-dir", required=True, help="raw --pmc SQ_INSTS_VALU SQ_INSTS_LDS SQ_WAVES ... run")
+    c.add_argument("--issue-cmd", required=True)
+    c.add_argument("--stats-dir", required=True, help="--kernel-trace --stats run of the same workload")
     c.add_argument("--kernel", required=True, help="substring of the kernel name, e.g. 'render_fwd_kernel<1, true, 0>'")
     c.add_argument("--key", default=None, help="name under which --json files the entry (default: --kernel)")
     c.add_argument("--workload", required=True)
