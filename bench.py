@@ -227,6 +227,24 @@ def main():
         for i, k in enumerate(names):
             samples[k].append(ev[i].elapsed_time(ev[i + 1]))
     stage_ms = {k: float(np.median(v)) for k, v in samples.items()}
+    # the compositing walks and the loss gradient as one launch (gs_render_fwd_bwd_l2, which the
+    # step uses) against the separate calls it stands for
+    fsamples, ssamples = [], []
+    for _ in range(STAGE_REPS):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record(stream)
+        r.render_fwd_bwd_l2(params, step.target, step.loss_views, step.grads, dL_out=dL, assign=True)
+        ev[1].record(stream)
+        r.render_fwd()
+        raster.l2_loss_grad(r, r.image, step.target, step.loss_views, dL)
+        r.render_bwd(params, dL, step.grads, assign=True)
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+        fsamples.append(ev[0].elapsed_time(ev[1]))
+        ssamples.append(ev[1].elapsed_time(ev[2]))
+    fused_walks = dict(ms=round(float(np.median(fsamples)), 4), separate_ms=round(float(np.median(ssamples)), 4),
+                       what="render_fwd + loss gradient + render_bwd (walk and projection backward) in one call; "
+                            "separate_ms: the three calls")
     K = r.pairs()
     useful_pairs = int(r.last.to(torch.int64).sum())
     # list entries walked: per tile, the largest last_contrib of its pixels
@@ -348,6 +366,7 @@ def main():
                    "graph": not args.no_graph},
         "per_view": per_view,
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+        "fused_walks": fused_walks,
         "pairs": K,
         "walked_entries": walked,
         "evaluated_pairs": walked * opts.tile_w * opts.tile_h,

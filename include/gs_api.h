@@ -292,6 +292,28 @@ int gs_project_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t V, cons
 int gs_l2_grad(const float* image, const float* target, const gs_camera* cams, int32_t V, int32_t mean_views,
                float* dL_dimage, gs_stream_t stream);
 
+/* Eq. 2 forward and backward for the mean-squared-error loss of gs_l2_grad,
+ * in one launch of the compositing walks: the same results, bit for bit, as
+ * gs_render_fwd, then gs_l2_grad(image, target, cams, V, mean_views, ...),
+ * then gs_render_bwd on the same arguments.  The loss gradient of a pixel
+ * needs only that pixel, so the backward of a tile may start once the forward
+ * of that tile is done: every tile's forward walk is taken first, in the
+ * heaviest-first order, and the backward items of finished tiles run while the
+ * deepest tiles' forward walks go on; each backward item waits, with a time
+ * limit, for its tile's forward (a wait that times out, which the ordering
+ * rules out, makes that item's gradients NaN instead of hanging).
+ * image, T_final, last_contrib: WRITTEN as by gs_render_fwd.  dL_dimage:
+ * device, image layout, or NULL; when given it receives dL/dimage as
+ * gs_l2_grad writes it (it may alias neither image nor target).  grads: as
+ * gs_render_bwd.  ws_bytes >= gs_workspace_size(...) (the same workspace as
+ * the other calls; this call also keeps per-tile flags in it).  With
+ * opts->fwd_chunk != 0 the call runs the three calls above one after the other
+ * and then needs dL_dimage (GS_E_INVALID without it).                          */
+int gs_render_fwd_bwd_l2(const gs_gaussians* g, const gs_camera* cams, int32_t V, const gs_opts* opts,
+                         const gs_projected* proj, const gs_binning* bins, const float* target, int32_t mean_views,
+                         float* image, float* T_final, int32_t* last_contrib, float* dL_dimage, gs_grads* grads,
+                         void* ws, size_t ws_bytes, gs_stream_t stream);
+
 /* Photometric loss of Eq. 7, its L1 and D-SSIM terms, over the V views of a
  * rendered image (layout of gs_render_fwd's image), and its gradient:
  *   L_v = (1 - lambda) mean|x - y| + lambda (1 - mean SSIM),  L = mean_v L_v

@@ -278,6 +278,15 @@ size_t render_ws_bytes(uint64_t capacity, int64_t nrec, const gs_opts* o) {
   return bwd_ws_bytes(capacity, nrec) + render_state_bytes(capacity, o);
 }
 
+// The fused forward + backward launch adds its tile flags and ticket after the
+// render regions: [total_tiles + 1] u32.
+size_t fused_ws_bytes(uint64_t capacity, int64_t nrec, const gs_opts* o, int64_t total_tiles) {
+  return render_ws_bytes(capacity, nrec, o) + align256(4 * ((size_t)total_tiles + 1));
+}
+uint32_t* fused_sync_ptr(void* ws, uint64_t capacity, int64_t nrec, const gs_opts* o) {
+  return (uint32_t*)((char*)ws + render_ws_bytes(capacity, nrec, o));
+}
+
 void attach_state(RenderArgs* a, uint64_t capacity, int64_t nrec, const gs_opts* o, const void* ws) {
   a->pair_live = pair_live_ptr(ws, capacity, nrec);
   char* base = (char*)ws + bwd_ws_bytes(capacity, nrec);
@@ -354,7 +363,7 @@ size_t gs_workspace_size(int64_t n, int32_t V, const gs_camera* cams, const gs_o
   if (n < 0 || capacity >= (1ull << 32) || !view_table(cams, V, opts, &vt, nullptr)) return 0;
   const SortPlan p = sort_plan(n, V, vt.total_tiles, capacity);
   const size_t sort_bytes = bin_sort_ws_bytes(p);
-  const size_t render_bytes = render_ws_bytes(capacity, (int64_t)V * n, opts);
+  const size_t render_bytes = fused_ws_bytes(capacity, (int64_t)V * n, opts, vt.total_tiles);
   return sort_bytes > render_bytes ? sort_bytes : render_bytes;
 }
 
@@ -439,6 +448,48 @@ int gs_render_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t V, const
   attach_state(&ra, bins->capacity, nrec, opts, ws);
   hipError_t e = launch_fill_u32((uint32_t*)ra.pair_live, (int64_t)(live_bytes(bins->capacity) / 4), 0u, s);
   if (e == hipSuccess) e = launch_render_bwd(ra, vt, T_final, last_contrib, dL_dimage, grad_pair, s);
+  if (e != hipSuccess) return GS_E_HIP;
+  return launched(launch_project_bwd(project_bwd_args(pa, opts, proj, bins, grad_pair, grads, g->sh_degree, ws, nrec),
+                                     vt, g->sh_degree, s));
+}
+
+int gs_render_fwd_bwd_l2(const gs_gaussians* g, const gs_camera* cams, int32_t V, const gs_opts* opts,
+                         const gs_projected* proj, const gs_binning* bins, const float* target, int32_t mean_views,
+                         float* image, float* T_final, int32_t* last_contrib, float* dL_dimage, gs_grads* grads,
+                         void* ws, size_t ws_bytes, gs_stream_t stream) {
+  ProjectArgs pa;
+  ViewTable vt;
+  if (!gaussians_ok(g, &pa) || !view_table(cams, V, opts, &vt, nullptr)) return GS_E_INVALID;
+  set_lowpass(&vt, opts, g->n);
+  if (!proj || !target || mean_views < 1 || !image || !T_final || !last_contrib || !grads) return GS_E_INVALID;
+  if (dL_dimage && (dL_dimage == image || dL_dimage == target)) return GS_E_INVALID;
+  if (!binning_ok(bins, (int64_t)V * g->n)) return GS_E_INVALID;
+  if (g->n > 0 && (!proj->splats || !proj->tiles_touched)) return GS_E_INVALID;
+  const int64_t nrec = (int64_t)V * g->n;
+  if (!ws || ws_bytes < fused_ws_bytes(bins->capacity, nrec, opts, vt.total_tiles) || !aligned(ws, 256))
+    return GS_E_INVALID;
+  float scale[GS_MAX_VIEWS];
+  for (int v = 0; v < V; ++v)  // as gs_l2_grad: 2 / (3 H W mean_views)
+    scale[v] = (float)(2.0 / ((double)(3 * (int64_t)cams[v].width * cams[v].height) * (double)mean_views));
+  if (opts->fwd_chunk != 0) {  // forward chunking: the three separate calls
+    if (!dL_dimage) return GS_E_INVALID;  // the separate backward reads dL/dimage from memory
+    int r = gs_render_fwd(proj, bins, cams, V, g->n, opts, image, T_final, last_contrib, ws, ws_bytes, stream);
+    if (r != GS_OK) return r;
+    r = gs_l2_grad(image, target, cams, V, mean_views, dL_dimage, stream);
+    if (r != GS_OK) return r;
+    return gs_render_bwd(g, cams, V, opts, proj, bins, T_final, last_contrib, dL_dimage, grads, ws, ws_bytes,
+                         stream);
+  }
+  const int d = device_ok();
+  if (d != GS_OK) return d;
+  hipStream_t s = (hipStream_t)stream;
+  float* grad_pair = (float*)ws;
+  RenderArgs ra = render_args(proj, bins, opts);
+  attach_state(&ra, bins->capacity, nrec, opts, ws);
+  hipError_t e = launch_fill_u32((uint32_t*)ra.pair_live, (int64_t)(live_bytes(bins->capacity) / 4), 0u, s);
+  if (e == hipSuccess)
+    e = launch_render_fused(ra, vt, image, T_final, last_contrib, target, scale, dL_dimage, grad_pair,
+                            fused_sync_ptr(ws, bins->capacity, nrec, opts), s);
   if (e != hipSuccess) return GS_E_HIP;
   return launched(launch_project_bwd(project_bwd_args(pa, opts, proj, bins, grad_pair, grads, g->sh_degree, ws, nrec),
                                      vt, g->sh_degree, s));

@@ -155,6 +155,12 @@ struct L2Args {
   int32_t nviews;
 };
 hipError_t launch_l2_grad(const float* image, const float* target, float* dL, const L2Args& a, hipStream_t s);
+// Forward and backward walks in one launch with the mean-squared-error gradient
+// dL = scale[v] (image - target) computed inline (render.hip).  Needs forward
+// chunking off; pair_live cleared by the caller; sync: [total_tiles + 1] u32.
+hipError_t launch_render_fused(const RenderArgs& a, const ViewTable& vt, float* image, float* T_final,
+                               int32_t* last_contrib, const float* target, const float* scale, float* dL_out,
+                               float* grad_pair, uint32_t* sync, hipStream_t s);
 
 // Target resize: per view the input and output sizes and pixel offsets.
 struct ResizeView {

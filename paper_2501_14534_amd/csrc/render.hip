@@ -312,20 +312,48 @@ __device__ __forceinline__ float reduce_scatter9(const float (&x)[GS_GRAD_FLOATS
 enum : int { kFull = 0, kCount = 1, kTPass = 2 };
 constexpr int kIlp = 4;  // records evaluated together by the forward walk
 
-template <int PPT, bool CULL, int MODE>
-__global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable vt, float* __restrict__ image,
-                                                         float* __restrict__ T_final, int32_t* __restrict__ last_out,
-                                                         int64_t item_base) {
+// Stores and loads of the values one work item hands to another within a
+// launch (image, T_final, last_contrib, chunk states).  COH: agent-scope
+// relaxed atomics, which go to the device's coherence point instead of a
+// compute die's L2, so an item on another die sees them once the flag that
+// follows them is seen, without a cache-wide writeback or invalidate.
+template <bool COH, typename T>
+__device__ __forceinline__ void put(T* p, T v) {
+  if (COH)
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else
+    *p = v;
+}
+template <bool COH>
+__device__ __forceinline__ void put4(float4* p, float4 v) {
+  float* f = (float*)p;
+  put<COH>(f + 0, v.x);
+  put<COH>(f + 1, v.y);
+  put<COH>(f + 2, v.z);
+  put<COH>(f + 3, v.w);
+}
+template <bool COH, typename T>
+__device__ __forceinline__ T get(const T* p) {
+  return COH ? __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : *p;
+}
+template <bool COH>
+__device__ __forceinline__ float4 get4(const float4* p) {
+  const float* f = (const float*)p;
+  return make_float4(get<COH>(f + 0), get<COH>(f + 1), get<COH>(f + 2), get<COH>(f + 3));
+}
+
+// One work item of a forward walk.  s_rec / s_cnt: per wave, the staged group
+// of records (a, b, c) and (COUNT) its hit counts.  Items [0, nfslots) are
+// the forward chunks that start at a forward boundary (slot order); the rest
+// are each tile's first chunk, in the tile schedule.  Counting walks have no
+// chunk items.
+template <int PPT, bool CULL, int MODE, bool COH = false>
+__device__ __forceinline__ void fwd_item(const RenderArgs& a, const ViewTable& vt, float* __restrict__ image,
+                                         float* __restrict__ T_final, int32_t* __restrict__ last_out, int64_t item,
+                                         float4 (*s_rec)[3][kWave], uint32_t (*s_cnt)[kWave]) {
   constexpr bool COUNT = MODE == kCount, TPASS = MODE == kTPass;
-  // per wave: the staged group of records (a, b, c), and (COUNT) its hit counts
-  __shared__ float4 s_rec[4][3][kWave];
-  __shared__ uint32_t s_cnt[4][kWave];
-  // Work items (blockIdx.x + item_base): [0, nfslots) are the forward chunks
-  // that start at a forward boundary (slot order); the rest are each tile's
-  // first chunk, in the tile schedule.  Counting launches have no chunk items.
   const int lf = COUNT ? 31 : a.log2_fchunk;
   const int64_t nfs = COUNT ? 0 : a.nfslots;
-  const int64_t item = (int64_t)blockIdx.x + item_base;
   int gtile;
   bool first;
   if (item < nfs) {
@@ -453,7 +481,7 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable
       float4* st = a.state + slot * tpx;
 #pragma unroll
       for (int p = 0; p < PPT; ++p) {
-        st[threadIdx.x * PPT + p] = make_float4(T[p], S0[p], S1[p], S2[p]);
+        put4<COH>(st + threadIdx.x * PPT + p, make_float4(T[p], S0[p], S1[p], S2[p]));
         S0[p] = S1[p] = S2[p] = 0.0f;
       }
       if (lane == 0) a.slot_owner[slot] = (uint32_t)gtile;  // every wave that gets here writes the same
@@ -569,12 +597,12 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable
     float4* st = a.state + slot * tpx;
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
-      float4 v = st[threadIdx.x * PPT + p];
+      float4 v = get4<COH>(st + threadIdx.x * PPT + p);
       const float e0 = v.y, e1 = v.z, e2 = v.w;  // colour of the chunk before boundary k
       v.y = S0[p];
       v.z = S1[p];
       v.w = S2[p];
-      st[threadIdx.x * PPT + p] = v;
+      put4<COH>(st + threadIdx.x * PPT + p, v);
       S0[p] = e0 + S0[p];
       S1[p] = e1 + S1[p];
       S2[p] = e2 + S2[p];
@@ -602,13 +630,23 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable
     if (x < va.W && y < va.H) {
       const int64_t pix = (int64_t)y * va.W + x;
       float* img = image + 3 * (int64_t)va.pix_off;
-      img[pix] = C0[p] + T[p] * a.bg[0];
-      img[plane + pix] = C1[p] + T[p] * a.bg[1];
-      img[2 * plane + pix] = C2[p] + T[p] * a.bg[2];
-      T_final[va.pix_off + pix] = T[p];
-      last_out[va.pix_off + pix] = last[p];
+      put<COH>(img + pix, C0[p] + T[p] * a.bg[0]);
+      put<COH>(img + plane + pix, C1[p] + T[p] * a.bg[1]);
+      put<COH>(img + 2 * plane + pix, C2[p] + T[p] * a.bg[2]);
+      put<COH>(T_final + va.pix_off + pix, T[p]);
+      put<COH>(last_out + va.pix_off + pix, last[p]);
     }
   }
+}
+
+// Work items [item_base, item_base + gridDim.x) of a forward walk, one per workgroup.
+template <int PPT, bool CULL, int MODE>
+__global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable vt, float* __restrict__ image,
+                                                         float* __restrict__ T_final, int32_t* __restrict__ last_out,
+                                                         int64_t item_base) {
+  __shared__ float4 s_rec[4][3][kWave];
+  __shared__ uint32_t s_cnt[4][kWave];
+  fwd_item<PPT, CULL, MODE>(a, vt, image, T_final, last_out, (int64_t)blockIdx.x + item_base, s_rec, s_cnt);
 }
 
 // Forward chunking: the tiles with several chunks.  Per pixel, the chunks'
@@ -676,34 +714,46 @@ __global__ void fwd_mark_kernel(RenderArgs a, int total_tiles) {
 
 constexpr float kPosScale = 2.77258872223978124f;  // 4 ln 2 = -2 / kQScale
 
-template <int PPT, bool CULL>
-__global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs a, ViewTable vt, const float* __restrict__ T_final,
-                                                         const int32_t* __restrict__ last_in,
-                                                         const float* __restrict__ dL_dimage,
-                                                         float* __restrict__ grad_pair) {
-  extern __shared__ __align__(16) unsigned char smem[];
+// The loss gradient a backward walk reads: dL/dimage from memory, or (fused
+// with the forward) the mean-squared-error gradient computed per pixel from
+// the image the forward wrote and the target, dL = scale_v (image - target)
+// in single precision, as gs_l2_grad computes it; the tile's first backward
+// item also stores it when dL_out is given.
+struct LossIn {
+  const float* dL_dimage;
+  const float* image;
+  const float* target;
+  float* dL_out;
+  float scale[GS_MAX_VIEWS];
+};
+
+// One work item of the backward walk.  Items [0, nslots) are the chunks that
+// start at a recorded boundary (slot order, so the long lists' chunks start
+// first); the rest are each tile's first chunk, in the tile schedule.  smem:
+// lds_bytes(bwd_batch(batch, waves), waves, true) bytes.
+template <int PPT, bool CULL, bool L2>
+__device__ __forceinline__ void bwd_item(const RenderArgs& a, const ViewTable& vt, const float* __restrict__ T_final,
+                                         const int32_t* __restrict__ last_in, const LossIn& loss,
+                                         float* __restrict__ grad_pair, int64_t item, unsigned char* smem) {
   __shared__ int s_max[4];
   __shared__ Box s_box[4];
-  // Work items: workgroups [0, nslots) take the chunks that start at a recorded
-  // boundary (slot order, so the long lists' chunks start first); the rest take
-  // each tile's first chunk, in the tile schedule.
   const int lg = a.log2_chunk;
   int gtile;
   bool first;
-  if ((int64_t)blockIdx.x < a.nslots) {
-    const uint32_t owner = a.slot_owner[blockIdx.x];
+  if (item < a.nslots) {
+    const uint32_t owner = a.slot_owner[item];
     if (owner >= (uint32_t)vt.total_tiles) return;  // no boundary here (uniform)
     gtile = (int)owner;
     first = false;
   } else {
-    const int b = (int)((int64_t)blockIdx.x - a.nslots);
+    const int b = (int)(item - a.nslots);
     gtile = a.order ? (int)a.order[b] : b;
     first = true;
   }
   const TileCtx tc = tile_ctx(vt, a, gtile);
   const uint64_t cmask = (1ull << lg) - 1;
   // chunk [cs, ce) of the tile's list [start, end)
-  const uint64_t cs = first ? (uint64_t)tc.start : (((uint64_t)blockIdx.x << lg) | ((uint64_t)tc.start & cmask));
+  const uint64_t cs = first ? (uint64_t)tc.start : (((uint64_t)item << lg) | ((uint64_t)tc.start & cmask));
   const uint64_t ce = min(cs + (1ull << lg), (uint64_t)tc.end);
   if (!first && !(cs > (uint64_t)tc.start && cs < (uint64_t)tc.end)) return;  // a record not of this list
   const ViewArgs& va = vt.v[tc.view];
@@ -742,12 +792,24 @@ __global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs a, ViewTable
     lc[p] = 0;
     if (x < va.W && y < va.H) {
       const int64_t pix = (int64_t)y * va.W + x;
-      const float* dl = dL_dimage + 3 * (int64_t)va.pix_off;
-      T[p] = T_final[va.pix_off + pix];
-      lc[p] = last_in[va.pix_off + pix];
-      g0[p] = dl[pix];
-      g1[p] = dl[plane + pix];
-      g2[p] = dl[2 * plane + pix];
+      const int64_t e0 = 3 * (int64_t)va.pix_off + pix;
+      T[p] = get<L2>(T_final + va.pix_off + pix);
+      lc[p] = get<L2>(last_in + va.pix_off + pix);
+      if (L2) {
+        const float sc = loss.scale[tc.view];
+        g0[p] = sc * (get<L2>(loss.image + e0) - loss.target[e0]);
+        g1[p] = sc * (get<L2>(loss.image + e0 + plane) - loss.target[e0 + plane]);
+        g2[p] = sc * (get<L2>(loss.image + e0 + 2 * plane) - loss.target[e0 + 2 * plane]);
+        if (first && loss.dL_out) {
+          loss.dL_out[e0] = g0[p];
+          loss.dL_out[e0 + plane] = g1[p];
+          loss.dL_out[e0 + 2 * plane] = g2[p];
+        }
+      } else {
+        g0[p] = loss.dL_dimage[e0];
+        g1[p] = loss.dL_dimage[e0 + plane];
+        g2[p] = loss.dL_dimage[e0 + 2 * plane];
+      }
       RdL[p] = T[p] * (a.bg[0] * g0[p] + a.bg[1] * g1[p] + a.bg[2] * g2[p]);
       my_max = max(my_max, lc[p]);
     }
@@ -787,7 +849,7 @@ __global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs a, ViewTable
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
       if (lc[p] > rel) {
-        const float4 v = st[threadIdx.x * PPT + p];
+        const float4 v = get4<L2>(st + threadIdx.x * PPT + p);
         float c0 = v.y, c1 = v.z, c2 = v.w;
         if (sf) {
           const float4 w = sf[threadIdx.x * PPT + p];
@@ -903,6 +965,103 @@ __global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs a, ViewTable
   }
 }
 
+template <int PPT, bool CULL>
+__global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs a, ViewTable vt, const float* __restrict__ T_final,
+                                                         const int32_t* __restrict__ last_in,
+                                                         const float* __restrict__ dL_dimage,
+                                                         float* __restrict__ grad_pair) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  LossIn loss;
+  loss.dL_dimage = dL_dimage;
+  loss.image = loss.target = nullptr;
+  loss.dL_out = nullptr;
+  bwd_item<PPT, CULL, false>(a, vt, T_final, last_in, loss, grad_pair, (int64_t)blockIdx.x, smem);
+}
+
+// Boundary owners of the backward chunks: slot (start + k 2^log2_chunk) >>
+// log2_chunk of every tile's list, k >= 1, whether or not the forward walk
+// reaches it (a chunk past the walk then finds nothing to do).  One thread per tile.
+__global__ void bwd_mark_kernel(RenderArgs a, int total_tiles) {
+  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gt >= total_tiles || *a.status != 0) return;
+  const uint64_t start = a.ranges[2 * gt], end = a.ranges[2 * gt + 1];
+  const int lg = a.log2_chunk;
+  for (uint64_t q = start + (1ull << lg); q < end; q += 1ull << lg) a.slot_owner[q >> lg] = (uint32_t)gt;
+}
+
+// Polls (at most kWaitPolls times, sleeping about 2000 cycles between polls)
+// until the flag is set; false if it never was (after about a second).
+constexpr int kWaitPolls = 1 << 20;
+__device__ __forceinline__ bool wait_flag(const uint32_t* flag) {
+  for (int i = 0; i < kWaitPolls; ++i) {
+    if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) return true;
+    __builtin_amdgcn_s_sleep(32);
+  }
+  return false;
+}
+
+// Forward and backward walks in one launch, for the mean-squared-error loss
+// (the loss gradient of a pixel needs only that pixel).  Each workgroup takes
+// the next work item from a ticket: first every tile's forward walk in the
+// heaviest-first schedule, then every tile's first backward chunk in the
+// reverse schedule (the short lists, whose forward walks end first, first),
+// then the backward chunks that start at a boundary (slot order; these belong
+// to the long lists, whose forward walks end last).  A forward item sets its
+// tile's flag once the image, T_final, last_contrib and chunk states of the
+// tile are written; a backward item waits for its tile's flag.  The flags it
+// waits for belong to items taken earlier, which wait for nothing, so every
+// wait ends (a wait that outlives its poll limit gives up and makes the
+// item's gradients NaN instead of blocking).  The backward items of finished
+// tiles run while the deepest tiles' forward walks are still going.  sync:
+// [total_tiles] flags, then the ticket, all zero at launch.
+template <int PPT, bool CULL>
+__global__ __launch_bounds__(256) void render_fused_kernel(RenderArgs a, ViewTable vt, float* __restrict__ image,
+                                                           float* __restrict__ T_final, int32_t* __restrict__ last,
+                                                           LossIn loss, float* __restrict__ grad_pair,
+                                                           uint32_t* __restrict__ sync) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ uint32_t s_ticket;
+  __shared__ int s_ok;
+  const int64_t ntiles = vt.total_tiles;
+  if (threadIdx.x == 0) s_ticket = atomicAdd(sync + ntiles, 1u);
+  __syncthreads();
+  const int64_t q = s_ticket;
+  if (q < ntiles) {
+    fwd_item<PPT, CULL, kFull, true>(a, vt, image, T_final, last, q, (float4(*)[3][kWave])smem,
+                                     (uint32_t(*)[kWave])(smem + sizeof(float4) * 4 * 3 * kWave));
+    // every thread's coherent stores of image, T_final, last_contrib and
+    // states have been acknowledged before the flag is set
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int gtile = a.order ? (int)a.order[q] : (int)q;
+      __hip_atomic_store(sync + gtile, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return;
+  }
+  // render_bwd_kernel's item numbering: [0, nslots) boundary chunks, then first chunks by schedule position
+  const int64_t qb = q - ntiles;
+  const int64_t item = qb < ntiles ? a.nslots + (ntiles - 1 - qb) : qb - ntiles;
+  if (threadIdx.x == 0) {
+    int gtile = -1;
+    if (item < a.nslots) {
+      const uint32_t owner = a.slot_owner[item];
+      if (owner < (uint32_t)ntiles) gtile = (int)owner;
+    } else {
+      const int64_t b = item - a.nslots;
+      gtile = a.order ? (int)a.order[b] : (int)b;
+    }
+    s_ok = gtile < 0 || wait_flag(sync + gtile);
+  }
+  __syncthreads();  // the tile's values are then read with coherent loads
+  LossIn l = loss;
+  if (!s_ok) {  // never seen the forward finish: poison this item's gradients
+    const float nan = __builtin_nanf("");
+    for (int v = 0; v < GS_MAX_VIEWS; ++v) l.scale[v] = nan;
+  }
+  bwd_item<PPT, CULL, true>(a, vt, T_final, last, l, grad_pair, item, smem);
+}
+
 static int tile_threads(const RenderArgs& a) { return (1 << (a.log2_tw + a.log2_th)) / a.ppt; }
 
 // Work items [item_base, item_base + items) of one walk launch.
@@ -973,6 +1132,47 @@ hipError_t launch_count_hits(const RenderArgs& a, const ViewTable& vt, hipStream
     case 1: count_ppt<1>(a, vt, s); break;
     case 2: count_ppt<2>(a, vt, s); break;
     default: count_ppt<4>(a, vt, s); break;
+  }
+  return hipGetLastError();
+}
+
+template <int PPT>
+static void fused_ppt(const RenderArgs& a, const ViewTable& vt, float* image, float* T_final, int32_t* last,
+                      const LossIn& loss, float* grad_pair, uint32_t* sync, hipStream_t s) {
+  const int nt = tile_threads(a);
+  const size_t bwd_sh = lds_bytes(bwd_batch(a.batch, nt / kWave), nt / kWave, true);
+  const size_t fwd_sh = sizeof(float4) * 4 * 3 * kWave + sizeof(uint32_t) * 4 * kWave;
+  const size_t sh = bwd_sh > fwd_sh ? bwd_sh : fwd_sh;
+  // forward items, then backward chunk items, then backward first chunks
+  const dim3 grid((unsigned)(2 * vt.total_tiles + a.nslots)), block((unsigned)nt);
+  if (a.cull)
+    hipLaunchKernelGGL((render_fused_kernel<PPT, true>), grid, block, sh, s, a, vt, image, T_final, last, loss,
+                       grad_pair, sync);
+  else
+    hipLaunchKernelGGL((render_fused_kernel<PPT, false>), grid, block, sh, s, a, vt, image, T_final, last, loss,
+                       grad_pair, sync);
+}
+
+hipError_t launch_render_fused(const RenderArgs& a, const ViewTable& vt, float* image, float* T_final,
+                               int32_t* last_contrib, const float* target, const float* scale, float* dL_out,
+                               float* grad_pair, uint32_t* sync, hipStream_t s) {
+  if (vt.total_tiles == 0) return hipSuccess;
+  if (a.nfslots != 0) return hipErrorInvalidValue;  // forward chunking runs as separate launches
+  LossIn loss;
+  loss.dL_dimage = nullptr;
+  loss.image = image;
+  loss.target = target;
+  loss.dL_out = dL_out;
+  for (int v = 0; v < GS_MAX_VIEWS; ++v) loss.scale[v] = v < vt.nviews ? scale[v] : 0.0f;
+  hipError_t e = launch_fill_u32(a.slot_owner, a.nslots, 0xffffffffu, s);
+  if (e == hipSuccess) e = launch_fill_u32(sync, vt.total_tiles + 1, 0u, s);  // flags and ticket
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(bwd_mark_kernel, dim3((unsigned)((vt.total_tiles + 255) / 256)), dim3(256), 0, s, a,
+                     vt.total_tiles);
+  switch (a.ppt) {
+    case 1: fused_ppt<1>(a, vt, image, T_final, last_contrib, loss, grad_pair, sync, s); break;
+    case 2: fused_ppt<2>(a, vt, image, T_final, last_contrib, loss, grad_pair, sync, s); break;
+    default: fused_ppt<4>(a, vt, image, T_final, last_contrib, loss, grad_pair, sync, s); break;
   }
   return hipGetLastError();
 }

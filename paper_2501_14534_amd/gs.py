@@ -20,7 +20,7 @@ GRAD_FLOATS = 9
 MAX_BATCH = 1024
 
 EXPORTS = ("gs_view_sizes", "gs_workspace_size", "gs_project", "gs_bin_sort", "gs_render_fwd", "gs_render_bwd",
-           "gs_blend_bwd", "gs_project_bwd", "gs_loss_workspace_size", "gs_loss_l1_dssim", "gs_l2_grad",
+           "gs_render_fwd_bwd_l2", "gs_blend_bwd", "gs_project_bwd", "gs_loss_workspace_size", "gs_loss_l1_dssim", "gs_l2_grad",
            "gs_mask_loss_workspace_size", "gs_mask_loss", "gs_mask_loss_noalloc", "gs_count_hits", "gs_significance_workspace_size",
            "gs_significance", "gs_blur_views", "gs_resize_views", "gs_strerror")
 
@@ -90,6 +90,9 @@ def load():
     L.gs_render_bwd.argtypes = [P(GsGaussians), P(GsCamera), C.c_int32, P(GsOpts), P(GsProjected), P(GsBinning),
                                 vp, vp, vp, P(GsGrads), vp, C.c_size_t, vp]
     L.gs_render_bwd.restype = C.c_int
+    L.gs_render_fwd_bwd_l2.argtypes = [P(GsGaussians), P(GsCamera), C.c_int32, P(GsOpts), P(GsProjected),
+                                       P(GsBinning), vp, C.c_int32, vp, vp, vp, vp, P(GsGrads), vp, C.c_size_t, vp]
+    L.gs_render_fwd_bwd_l2.restype = C.c_int
     L.gs_blend_bwd.argtypes = [P(GsCamera), C.c_int32, C.c_int64, P(GsOpts), P(GsProjected), P(GsBinning), vp, vp,
                                vp, vp, vp, C.c_size_t, vp]
     L.gs_blend_bwd.restype = C.c_int
@@ -197,6 +200,13 @@ def render_fwd(proj, bins, cams_arr, V, n, opts_s, image, T_final, last, ws, ws_
 def render_bwd(g, cams_arr, V, opts_s, proj, bins, T_final, last, dL_dimage, grads, ws, ws_bytes, stream) -> int:
     return load().gs_render_bwd(C.byref(g), cams_arr, V, C.byref(opts_s), C.byref(proj), C.byref(bins), T_final, last,
                                 dL_dimage, C.byref(grads), ws, ws_bytes, stream)
+
+
+def render_fwd_bwd_l2(g, cams_arr, V, opts_s, proj, bins, target, mean_views, image, T_final, last, dL_dimage,
+                      grads, ws, ws_bytes, stream) -> int:
+    return load().gs_render_fwd_bwd_l2(C.byref(g), cams_arr, V, C.byref(opts_s), C.byref(proj), C.byref(bins), target,
+                                       int(mean_views), image, T_final, last, dL_dimage, C.byref(grads), ws,
+                                       ws_bytes, stream)
 
 
 def blend_bwd(cams_arr, V, n, opts_s, proj, bins, T_final, last, dL_dimage, grad_pair, ws, ws_bytes, stream) -> int:

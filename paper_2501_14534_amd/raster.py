@@ -136,6 +136,22 @@ class Rasterizer:
                                gs.ptr(self.last), gs.ptr(dL_dimage), gr, gs.ptr(self.ws), self.ws_bytes, _stream()),
                  "gs_render_bwd")
 
+    def render_fwd_bwd_l2(self, params, target: torch.Tensor, views: int, grads: Dict[str, torch.Tensor],
+                          dL_out: Optional[torch.Tensor] = None, assign: bool = False) -> None:
+        """Compositing forward, mean-squared-error gradient and backward in one launch of the walks
+        (gs_render_fwd_bwd_l2): the image and the gradients of render_fwd, l2_loss_grad and
+        render_bwd, bit for bit; dL_out, if given, receives dL/dimage."""
+        g = self.gaussians(params)
+        if target.numel() != self.image.numel() or not target.is_contiguous():
+            raise ValueError("target must be contiguous and shaped like the image")
+        if dL_out is not None and (dL_out.numel() != self.image.numel() or not dL_out.is_contiguous()):
+            raise ValueError("dL_out must be contiguous and shaped like the image")
+        gr = gs.GsGrads(*[gs.ptr(grads.get(k)) for k in PARAM_NAMES], None, int(assign))
+        gs.check(gs.render_fwd_bwd_l2(g, self.cams_arr, self.V, self.opts_s, self.proj, self.bins, gs.ptr(target),
+                                      int(views), gs.ptr(self.image), gs.ptr(self.T_final), gs.ptr(self.last),
+                                      gs.ptr(dL_out), gr, gs.ptr(self.ws), self.ws_bytes, _stream()),
+                 "gs_render_fwd_bwd_l2")
+
     def blend_bwd(self, dL_dimage: torch.Tensor, grad_pair: torch.Tensor) -> None:
         """Back-to-front walk only: writes the per-pair splat gradients [capacity, 9] (emission order)."""
         if grad_pair.numel() < self.capacity * gs.GRAD_FLOATS:
@@ -322,14 +338,18 @@ class Step:
     (gs_mask_loss), or None.  sh_rest_every: k > 1 computes the SH bands 1..3
     gradients only on every k-th step (the others skip writing them), the
     sparse SH update the paper adopts (Sec. 3.2.5); two graphs are captured and
-    replayed in turn.
+    replayed in turn.  fused (loss "l2" only): the forward walk, the loss
+    gradient and the backward walk run as one launch (gs_render_fwd_bwd_l2),
+    with the same results as the three separate calls (slower on the
+    benchmark workloads, so off by default).
 
     The binning capacity is fixed while a graph exists; `run()` reads the
     device status after the step and, on overflow, grows the buffers,
     re-captures and runs again."""
 
     def __init__(self, rast: Rasterizer, params, target_flat: torch.Tensor, graph: bool = True,
-                 loss_views: Optional[int] = None, loss: str = "l2", mask_loss=None, sh_rest_every: int = 1):
+                 loss_views: Optional[int] = None, loss: str = "l2", mask_loss=None, sh_rest_every: int = 1,
+                 fused: bool = False):
         self.rast = rast
         self.params = params
         self.target = target_flat
@@ -343,6 +363,8 @@ class Step:
         if loss not in ("l2", "l1_dssim"):
             raise ValueError(loss)
         self.loss_kind = loss
+        # loss "l2": the compositing walks of the step in one launch (gs_render_fwd_bwd_l2)
+        self.fused = bool(fused)
         self.ploss = None
         if loss == "l1_dssim":
             from .photometric import PhotometricLoss
@@ -374,11 +396,6 @@ class Step:
         r = self.rast
         r.project(self.params)
         r.bin_sort()
-        r.render_fwd()
-        if self.ploss is not None:
-            self.ploss(r.image, self.target, out=self.dL)
-        else:
-            l2_loss_grad(r, r.image, self.target, self.loss_views, self.dL)
         # the gradients are written, not added: only the ones this step does not write are
         # cleared (the SH-rest gradient on sparse steps; the SH gradients at degree 0)
         grads = self.grads
@@ -387,7 +404,16 @@ class Step:
         for k in self.grads:
             if (k == "sh_rest" and not with_sh_rest) or (r.deg == 0 and k in ("sh_rest", "sh_mask_logits")):
                 self.grads[k].zero_()
-        r.render_bwd(self.params, self.dL, grads, assign=True)
+        if self.ploss is None and self.fused:
+            # mean squared error: forward, loss gradient and backward walks in one launch
+            r.render_fwd_bwd_l2(self.params, self.target, self.loss_views, grads, dL_out=self.dL, assign=True)
+        else:
+            r.render_fwd()
+            if self.ploss is not None:
+                self.ploss(r.image, self.target, out=self.dL)
+            else:
+                l2_loss_grad(r, r.image, self.target, self.loss_views, self.dL)
+            r.render_bwd(self.params, self.dL, grads, assign=True)
         if self.mask_loss is not None:
             g = r.gaussians(self.params)
             gr = gs.GsGrads(*[gs.ptr(grads.get(k)) for k in PARAM_NAMES], None)
