@@ -298,15 +298,17 @@ int gs_l2_grad(const float* image, const float* target, const gs_camera* cams, i
  * then gs_render_bwd on the same arguments.  The loss gradient of a pixel
  * needs only that pixel, so the backward of a tile may start once the forward
  * of that tile is done: every tile's forward walk is taken first, in the
- * heaviest-first order, and the backward items of finished tiles run while the
- * deepest tiles' forward walks go on; each backward item waits, with a time
- * limit, for its tile's forward (a wait that times out, which the ordering
- * rules out, makes that item's gradients NaN instead of hanging).
+ * heaviest-first order, then the backward items, shortest lists first, so that
+ * the backward of finished tiles runs while the deepest tiles' forward walks go
+ * on; each backward item waits, with a time limit, for its tile's forward (a
+ * wait that times out, which the ordering rules out, makes that item's
+ * gradients NaN instead of hanging).
  * image, T_final, last_contrib: WRITTEN as by gs_render_fwd.  dL_dimage:
  * device, image layout, or NULL; when given it receives dL/dimage as
  * gs_l2_grad writes it (it may alias neither image nor target).  grads: as
  * gs_render_bwd.  ws_bytes >= gs_workspace_size(...) (the same workspace as
- * the other calls; this call also keeps per-tile flags in it).  With
+ * the other calls; this call also keeps per-tile flags and its list of
+ * backward items in it).  With
  * opts->fwd_chunk != 0 the call runs the three calls above one after the other
  * and then needs dL_dimage (GS_E_INVALID without it).                          */
 int gs_render_fwd_bwd_l2(const gs_gaussians* g, const gs_camera* cams, int32_t V, const gs_opts* opts,

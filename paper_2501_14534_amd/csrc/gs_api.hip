@@ -278,10 +278,11 @@ size_t render_ws_bytes(uint64_t capacity, int64_t nrec, const gs_opts* o) {
   return bwd_ws_bytes(capacity, nrec) + render_state_bytes(capacity, o);
 }
 
-// The fused forward + backward launch adds its tile flags and ticket after the
-// render regions: [total_tiles + 1] u32.
+// The fused forward + backward launch adds its tile flags, ticket and backward
+// work list after the render regions.
 size_t fused_ws_bytes(uint64_t capacity, int64_t nrec, const gs_opts* o, int64_t total_tiles) {
-  return render_ws_bytes(capacity, nrec, o) + align256(4 * ((size_t)total_tiles + 1));
+  return render_ws_bytes(capacity, nrec, o) +
+         align256(4 * (size_t)fused_sync_words(total_tiles, chunk_slots(capacity, o)));
 }
 uint32_t* fused_sync_ptr(void* ws, uint64_t capacity, int64_t nrec, const gs_opts* o) {
   return (uint32_t*)((char*)ws + render_ws_bytes(capacity, nrec, o));

@@ -157,7 +157,12 @@ struct L2Args {
 hipError_t launch_l2_grad(const float* image, const float* target, float* dL, const L2Args& a, hipStream_t s);
 // Forward and backward walks in one launch with the mean-squared-error gradient
 // dL = scale[v] (image - target) computed inline (render.hip).  Needs forward
-// chunking off; pair_live cleared by the caller; sync: [total_tiles + 1] u32.
+// chunking off; pair_live cleared by the caller; sync: fused_sync_words u32
+// (tile flags, the ticket, kListHist counts of the backward work list, the list).
+constexpr int kListHist = 129;
+inline int64_t fused_sync_words(int64_t total_tiles, int64_t nslots) {
+  return total_tiles + 1 + kListHist + total_tiles + nslots;
+}
 hipError_t launch_render_fused(const RenderArgs& a, const ViewTable& vt, float* image, float* T_final,
                                int32_t* last_contrib, const float* target, const float* scale, float* dL_out,
                                float* grad_pair, uint32_t* sync, hipStream_t s);

@@ -310,7 +310,10 @@ __device__ __forceinline__ float reduce_scatter9(const float (&x)[GS_GRAD_FLOATS
 // fwd_combine_kernel adds them up.  The critical path of a deep tile becomes
 // about three chunks instead of its whole list.
 enum : int { kFull = 0, kCount = 1, kTPass = 2 };
-constexpr int kIlp = 4;  // records evaluated together by the forward walk
+// records evaluated together by the forward walk: four independent chains a
+// lane (PPT pixels per record)
+template <int PPT>
+constexpr int ilp_records() { return PPT >= 4 ? 1 : 4 / PPT; }
 
 // Stores and loads of the values one work item hands to another within a
 // launch (image, T_final, last_contrib, chunk states).  COH: agent-scope
@@ -346,9 +349,9 @@ __device__ __forceinline__ float4 get4(const float4* p) {
 // of records (a, b, c) and (COUNT) its hit counts.  Items [0, nfslots) are
 // the forward chunks that start at a forward boundary (slot order); the rest
 // are each tile's first chunk, in the tile schedule.  Counting walks have no
-// chunk items.
+// chunk items.  Returns the largest last_contrib this thread stored (0 if none).
 template <int PPT, bool CULL, int MODE, bool COH = false>
-__device__ __forceinline__ void fwd_item(const RenderArgs& a, const ViewTable& vt, float* __restrict__ image,
+__device__ __forceinline__ int fwd_item(const RenderArgs& a, const ViewTable& vt, float* __restrict__ image,
                                          float* __restrict__ T_final, int32_t* __restrict__ last_out, int64_t item,
                                          float4 (*s_rec)[3][kWave], uint32_t (*s_cnt)[kWave]) {
   constexpr bool COUNT = MODE == kCount, TPASS = MODE == kTPass;
@@ -358,7 +361,7 @@ __device__ __forceinline__ void fwd_item(const RenderArgs& a, const ViewTable& v
   bool first;
   if (item < nfs) {
     const uint32_t owner = a.fslot_owner[item];
-    if (owner >= (uint32_t)vt.total_tiles) return;  // no boundary here (uniform)
+    if (owner >= (uint32_t)vt.total_tiles) return 0;  // no boundary here (uniform)
     gtile = (int)owner;
     first = false;
   } else {
@@ -369,13 +372,13 @@ __device__ __forceinline__ void fwd_item(const RenderArgs& a, const ViewTable& v
   const TileCtx tc = tile_ctx(vt, a, gtile);
   const uint64_t fmask = (1ull << lf) - 1;
   const uint64_t cs64 = first ? (uint64_t)tc.start : (((uint64_t)item << lf) | ((uint64_t)tc.start & fmask));
-  if (!first && !(cs64 > (uint64_t)tc.start && cs64 < (uint64_t)tc.end)) return;  // a record not of this list
+  if (!first && !(cs64 > (uint64_t)tc.start && cs64 < (uint64_t)tc.end)) return 0;  // a record not of this list
   const uint32_t cs = (uint32_t)cs64;
   const uint32_t ce = (uint32_t)min(cs64 + (1ull << lf), (uint64_t)tc.end);
   const uint32_t len = tc.end - tc.start;
   const uint32_t nfc = len == 0 ? 1u : (uint32_t)(((uint64_t)len + fmask) >> lf);  // forward chunks of the list
   const uint32_t kf = (uint32_t)((cs64 - tc.start) >> lf);                           // this chunk
-  if (TPASS && (kf == 0 || kf + 1 == nfc)) return;  // chunk 0 leaves its own; the last one is not needed
+  if (TPASS && (kf == 0 || kf + 1 == nfc)) return 0;  // chunk 0 leaves its own; the last one is not needed
   const ViewArgs& va = vt.v[tc.view];
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   float4* s_a = s_rec[wave][0];
@@ -538,33 +541,45 @@ __device__ __forceinline__ void fwd_item(const RenderArgs& a, const ViewTable& v
         }
         if (COUNT && lane == 0 && taken != 0) s_hits[j] += taken;
       };
-      // Four records at a time (in list order): their falloff and alpha do not
-      // depend on the transmittance, so the four evaluations run as independent
-      // chains before the four dependent compositing steps.
+      // R records at a time (in list order) while R are left: their falloff
+      // and alpha do not depend on the transmittance, so the R evaluations run
+      // as independent chains before the R dependent compositing steps (no
+      // record is guarded on its own, which would let the compiler sink each
+      // evaluation next to its compositing step and serialise the
+      // exponentials' latencies); the last ones one at a time.
       const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+      auto eval_one = [&](int j, Eval (&e)[PPT], bool (&in)[PPT], float4& rc) {
+        const float4 ra = s_a[j], rb = s_b[j];
+        rc = COUNT ? zero4 : s_c[j];
+#pragma unroll
+        for (int p = 0; p < PPT; ++p)
+          in[p] = eval_splat_all(px[p], py[p], ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, &e[p]);
+      };
+      constexpr int R = ilp_records<PPT>();
       while (m != 0) {
-        int jq[kIlp];
-        bool vq[kIlp];
+        if (R == 1 || __popcll(m) >= R) {  // wave-uniform
+          int jq[R];
 #pragma unroll
-        for (int q = 0; q < kIlp; ++q) {
-          vq[q] = m != 0;
-          jq[q] = vq[q] ? __builtin_ctzll(m) : jq[0];
+          for (int q = 0; q < R; ++q) {
+            jq[q] = __builtin_ctzll(m);
+            m &= m - 1;
+          }
+          float4 rcq[R];
+          Eval eq[R][PPT];
+          bool iq[R][PPT];
+#pragma unroll
+          for (int q = 0; q < R; ++q) eval_one(jq[q], eq[q], iq[q], rcq[q]);
+#pragma unroll
+          for (int q = 0; q < R; ++q) composite(jq[q], eq[q], iq[q], rcq[q]);
+        } else {
+          const int j = __builtin_ctzll(m);
           m &= m - 1;
+          float4 rc;
+          Eval e[PPT];
+          bool in[PPT];
+          eval_one(j, e, in, rc);
+          composite(j, e, in, rc);
         }
-        float4 rcq[kIlp];
-        Eval eq[kIlp][PPT];
-        bool iq[kIlp][PPT];
-#pragma unroll
-        for (int q = 0; q < kIlp; ++q) {
-          const float4 ra = s_a[jq[q]], rb = s_b[jq[q]];
-          rcq[q] = COUNT ? zero4 : s_c[jq[q]];
-#pragma unroll
-          for (int p = 0; p < PPT; ++p)
-            iq[q][p] = eval_splat_all(px[p], py[p], ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, &eq[q][p]);
-        }
-#pragma unroll
-        for (int q = 0; q < kIlp; ++q)
-          if (vq[q]) composite(jq[q], eq[q], iq[q], rcq[q]);  // wave-uniform
       }
       if (COUNT) {
         // flush the group's counters: lane l adds entry l's hits to its Gaussian
@@ -583,29 +598,40 @@ __device__ __forceinline__ void fwd_item(const RenderArgs& a, const ViewTable& v
     ge3 = ge4;
   }
 
-  if (COUNT) return;
+  if (COUNT) return 0;
   if (TPASS) {  // the product, at the boundary that ends this chunk
     float* fp = a.fprod + (int64_t)((uint64_t)ce >> lf) * tpx;
 #pragma unroll
     for (int p = 0; p < PPT; ++p) fp[threadIdx.x * PPT + p] = T[p];
-    return;
+    return 0;
   }
   // Each recorded state becomes (T there, colour composited after it within
-  // this walk): the suffix sums of the segments' colours, last one first.
-  for (int k = nbnd - 1; k >= 0; --k) {
-    const int64_t slot = (int64_t)((b0 + ((uint64_t)k << lc)) >> lc);
-    float4* st = a.state + slot * tpx;
+  // this walk): the suffix sums of the segments' colours, last one first.  The
+  // states are read kSuf at a time, all loads in flight together (a deep list
+  // records dozens of states, and one load at a time would put as many memory
+  // round trips on the walk's critical path).
+  constexpr int kSuf = PPT >= 4 ? 1 : 4 / PPT;
+  for (int k0 = nbnd - 1; k0 >= 0; k0 -= kSuf) {
+    float4 v[kSuf][PPT];
 #pragma unroll
-    for (int p = 0; p < PPT; ++p) {
-      float4 v = get4<COH>(st + threadIdx.x * PPT + p);
-      const float e0 = v.y, e1 = v.z, e2 = v.w;  // colour of the chunk before boundary k
-      v.y = S0[p];
-      v.z = S1[p];
-      v.w = S2[p];
-      put4<COH>(st + threadIdx.x * PPT + p, v);
-      S0[p] = e0 + S0[p];
-      S1[p] = e1 + S1[p];
-      S2[p] = e2 + S2[p];
+    for (int i = 0; i < kSuf; ++i) {
+      if (k0 - i < 0) break;  // wave-uniform
+      const int64_t slot = (int64_t)((b0 + ((uint64_t)(k0 - i) << lc)) >> lc);
+#pragma unroll
+      for (int p = 0; p < PPT; ++p) v[i][p] = get4<COH>(a.state + slot * tpx + threadIdx.x * PPT + p);
+    }
+#pragma unroll
+    for (int i = 0; i < kSuf; ++i) {
+      if (k0 - i < 0) break;
+      const int64_t slot = (int64_t)((b0 + ((uint64_t)(k0 - i) << lc)) >> lc);
+#pragma unroll
+      for (int p = 0; p < PPT; ++p) {
+        const float e0 = v[i][p].y, e1 = v[i][p].z, e2 = v[i][p].w;  // colour of the chunk before the boundary
+        put4<COH>(a.state + slot * tpx + threadIdx.x * PPT + p, make_float4(v[i][p].x, S0[p], S1[p], S2[p]));
+        S0[p] = e0 + S0[p];
+        S1[p] = e1 + S1[p];
+        S2[p] = e2 + S2[p];
+      }
     }
   }
 
@@ -621,9 +647,10 @@ __device__ __forceinline__ void fwd_item(const RenderArgs& a, const ViewTable& v
       a.flast[idx * tpx + threadIdx.x * PPT + p] = dead[p] ? -1 : last[p];
       if (kf == 0) a.fprod[idx * tpx + threadIdx.x * PPT + p] = done[p] ? 0.0f : T[p];
     }
-    return;
+    return 0;
   }
   const int64_t plane = (int64_t)va.W * va.H;
+  int my_max = 0;
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
     const int x = (int)px[p], y = (int)py[p];
@@ -635,15 +662,20 @@ __device__ __forceinline__ void fwd_item(const RenderArgs& a, const ViewTable& v
       put<COH>(img + 2 * plane + pix, C2[p] + T[p] * a.bg[2]);
       put<COH>(T_final + va.pix_off + pix, T[p]);
       put<COH>(last_out + va.pix_off + pix, last[p]);
+      my_max = max(my_max, last[p]);
     }
   }
+  return my_max;
 }
 
 // Work items [item_base, item_base + gridDim.x) of a forward walk, one per workgroup.
+// At one pixel a thread the kernel is held to 80 registers (six waves per SIMD).
 template <int PPT, bool CULL, int MODE>
-__global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a, ViewTable vt, float* __restrict__ image,
-                                                         float* __restrict__ T_final, int32_t* __restrict__ last_out,
-                                                         int64_t item_base) {
+__global__ __launch_bounds__(256, PPT == 1 ? 6 : 1) void render_fwd_kernel(RenderArgs a, ViewTable vt,
+                                                                           float* __restrict__ image,
+                                                                           float* __restrict__ T_final,
+                                                                           int32_t* __restrict__ last_out,
+                                                                           int64_t item_base) {
   __shared__ float4 s_rec[4][3][kWave];
   __shared__ uint32_t s_cnt[4][kWave];
   fwd_item<PPT, CULL, MODE>(a, vt, image, T_final, last_out, (int64_t)blockIdx.x + item_base, s_rec, s_cnt);
@@ -730,11 +762,14 @@ struct LossIn {
 // One work item of the backward walk.  Items [0, nslots) are the chunks that
 // start at a recorded boundary (slot order, so the long lists' chunks start
 // first); the rest are each tile's first chunk, in the tile schedule.  smem:
-// lds_bytes(bwd_batch(batch, waves), waves, true) bytes.
+// lds_bytes(bwd_batch(batch, waves), waves, true) bytes.  ok false (a wait for
+// the tile's forward that timed out): the item's loss gradient is NaN.  walked
+// >= 0: the tile's largest last_contrib, known beforehand.
 template <int PPT, bool CULL, bool L2>
 __device__ __forceinline__ void bwd_item(const RenderArgs& a, const ViewTable& vt, const float* __restrict__ T_final,
                                          const int32_t* __restrict__ last_in, const LossIn& loss,
-                                         float* __restrict__ grad_pair, int64_t item, unsigned char* smem) {
+                                         float* __restrict__ grad_pair, int64_t item, unsigned char* smem,
+                                         bool ok = true, int walked = -1) {
   __shared__ int s_max[4];
   __shared__ Box s_box[4];
   const int lg = a.log2_chunk;
@@ -756,6 +791,8 @@ __device__ __forceinline__ void bwd_item(const RenderArgs& a, const ViewTable& v
   const uint64_t cs = first ? (uint64_t)tc.start : (((uint64_t)item << lg) | ((uint64_t)tc.start & cmask));
   const uint64_t ce = min(cs + (1ull << lg), (uint64_t)tc.end);
   if (!first && !(cs > (uint64_t)tc.start && cs < (uint64_t)tc.end)) return;  // a record not of this list
+  // a chunk at or past the tile's largest last_contrib has nothing to do (uniform)
+  if (!first && walked >= 0 && cs >= (uint64_t)tc.start + (uint64_t)walked) return;
   const ViewArgs& va = vt.v[tc.view];
   const int nthreads = blockDim.x;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave, nwaves = nthreads / kWave;
@@ -796,7 +833,7 @@ __device__ __forceinline__ void bwd_item(const RenderArgs& a, const ViewTable& v
       T[p] = get<L2>(T_final + va.pix_off + pix);
       lc[p] = get<L2>(last_in + va.pix_off + pix);
       if (L2) {
-        const float sc = loss.scale[tc.view];
+        const float sc = ok ? loss.scale[tc.view] : __builtin_nanf("");
         g0[p] = sc * (get<L2>(loss.image + e0) - loss.target[e0]);
         g1[p] = sc * (get<L2>(loss.image + e0 + plane) - loss.target[e0 + plane]);
         g2[p] = sc * (get<L2>(loss.image + e0 + 2 * plane) - loss.target[e0 + 2 * plane]);
@@ -978,88 +1015,164 @@ __global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs a, ViewTable
   bwd_item<PPT, CULL, false>(a, vt, T_final, last_in, loss, grad_pair, (int64_t)blockIdx.x, smem);
 }
 
-// Boundary owners of the backward chunks: slot (start + k 2^log2_chunk) >>
-// log2_chunk of every tile's list, k >= 1, whether or not the forward walk
-// reaches it (a chunk past the walk then finds nothing to do).  One thread per tile.
-__global__ void bwd_mark_kernel(RenderArgs a, int total_tiles) {
-  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gt >= total_tiles || *a.status != 0) return;
-  const uint64_t start = a.ranges[2 * gt], end = a.ranges[2 * gt + 1];
+// Backward work list of the one-launch walks.  Each tile contributes its first
+// chunk and one item per boundary (start + k 2^log2_chunk, k >= 1, whether or
+// not the forward walk reaches it: a chunk past the walk then finds nothing to
+// do).  Tiles are grouped by the bit length of their list length and the groups
+// laid out lightest first: a tile's backward items are then taken about when its
+// forward walk ends, and the deepest lists' items, whose forward walks end last,
+// come last (an item taken before its tile's forward walk has ended holds its
+// workgroup slot while it waits).  An entry is a render_bwd_kernel item number
+// with the schedule off: a boundary chunk is its slot, tile t's first chunk
+// nslots + t.  The count pass also records each boundary's owner.
+// hist: [0, 64) items per group, [64, 128) write positions, [128] the total.
+__device__ __forceinline__ int list_group(uint32_t len) { return len ? 32 - __clz(len) : 0; }
+
+__device__ __forceinline__ uint32_t list_items(uint32_t len, int lg) {
+  return (uint64_t)len > (1ull << lg) ? (uint32_t)(((uint64_t)len - 1) >> lg) + 1u : 1u;
+}
+
+__device__ __forceinline__ uint32_t list_len(const RenderArgs& a, int64_t t) {
+  return *a.status == 0 ? a.ranges[2 * t + 1] - a.ranges[2 * t] : 0u;
+}
+
+__global__ __launch_bounds__(256) void list_count_kernel(RenderArgs a, int64_t tiles, uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[64];
+  if (threadIdx.x < 64) h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < tiles) {
+    const uint32_t len = list_len(a, t);
+    const int lg = a.log2_chunk;
+    const uint64_t start = a.ranges[2 * t];
+    for (uint64_t q = start + (1ull << lg); q < start + len; q += 1ull << lg) a.slot_owner[q >> lg] = (uint32_t)t;
+    atomicAdd(&h[list_group(len)], list_items(len, lg));
+  }
+  __syncthreads();
+  if (threadIdx.x < 64 && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+}
+
+__global__ void list_scan_kernel(uint32_t* __restrict__ hist) {
+  if (threadIdx.x != 0) return;
+  uint32_t run = 0;
+  for (int g = 0; g < 64; ++g) {
+    hist[64 + g] = run;
+    run += hist[g];
+  }
+  hist[128] = run;
+}
+
+__global__ __launch_bounds__(256) void list_scatter_kernel(RenderArgs a, int64_t tiles, uint32_t* __restrict__ hist,
+                                                           uint32_t* __restrict__ list) {
+  // offsets within the block per group (LDS), one global reservation per group and block
+  __shared__ uint32_t h[64], base[64];
+  if (threadIdx.x < 64) h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int lg = a.log2_chunk;
-  for (uint64_t q = start + (1ull << lg); q < end; q += 1ull << lg) a.slot_owner[q >> lg] = (uint32_t)gt;
+  int g = 0;
+  uint32_t len = 0, n = 0, off = 0;
+  if (t < tiles) {
+    len = list_len(a, t);
+    g = list_group(len);
+    n = list_items(len, lg);
+    off = atomicAdd(&h[g], n);
+  }
+  __syncthreads();
+  if (threadIdx.x < 64 && h[threadIdx.x]) base[threadIdx.x] = atomicAdd(&hist[64 + threadIdx.x], h[threadIdx.x]);
+  __syncthreads();
+  if (t >= tiles) return;
+  uint32_t* out = list + base[g] + off;
+  out[0] = (uint32_t)(a.nslots + t);
+  const uint64_t start = a.ranges[2 * t];
+  for (uint32_t k = 1; k < n; ++k) out[k] = (uint32_t)((start + ((uint64_t)k << lg)) >> lg);
 }
 
 // Polls (at most kWaitPolls times, sleeping about 2000 cycles between polls)
-// until the flag is set; false if it never was (after about a second).
+// until the flag is set; its value, or 0 if it never was (after about a second).
 constexpr int kWaitPolls = 1 << 20;
-__device__ __forceinline__ bool wait_flag(const uint32_t* flag) {
+__device__ __forceinline__ uint32_t wait_flag(const uint32_t* flag) {
   for (int i = 0; i < kWaitPolls; ++i) {
-    if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) return true;
+    const uint32_t v = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (v != 0u) return v;
     __builtin_amdgcn_s_sleep(32);
   }
-  return false;
+  return 0u;
 }
 
 // Forward and backward walks in one launch, for the mean-squared-error loss
 // (the loss gradient of a pixel needs only that pixel).  Each workgroup takes
 // the next work item from a ticket: first every tile's forward walk in the
-// heaviest-first schedule, then every tile's first backward chunk in the
-// reverse schedule (the short lists, whose forward walks end first, first),
-// then the backward chunks that start at a boundary (slot order; these belong
-// to the long lists, whose forward walks end last).  A forward item sets its
-// tile's flag once the image, T_final, last_contrib and chunk states of the
-// tile are written; a backward item waits for its tile's flag.  The flags it
+// heaviest-first schedule, then the backward work list (lightest lists first,
+// see list_count_kernel).  A forward item sets its tile's flag once the image,
+// T_final, last_contrib and chunk states of the tile are written; a backward
+// item waits for its tile's flag, which holds 1 + the tile's largest
+// last_contrib (a boundary chunk past it then leaves at once).  The flags it
 // waits for belong to items taken earlier, which wait for nothing, so every
-// wait ends (a wait that outlives its poll limit gives up and makes the
-// item's gradients NaN instead of blocking).  The backward items of finished
-// tiles run while the deepest tiles' forward walks are still going.  sync:
-// [total_tiles] flags, then the ticket, all zero at launch.
+// wait ends (a wait that outlives its poll limit gives up and makes the item's
+// gradients NaN instead of blocking).
+// The backward items of finished tiles run while the deepest tiles' forward
+// walks are still going.  sync: [total_tiles] flags, the ticket, all zero at
+// launch, then the list's counts (kListHist words) and the list.
+// At one pixel a thread the kernel is held to 80 registers (six waves per SIMD,
+// as many as the backward's LDS allows).
 template <int PPT, bool CULL>
-__global__ __launch_bounds__(256) void render_fused_kernel(RenderArgs a, ViewTable vt, float* __restrict__ image,
-                                                           float* __restrict__ T_final, int32_t* __restrict__ last,
-                                                           LossIn loss, float* __restrict__ grad_pair,
-                                                           uint32_t* __restrict__ sync) {
+__global__ __launch_bounds__(256, PPT == 1 ? 6 : 1) void render_fused_kernel(RenderArgs a, ViewTable vt,
+                                                                             float* __restrict__ image,
+                                                                             float* __restrict__ T_final,
+                                                                             int32_t* __restrict__ last, LossIn loss,
+                                                                             float* __restrict__ grad_pair,
+                                                                             uint32_t* __restrict__ sync) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ uint32_t s_ticket;
-  __shared__ int s_ok;
+  __shared__ uint32_t s_flag;
+  __shared__ int s_wmax[4];
   const int64_t ntiles = vt.total_tiles;
   if (threadIdx.x == 0) s_ticket = atomicAdd(sync + ntiles, 1u);
   __syncthreads();
   const int64_t q = s_ticket;
   if (q < ntiles) {
-    fwd_item<PPT, CULL, kFull, true>(a, vt, image, T_final, last, q, (float4(*)[3][kWave])smem,
-                                     (uint32_t(*)[kWave])(smem + sizeof(float4) * 4 * 3 * kWave));
+    // forward walks issue ahead of the backward waves that share their SIMD:
+    // the deepest lists' forward walks are the launch's critical path
+    __builtin_amdgcn_s_setprio(3);
+    int my_max = fwd_item<PPT, CULL, kFull, true>(a, vt, image, T_final, last, q, (float4(*)[3][kWave])smem,
+                                                  (uint32_t(*)[kWave])(smem + sizeof(float4) * 4 * 3 * kWave));
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) my_max = max(my_max, __shfl_xor(my_max, o, kWave));
+    if ((threadIdx.x & (kWave - 1)) == 0) s_wmax[threadIdx.x / kWave] = my_max;
     // every thread's coherent stores of image, T_final, last_contrib and
     // states have been acknowledged before the flag is set
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
+      int m = 0;
+      for (int w = 0; w < (int)blockDim.x / kWave; ++w) m = max(m, s_wmax[w]);
       const int gtile = a.order ? (int)a.order[q] : (int)q;
-      __hip_atomic_store(sync + gtile, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      // the flag: 1 + the largest last_contrib of the tile
+      __hip_atomic_store(sync + gtile, (uint32_t)m + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     return;
   }
-  // render_bwd_kernel's item numbering: [0, nslots) boundary chunks, then first chunks by schedule position
+  const uint32_t* hist = sync + ntiles + 1;
   const int64_t qb = q - ntiles;
-  const int64_t item = qb < ntiles ? a.nslots + (ntiles - 1 - qb) : qb - ntiles;
+  if (qb >= (int64_t)hist[128]) return;  // past the list (the grid is sized for the most items)
+  const int64_t item = hist[kListHist + qb];
+  RenderArgs ab = a;
+  ab.order = nullptr;  // first chunks are numbered by tile
   if (threadIdx.x == 0) {
     int gtile = -1;
     if (item < a.nslots) {
       const uint32_t owner = a.slot_owner[item];
       if (owner < (uint32_t)ntiles) gtile = (int)owner;
     } else {
-      const int64_t b = item - a.nslots;
-      gtile = a.order ? (int)a.order[b] : (int)b;
+      gtile = (int)(item - a.nslots);
     }
-    s_ok = gtile < 0 || wait_flag(sync + gtile);
+    s_flag = gtile < 0 ? 1u : wait_flag(sync + gtile);
   }
   __syncthreads();  // the tile's values are then read with coherent loads
-  LossIn l = loss;
-  if (!s_ok) {  // never seen the forward finish: poison this item's gradients
-    const float nan = __builtin_nanf("");
-    for (int v = 0; v < GS_MAX_VIEWS; ++v) l.scale[v] = nan;
-  }
-  bwd_item<PPT, CULL, true>(a, vt, T_final, last, l, grad_pair, item, smem);
+  // a flag never seen set: the item's loss gradient, hence its gradients, are NaN
+  const uint32_t f = s_flag;
+  bwd_item<PPT, CULL, true>(ab, vt, T_final, last, loss, grad_pair, item, smem, f != 0u, f != 0u ? (int)(f - 1u) : -1);
 }
 
 static int tile_threads(const RenderArgs& a) { return (1 << (a.log2_tw + a.log2_th)) / a.ppt; }
@@ -1143,7 +1256,7 @@ static void fused_ppt(const RenderArgs& a, const ViewTable& vt, float* image, fl
   const size_t bwd_sh = lds_bytes(bwd_batch(a.batch, nt / kWave), nt / kWave, true);
   const size_t fwd_sh = sizeof(float4) * 4 * 3 * kWave + sizeof(uint32_t) * 4 * kWave;
   const size_t sh = bwd_sh > fwd_sh ? bwd_sh : fwd_sh;
-  // forward items, then backward chunk items, then backward first chunks
+  // forward items, then at most one backward item per tile and one per boundary slot
   const dim3 grid((unsigned)(2 * vt.total_tiles + a.nslots)), block((unsigned)nt);
   if (a.cull)
     hipLaunchKernelGGL((render_fused_kernel<PPT, true>), grid, block, sh, s, a, vt, image, T_final, last, loss,
@@ -1165,10 +1278,14 @@ hipError_t launch_render_fused(const RenderArgs& a, const ViewTable& vt, float* 
   loss.dL_out = dL_out;
   for (int v = 0; v < GS_MAX_VIEWS; ++v) loss.scale[v] = v < vt.nviews ? scale[v] : 0.0f;
   hipError_t e = launch_fill_u32(a.slot_owner, a.nslots, 0xffffffffu, s);
-  if (e == hipSuccess) e = launch_fill_u32(sync, vt.total_tiles + 1, 0u, s);  // flags and ticket
+  if (e == hipSuccess) e = launch_fill_u32(sync, vt.total_tiles + 1 + 64, 0u, s);  // flags, ticket, list counts
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(bwd_mark_kernel, dim3((unsigned)((vt.total_tiles + 255) / 256)), dim3(256), 0, s, a,
-                     vt.total_tiles);
+  uint32_t* hist = sync + vt.total_tiles + 1;
+  const dim3 tgrid((unsigned)((vt.total_tiles + 255) / 256));
+  hipLaunchKernelGGL(list_count_kernel, tgrid, dim3(256), 0, s, a, (int64_t)vt.total_tiles, hist);
+  hipLaunchKernelGGL(list_scan_kernel, dim3(1), dim3(64), 0, s, hist);
+  hipLaunchKernelGGL(list_scatter_kernel, tgrid, dim3(256), 0, s, a, (int64_t)vt.total_tiles, hist,
+                     hist + kListHist);
   switch (a.ppt) {
     case 1: fused_ppt<1>(a, vt, image, T_final, last_contrib, loss, grad_pair, sync, s); break;
     case 2: fused_ppt<2>(a, vt, image, T_final, last_contrib, loss, grad_pair, sync, s); break;
