@@ -310,6 +310,7 @@ __device__ __forceinline__ float reduce_scatter9(const float (&x)[GS_GRAD_FLOATS
 // fwd_combine_kernel adds them up.  The critical path of a deep tile becomes
 // about three chunks instead of its whole list.
 enum : int { kFull = 0, kCount = 1, kTPass = 2 };
+constexpr int kHalves = 2;  // entries a lane stages per forward group
 // records evaluated together by the forward walk: four independent chains a
 // lane (PPT pixels per record)
 template <int PPT>
@@ -353,7 +354,7 @@ __device__ __forceinline__ float4 get4(const float4* p) {
 template <int PPT, bool CULL, int MODE, bool COH = false>
 __device__ __forceinline__ int fwd_item(const RenderArgs& a, const ViewTable& vt, float* __restrict__ image,
                                          float* __restrict__ T_final, int32_t* __restrict__ last_out, int64_t item,
-                                         float4 (*s_rec)[3][kWave], uint32_t (*s_cnt)[kWave]) {
+                                         float4 (*s_rec)[3][kHalves * kWave], uint32_t (*s_cnt)[kHalves * kWave]) {
   constexpr bool COUNT = MODE == kCount, TPASS = MODE == kTPass;
   const int lf = COUNT ? 31 : a.log2_fchunk;
   const int64_t nfs = COUNT ? 0 : a.nfslots;
@@ -385,7 +386,10 @@ __device__ __forceinline__ int fwd_item(const RenderArgs& a, const ViewTable& vt
   float4* s_b = s_rec[wave][1];
   float4* s_c = s_rec[wave][2];
   uint32_t* s_hits = s_cnt[wave];  // COUNT only
-  if (COUNT) s_hits[lane] = 0u;
+  if (COUNT) {
+#pragma unroll
+    for (int h = 0; h < kHalves; ++h) s_hits[h * kWave + lane] = 0u;
+  }
 
   // C: colour composited so far (the image, summed in list order whatever
   // the tiling); S: colour composited since the last chunk boundary (kept
@@ -435,14 +439,18 @@ __device__ __forceinline__ int fwd_item(const RenderArgs& a, const ViewTable& vt
   uint64_t b0 = (uint64_t)tc.start + ((((uint64_t)cs - tc.start) + ((1ull << lc) - 1)) >> lc << lc);
   if (b0 == (uint64_t)tc.start) b0 += 1ull << lc;
   // Each wave walks its own sub-tile independently (no workgroup barrier), in
-  // groups of up to 64 entries (batch_depth if smaller) that never straddle a
-  // chunk boundary: lane l stages entry l of the group into the wave's LDS,
-  // with its culling bit for the wave's live box.  Software-pipelined gather,
-  // two groups deep (late in a deep list most records are culled, and a
-  // group's walk is shorter than a gather's latency): while group g is walked,
-  // lane l holds the record of entry l of group g + 1 and has those of group
-  // g + 2 in flight, and the id of entry l of group g + 3.
-  const uint32_t G = (uint32_t)min(kWave, a.batch);
+  // groups of up to kHalves x 64 entries (batch_depth if smaller) that never
+  // straddle a chunk boundary: lane l stages entries l and 64 + l of the group
+  // into the wave's LDS, with their culling bits for the wave's live box.  The
+  // records of group g + 1 are loaded into the registers group g was just
+  // staged from, while group g is walked, and the ids of group g + 2 with them.
+  // Late in a deep list most records are culled and a group's walk is much
+  // shorter than a gather's latency, so a walk that lone waves take (the
+  // deepest lists) is bound by one latency per group: two entries a lane halve
+  // the groups.  (Deeper prefetching across groups is undone by the waits the
+  // compiler puts in front of loop-carried loads.)
+  constexpr uint32_t GH = kWave;                         // entries per half group
+  const uint32_t G = (uint32_t)min(kHalves * kWave, a.batch);
   auto group_end = [&](uint32_t b) -> uint32_t {
     const uint64_t rel = b - tc.start;
     const uint64_t next = (uint64_t)tc.start + (((rel >> lc) + 1) << lc);
@@ -451,23 +459,31 @@ __device__ __forceinline__ int fwd_item(const RenderArgs& a, const ViewTable& vt
   uint32_t gs = cs;                                // group g: [gs, ge)
   uint32_t ge = gs < ce ? group_end(gs) : gs;      // g + 1: [ge, ge2)
   uint32_t ge2 = ge < ce ? group_end(ge) : ge;     // g + 2: [ge2, ge3)
-  uint32_t ge3 = ge2 < ce ? group_end(ge2) : ge2;  // g + 3: [ge3, ge4)
   const float4 zf4 = make_float4(0.f, 0.f, 0.f, 0.f);
-  float4 pa = zf4, pb = zf4, pc = zf4, qa = zf4, qb = zf4, qc = zf4;
-  uint32_t cid = 0, qid = 0, nid = 0;  // ids of entry `lane` of groups g, g + 1, g + 2 (then g + 3)
-  if (gs + lane < ge) {
-    cid = a.ids[gs + lane];
-    pa = a.splats[(size_t)cid * 3 + 0];
-    pb = a.splats[(size_t)cid * 3 + 1];
-    if (!COUNT) pc = a.splats[(size_t)cid * 3 + 2];
+  float4 ra[kHalves], rb[kHalves], rc[kHalves];  // records of entries l, 64 + l of the group staged next
+  uint32_t rid[kHalves], nid[kHalves];           // their ids; the ids of the group after it
+  // every lane loads: a lane past a group's end takes the list's last entry,
+  // which is never staged (a load under a lane condition leaves a merged value
+  // whose register copy waits for the load)
+  const uint32_t elast = tc.end - 1;  // used only when the walk has entries
+#pragma unroll
+  for (int h = 0; h < kHalves; ++h) {
+    ra[h] = rb[h] = rc[h] = zf4;
+    rid[h] = nid[h] = 0;
   }
-  if (ge + lane < ge2) {
-    qid = a.ids[ge + lane];
-    qa = a.splats[(size_t)qid * 3 + 0];
-    qb = a.splats[(size_t)qid * 3 + 1];
-    if (!COUNT) qc = a.splats[(size_t)qid * 3 + 2];
+  if (cs < ce) {
+#pragma unroll
+    for (int h = 0; h < kHalves; ++h) {
+      rid[h] = a.ids[min(gs + h * GH + lane, elast)];
+      nid[h] = a.ids[min(ge + h * GH + lane, elast)];
+    }
+#pragma unroll
+    for (int h = 0; h < kHalves; ++h) {
+      ra[h] = a.splats[(size_t)rid[h] * 3 + 0];
+      rb[h] = a.splats[(size_t)rid[h] * 3 + 1];
+      if (!COUNT) rc[h] = a.splats[(size_t)rid[h] * 3 + 2];
+    }
   }
-  if (ge2 + lane < ge3) nid = a.ids[ge2 + lane];
   while (gs < ce) {
     bool alive = false, live[PPT];
 #pragma unroll
@@ -493,27 +509,38 @@ __device__ __forceinline__ int fwd_item(const RenderArgs& a, const ViewTable& vt
     const int cnt = (int)(ge - gs);
     Box box;
     if (CULL) box = live_box<PPT>(px, py, live);  // all lanes: a cross-lane reduction
-    bool bit = lane < cnt;
-    if (bit) {  // entry `lane` from the registers
-      s_a[lane] = staged_a(pa);
-      s_b[lane] = staged_b(pb);
-      if (!COUNT) s_c[lane] = pc;
-      if (CULL) bit = footprint_mask(pa, pb, 1, &box) != 0u;
+    bool bits[kHalves];
+    uint32_t gid[kHalves];
+#pragma unroll
+    for (int h = 0; h < kHalves; ++h) {
+      const int e = h * (int)GH + lane;
+      bits[h] = e < cnt;
+      if (bits[h]) {  // entry e from the registers
+        s_a[e] = staged_a(ra[h]);
+        s_b[e] = staged_b(rb[h]);
+        if (!COUNT) s_c[e] = rc[h];
+        if (CULL) bits[h] = footprint_mask(ra[h], rb[h], 1, &box) != 0u;
+      }
+      gid[h] = rid[h];
     }
-    const uint32_t gid = cid;
-    // rotate: group g + 1 moves up; issue group g + 2's record loads and
-    // group g + 3's id loads
-    const uint32_t ge4 = ge3 < ce ? group_end(ge3) : ge3;
-    pa = qa, pb = qb, pc = qc, cid = qid;
-    qid = nid;
-    if (ge2 + lane < ge3) {
-      qa = a.splats[(size_t)qid * 3 + 0];
-      qb = a.splats[(size_t)qid * 3 + 1];
-      if (!COUNT) qc = a.splats[(size_t)qid * 3 + 2];
+    // group g + 1's record loads into the registers just staged from, and
+    // group g + 2's id loads
+    const uint32_t ge3 = ge2 < ce ? group_end(ge2) : ge2;
+#pragma unroll
+    for (int h = 0; h < kHalves; ++h) {
+      rid[h] = nid[h];
+      ra[h] = a.splats[(size_t)rid[h] * 3 + 0];
+      rb[h] = a.splats[(size_t)rid[h] * 3 + 1];
+      if (!COUNT) rc[h] = a.splats[(size_t)rid[h] * 3 + 2];
     }
-    nid = ge3 + lane < ge4 ? a.ids[ge3 + lane] : 0u;
+    if (ge < ce) {  // uniform; elast is an entry of the walk here
+#pragma unroll
+      for (int h = 0; h < kHalves; ++h) nid[h] = a.ids[min(ge2 + h * GH + lane, elast)];
+    }
     wave_lds_sync();  // the staged group is visible to the whole wave
-    uint64_t m = __ballot(bit);
+#pragma unroll
+    for (int h = 0; h < kHalves; ++h) {
+    uint64_t m = __ballot(bits[h]);
     if (m != 0) {
       // composite one evaluated record into this lane's pixel(s); branch-free: a
       // lane that skips the splat adds exact zeros
@@ -556,12 +583,13 @@ __device__ __forceinline__ int fwd_item(const RenderArgs& a, const ViewTable& vt
           in[p] = eval_splat_all(px[p], py[p], ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, &e[p]);
       };
       constexpr int R = ilp_records<PPT>();
+      const int hoff = h * (int)GH;  // bit b of m is entry hoff + b
       while (m != 0) {
         if (R == 1 || __popcll(m) >= R) {  // wave-uniform
           int jq[R];
 #pragma unroll
           for (int q = 0; q < R; ++q) {
-            jq[q] = __builtin_ctzll(m);
+            jq[q] = hoff + __builtin_ctzll(m);
             m &= m - 1;
           }
           float4 rcq[R];
@@ -572,7 +600,7 @@ __device__ __forceinline__ int fwd_item(const RenderArgs& a, const ViewTable& vt
 #pragma unroll
           for (int q = 0; q < R; ++q) composite(jq[q], eq[q], iq[q], rcq[q]);
         } else {
-          const int j = __builtin_ctzll(m);
+          const int j = hoff + __builtin_ctzll(m);
           m &= m - 1;
           float4 rc;
           Eval e[PPT];
@@ -582,20 +610,20 @@ __device__ __forceinline__ int fwd_item(const RenderArgs& a, const ViewTable& vt
         }
       }
       if (COUNT) {
-        // flush the group's counters: lane l adds entry l's hits to its Gaussian
+        // flush the half's counters: lane l adds entry hoff + l's hits to its Gaussian
         wave_lds_sync();
-        const uint32_t h = lane < cnt ? s_hits[lane] : 0u;
-        if (h != 0) {
-          atomicAdd(a.hits + ((int64_t)gid - (int64_t)tc.view * a.n), h);
-          s_hits[lane] = 0u;
+        const uint32_t hv = hoff + lane < cnt ? s_hits[hoff + lane] : 0u;
+        if (hv != 0) {
+          atomicAdd(a.hits + ((int64_t)gid[h] - (int64_t)tc.view * a.n), hv);
+          s_hits[hoff + lane] = 0u;
         }
       }
+    }
     }
     wave_lds_sync();  // every lane has read the group before the next one overwrites it
     gs = ge;
     ge = ge2;
     ge2 = ge3;
-    ge3 = ge4;
   }
 
   if (COUNT) return 0;
@@ -676,8 +704,8 @@ __global__ __launch_bounds__(256, PPT == 1 ? 6 : 1) void render_fwd_kernel(Rende
                                                                            float* __restrict__ T_final,
                                                                            int32_t* __restrict__ last_out,
                                                                            int64_t item_base) {
-  __shared__ float4 s_rec[4][3][kWave];
-  __shared__ uint32_t s_cnt[4][kWave];
+  __shared__ float4 s_rec[4][3][kHalves * kWave];
+  __shared__ uint32_t s_cnt[4][kHalves * kWave];
   fwd_item<PPT, CULL, MODE>(a, vt, image, T_final, last_out, (int64_t)blockIdx.x + item_base, s_rec, s_cnt);
 }
 
@@ -1135,8 +1163,9 @@ __global__ __launch_bounds__(256, PPT == 1 ? 6 : 1) void render_fused_kernel(Ren
     // forward walks issue ahead of the backward waves that share their SIMD:
     // the deepest lists' forward walks are the launch's critical path
     __builtin_amdgcn_s_setprio(3);
-    int my_max = fwd_item<PPT, CULL, kFull, true>(a, vt, image, T_final, last, q, (float4(*)[3][kWave])smem,
-                                                  (uint32_t(*)[kWave])(smem + sizeof(float4) * 4 * 3 * kWave));
+    int my_max = fwd_item<PPT, CULL, kFull, true>(
+        a, vt, image, T_final, last, q, (float4(*)[3][kHalves * kWave])smem,
+        (uint32_t(*)[kHalves * kWave])(smem + sizeof(float4) * 4 * 3 * kHalves * kWave));
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) my_max = max(my_max, __shfl_xor(my_max, o, kWave));
     if ((threadIdx.x & (kWave - 1)) == 0) s_wmax[threadIdx.x / kWave] = my_max;
@@ -1254,7 +1283,7 @@ static void fused_ppt(const RenderArgs& a, const ViewTable& vt, float* image, fl
                       const LossIn& loss, float* grad_pair, uint32_t* sync, hipStream_t s) {
   const int nt = tile_threads(a);
   const size_t bwd_sh = lds_bytes(bwd_batch(a.batch, nt / kWave), nt / kWave, true);
-  const size_t fwd_sh = sizeof(float4) * 4 * 3 * kWave + sizeof(uint32_t) * 4 * kWave;
+  const size_t fwd_sh = (sizeof(float4) * 4 * 3 + sizeof(uint32_t) * 4) * kHalves * kWave;
   const size_t sh = bwd_sh > fwd_sh ? bwd_sh : fwd_sh;
   // forward items, then at most one backward item per tile and one per boundary slot
   const dim3 grid((unsigned)(2 * vt.total_tiles + a.nslots)), block((unsigned)nt);
